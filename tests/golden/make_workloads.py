@@ -1,0 +1,188 @@
+"""Write the stored workload geometries ``geom_<name>.json``.
+
+Run from the repository root:  python tests/golden/make_workloads.py [names...]
+
+Everything here that needs the tracking method (where a reference orbit
+appears at each epoch, where an injected source lands in each image, the
+matched filter's sum of squared weights) is computed by ``oracle/`` only;
+random draws come from ``synth``.  No value is taken from the GPU library.
+
+Geometry recipe (a co-moving, "focused" survey, Sec. 4.2): every exposure's
+tangent point follows a reference orbit's apparent direction at its epoch,
+plus a seeded jitter of up to 10% of the field width and, for mosaics, one of
+several fixed field offsets.  The grid field is the tangent plane of the
+middle exposure; candidate orbits are drawn through it by ``synth``.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+OUT = os.path.dirname(os.path.abspath(__file__))
+
+
+def apparent_eq(el, t0, t, robs):
+    rho, tau, helio, st = oracle.light_time(el, t0, t, robs)
+    u = rho / np.linalg.norm(rho)
+    return oracle.ecl_to_eq(u)
+
+
+def sum_p2(fwhm):
+    """Sum of squared filter weights: the oracle's phi on a unit-variance image."""
+    R = 16
+    z = np.zeros((2 * R + 1, 2 * R + 1), np.float32)
+    one = np.ones_like(z)
+    return oracle.stamp(z, one, R, R, fwhm)[1]
+
+
+def make_epochs(rng, n, span, t_start=0.0):
+    """Sorted epochs; the orbit epoch t0 is the middle exposure's epoch."""
+    t = synth.sorted_epochs(rng, n, span, t_start)
+    return t, float(t[n // 2])
+
+
+def make_exposures(rng, t, W, H, arcsec, el_ref, t0, lam_mid, offsets, sigma_rng, fwhm,
+                   jitter=0.1):
+    n = len(t)
+    obs = synth.observer_circular(t, t0, lam_mid)
+    scale = arcsec / 3600.0
+    fw = math.radians(W * scale)
+    fh = math.radians(H * scale)
+    exps = []
+    for k in range(n):
+        u = apparent_eq(el_ref, t0, t[k], obs[k])
+        e1, e2 = synth.tangent_basis(u)
+        ox, oy = offsets[k % len(offsets)]
+        jx, jy = rng.uniform(-jitter, jitter, 2)
+        d = synth.unit(u + (ox + jx) * fw * e1 + (oy + jy) * fh * e2)
+        ra, dec = synth.vec_to_radec(d)
+        s = float(rng.uniform(*sigma_rng)) if sigma_rng[0] != sigma_rng[1] else float(sigma_rng[0])
+        exps.append(dict(t=float(t[k]), obs=[float(v) for v in obs[k]], crval=[float(ra), float(dec)],
+                         crpix=[W / 2.0 + 0.5, H / 2.0 + 0.5], cd=[-scale, 0.0, 0.0, scale],
+                         width=int(W), height=int(H), fwhm=float(fwhm), sigma=s, field=k % len(offsets)))
+    return exps
+
+
+def grid_field(exps, t0, lam_mid, W, H, arcsec):
+    mid = int(np.argmin([abs(x["t"] - t0) for x in exps]))
+    x = exps[mid]
+    c = oracle.eq_to_ecl(synth.radec_to_vec(x["crval"][0], x["crval"][1]))
+    e1, e2 = synth.tangent_basis(c)
+    hw = math.radians(0.5 * W * arcsec / 3600.0)
+    hh = math.radians(0.5 * H * arcsec / 3600.0)
+    obs = synth.observer_circular([t0], t0, lam_mid)[0]
+    return dict(t=t0, obs=[float(v) for v in obs], center=[float(v) for v in c],
+                east=[float(v) for v in e1], north=[float(v) for v in e2], half_w=hw, half_h=hh)
+
+
+def hits_of(el, t0, exps):
+    s = oracle.samples(np.asarray(el)[None, :], t0, exps)
+    ok = (s["flags"][0] & 3) == 3
+    return [[int(e), float(s["px"][0, e]), float(s["py"][0, e])] for e in np.nonzero(ok)[0]]
+
+
+def reference_orbit(seed, t0, lam_mid, a, e, inc_deg, beta_deg):
+    """An orbit at opposition at t0: on the anti-Sun line of sight, latitude beta."""
+    rng = synth.make_rng(seed, 7)
+    b = math.radians(beta_deg)
+    d = np.array([math.cos(b) * math.cos(lam_mid), math.cos(b) * math.sin(lam_mid), math.sin(b)])
+    obs = synth.observer_circular([t0], t0, lam_mid)[0]
+    for _ in range(100):
+        el, ok = synth.orbits_through(rng, d[None, :], obs, a, e, math.radians(inc_deg))
+        if ok[0]:
+            return el[0]
+    raise RuntimeError("no reference orbit")
+
+
+def draw_injections(seed, gf, t0, exps, n, s_rng, a_rng, e_rng, inc_rng, fwhm, min_snr=3.0,
+                    stream=0):
+    rng = synth.make_rng(seed, 55, stream)
+    p2 = sum_p2(fwhm)
+    out = []
+    tries = 0
+    while len(out) < n:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("injection rejection sampling did not finish")
+        el = synth.candidate_orbits(gf, 1, seed, a_rng, e_rng, inc_rng, stream=100000 * stream + tries)[0]
+        s = float(rng.uniform(*s_rng))
+        hits = hits_of(el, t0, exps)
+        if s * math.sqrt(len(hits)) < min_snr:
+            continue
+        out.append(dict(el=[float(v) for v in el], s=s, flux=s / math.sqrt(p2), hits=hits))
+    return out
+
+
+def tiny(seed=1):
+    """20 x 256^2 FP32, sigma 1, 0.2"/px, 30 days, one source s=1.5 on the
+    reference orbit (a 2.7, e 0.1, i 5 deg), 10^4 candidate orbits."""
+    lam = 0.4
+    rng = synth.make_rng(seed, 1)
+    t, t0 = make_epochs(rng, 20, 30.0)
+    el_ref = reference_orbit(seed, t0, lam, 2.7, 0.1, 5.0, 1.0)
+    exps = make_exposures(rng, t, 256, 256, 0.2, el_ref, t0, lam, [(0.0, 0.0)], (1.0, 1.0), 3.0)
+    gf = grid_field(exps, t0, lam, 256, 256, 0.2)
+    p2 = sum_p2(3.0)
+    inj = [dict(el=[float(v) for v in el_ref], s=1.5, flux=1.5 / math.sqrt(p2), hits=hits_of(el_ref, t0, exps))]
+    return dict(name="tiny", seed=seed, t0=t0, dtype="f32", nan_frac=0.0, exposures=exps, grid_field=gf,
+                grid=dict(n=10000, a=[2.0, 3.5], e=[0.0, 0.3], inc_deg=[0.0, 15.0], cloud=0),
+                injections=inj)
+
+
+MOSAIC10 = [((k % 5) - 2) * 0.9 for k in range(10)]
+MOSAIC10 = [(MOSAIC10[k], ((k // 5) - 0.5) * 0.9) for k in range(10)]
+
+
+def survey(seed=2, n_exp=200, side=2048, n_orb=10_000_000, n_inj=20, cloud=1000, name="survey",
+           span=60.0, nan_frac=0.005, offsets=MOSAIC10, width=None):
+    """Survey-scale mosaic: FP32 images plus variance, sigma U(0.8, 1.25),
+    NaN-masked pixels, 0.2"/px, 10 field offsets; injections at per-image
+    S/N U(0.5, 2) conditioned on s sqrt(n_hit) >= 3, each with a cloud of
+    perturbed-a orbits."""
+    lam = 1.1
+    W = side if width is None else width
+    H = side
+    rng = synth.make_rng(seed, 1)
+    t, t0 = make_epochs(rng, n_exp, span)
+    el_ref = reference_orbit(seed, t0, lam, 2.7, 0.1, 5.0, 0.8)
+    exps = make_exposures(rng, t, W, H, 0.2, el_ref, t0, lam, offsets, (0.8, 1.25), 3.0)
+    gf = grid_field(exps, t0, lam, W, H, 0.2)
+    injs = draw_injections(seed, gf, t0, exps, n_inj, (0.5, 2.0), (2.0, 3.5), (0.0, 0.3), (0.0, 15.0), 3.0)
+    return dict(name=name, seed=seed, t0=t0, dtype="f32", nan_frac=nan_frac, exposures=exps, grid_field=gf,
+                grid=dict(n=n_orb, a=[2.0, 3.5], e=[0.0, 0.3], inc_deg=[0.0, 15.0], cloud=cloud,
+                          cloud_da=1.5e-4), injections=injs)
+
+
+def survey_small(seed=3):
+    """Scaled-down survey for full oracle parity: 24 ragged 600x440 images,
+    4 field offsets, 2x10^4 orbits, 3 injections with clouds of 50."""
+    offs = [(-0.45, -0.45), (0.45, -0.45), (-0.45, 0.45), (0.45, 0.45)]
+    return survey(seed=seed, n_exp=24, side=440, width=600, n_orb=20000, n_inj=3, cloud=50,
+                  name="survey_small", span=8.0, offsets=offs)
+
+
+WORKLOADS = {"tiny": tiny, "survey": survey, "survey_small": survey_small}
+
+
+def main(names):
+    for nm in names or list(WORKLOADS):
+        g = WORKLOADS[nm]()
+        path = os.path.join(OUT, f"geom_{nm}.json")
+        with open(path, "w") as f:
+            json.dump(g, f, indent=None, separators=(",", ":"))
+        nh = [len(i["hits"]) for i in g["injections"]]
+        print(f"{nm}: {len(g['exposures'])} exposures, {len(g['injections'])} injections, hits {nh} -> {path}")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
