@@ -1,0 +1,158 @@
+/*
+ * dtrack.h -- C ABI of libdtrack, the MI355X (gfx950) implementation of the
+ * hot path of non-linear digital tracking (Golovich et al. 2025, "Survey-Wide
+ * Asteroid Discovery with a High-Performance Computing Enabled Non-Linear
+ * Digital Tracking Framework").
+ *
+ * The library answers the problem stated by Algorithm 1 and Sec. 3 of the
+ * paper: given images with per-pixel noise variance, their epochs, observer
+ * positions and WCS, and a set of candidate Keplerian orbits, it carries every
+ * orbit to every exposure, maps it to pixels, applies a Gaussian matched filter
+ * where it lands, combines the per-image signals under a constant-flux model
+ * into one S/N per orbit, and selects the significant orbits.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns dt_status; DT_OK == 0.  No C++ exception crosses
+ *     the ABI.  On failure dt_last_error() returns a thread-local message.
+ *   - All arguments are validated before any work is enqueued; on DT_E_ARG or
+ *     DT_E_DOMAIN nothing is written.
+ *   - "device" pointers are HIP device allocations on the context's device;
+ *     "host" pointers are ordinary host memory read during the call only.
+ *   - The caller owns every buffer it passes.  Image buffers are borrowed by a
+ *     patch for its lifetime; the library owns (and frees in *_destroy) the
+ *     matched-filter planes, metadata and scratch it allocates.
+ *   - All GPU work is enqueued on the context's HIP stream; outputs are valid
+ *     after that stream is synchronised.  A context is used by one host thread.
+ *   - Units: days, AU, radians for orbital elements, degrees for WCS.
+ */
+#ifndef DTRACK_H
+#define DTRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DT_OK = 0,
+  DT_E_ARG = -1,     /* null pointer, bad size or shape */
+  DT_E_DOMAIN = -2,  /* value outside the method's domain (e.g. e >= 1, a <= 0, singular CD) */
+  DT_E_OOM = -3,     /* device allocation failed or the context memory limit would be exceeded */
+  DT_E_HIP = -4,     /* a HIP runtime call failed; message has hipGetErrorString */
+  DT_E_STATE = -5    /* object used in the wrong state (e.g. destroyed context) */
+} dt_status;
+
+typedef enum { DT_F32 = 0, DT_F16 = 1 } dt_dtype;
+
+typedef struct dt_ctx dt_ctx;
+typedef struct dt_patch dt_patch;
+
+/* One exposure (host record, copied at patch creation).  Sec. 3: each image
+ * header supplies the epoch, the WCS and the PSF width; the observer position
+ * at the epoch is supplied by the caller (the paper takes it from an
+ * ephemeris).  The WCS is FITS TAN with a CD matrix: pixel (x, y) with
+ * 0-based centres at integers maps to intermediate coordinates
+ * CD * (x + 1 - CRPIX1, y + 1 - CRPIX2) in degrees. */
+typedef struct {
+  double t;               /* mid-exposure epoch (days), same scale as the orbit epoch */
+  double obs_xyz_au[3];   /* heliocentric observer position, ecliptic J2000, AU */
+  double crval_deg[2];    /* TAN tangent point (RA, Dec), equatorial J2000, degrees */
+  double crpix[2];        /* FITS 1-based reference pixel (x, y) */
+  double cd_deg[4];       /* CD1_1, CD1_2, CD2_1, CD2_2 (deg/px); must be invertible */
+  int32_t width, height;  /* pixels; images are row-major [height][width] */
+  float psf_fwhm_px;      /* Gaussian PSF FWHM in pixels, 0.5 <= fwhm <= 8 */
+  float reserved;         /* set to 0 */
+} dt_exposure;
+
+/* A set of candidate orbits in SoA form (device pointers, n doubles each):
+ * osculating heliocentric ecliptic-J2000 elements at the common epoch
+ * `epoch`: semi-major axis a (AU), eccentricity e in [0, 1), inclination,
+ * longitude of the ascending node, argument of perihelion and mean anomaly
+ * (radians).  Sec. 3: two-body elliptical motion about a fixed Sun. */
+typedef struct {
+  int64_t n;
+  double epoch;
+  const double *a, *e, *inc, *node, *peri, *m0;
+} dt_orbits;
+
+/* Thread-local message describing the last failure of this thread ("" if none). */
+const char *dt_last_error(void);
+/* Library version string. */
+const char *dt_version(void);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+dt_status dt_ctx_create(int device, void *hip_stream, dt_ctx **out);
+/* Change the stream later calls enqueue on. */
+dt_status dt_ctx_set_stream(dt_ctx *ctx, void *hip_stream);
+/* Cap the bytes of device memory the context may hold (planes, metadata,
+ * scratch); 0 = no cap.  Later allocations beyond it fail with DT_E_OOM. */
+dt_status dt_ctx_set_mem_limit(dt_ctx *ctx, size_t bytes);
+/* Bytes of device memory currently held by the context. */
+dt_status dt_ctx_mem_used(dt_ctx *ctx, size_t *out);
+/* Destroy the context; its patches must be destroyed first (DT_E_STATE otherwise). */
+dt_status dt_ctx_destroy(dt_ctx *ctx);
+
+/* Build a patch: n_exp exposures (host array `exps`) with their flux and
+ * variance images (host arrays of n_exp device pointers, each a row-major
+ * height x width image of `dtype`).  Enqueues the exposure-metadata kernel
+ * and the matched-filter pre-pass (Sec. 3, FindLocalSignal): for every pixel
+ * the planes psi = sum P D / V and phi = sum P^2 / V over a (2R+1)^2 stamp of
+ * the unit-sum Gaussian P (sigma = FWHM / 2.3548, R = ceil(3 sigma)), pixels
+ * off the image, non-finite or with V <= 0 carrying no weight.  By linearity
+ * this equals the filter applied at the nearest pixel of any intersection.
+ * Image buffers are borrowed until dt_patch_destroy; the planes are owned. */
+dt_status dt_patch_create(dt_ctx *ctx, const dt_exposure *exps, int32_t n_exp,
+                          const void *const *d_flux, const void *const *d_var, dt_dtype dtype,
+                          dt_patch **out);
+/* Re-run the pre-pass after the caller changed the borrowed images in place. */
+dt_status dt_patch_refresh(dt_patch *p);
+dt_status dt_patch_destroy(dt_patch *p);
+/* Copy the (psi, phi) plane of exposure `e` (caller order) into d_out
+ * (device, height*width float2 interleaved {psi, phi}, row-major). */
+dt_status dt_patch_plane(dt_patch *p, int32_t e, float *d_out);
+
+/* The plain stack (Algorithm 1 SearchImages + FilterGPUIntersections +
+ * FindLocalSignal + constant-flux combination, Sec. 3): for every orbit,
+ * over every exposure in epoch order, propagate with light time, project
+ * through the TAN WCS, take the nearest pixel floor(p + 0.5); a sample is
+ * valid if it is in front of the tangent plane, inside the image and the
+ * filter weight phi there is > 0.  Outputs (device, n each):
+ *   d_snr    = Psi / sqrt(Phi), Psi = sum psi, Phi = sum phi over valid samples
+ *   d_flux   = Psi / Phi       (both 0 when Phi == 0)
+ *   d_nvalid = number of valid samples.
+ * Any output pointer may be NULL.  The call does not synchronise: an orbit
+ * outside the domain (non-finite element, a <= 0, e outside [0, 1)) gets
+ * S/N = flux = NaN and nvalid = -1; dt_orbits_validate reports such orbits
+ * as an error before any stacking if the caller wants that. */
+dt_status dt_stack(dt_patch *p, const dt_orbits *orbits, float *d_snr, float *d_flux,
+                   int32_t *d_nvalid);
+
+/* Count the orbits outside the domain (synchronises the context stream).
+ * Returns DT_E_DOMAIN if *n_bad > 0, DT_OK otherwise. */
+dt_status dt_orbits_validate(dt_ctx *ctx, const dt_orbits *orbits, int64_t *n_bad);
+
+/* Detection (Algorithm 1 FindSignificantResults): the k orbits of largest
+ * S/N among those with S/N >= threshold, ordered by S/N descending, ties to
+ * the lower index.  d_snr: device, n floats (NaN never selected).
+ * Outputs (device): d_idx[k] int64, d_val[k] float, d_count[1] = number
+ * written (<= k).  1 <= k <= 4096, n < 2^32. */
+dt_status dt_topk(dt_ctx *ctx, const float *d_snr, int64_t n, int32_t k, float threshold,
+                  int64_t *d_idx, float *d_val, int32_t *d_count);
+
+/* Per-sample table for m selected orbits (device int64 ids into `orbits`),
+ * computed by the same device code and in the same order as dt_stack.
+ * Outputs (device, m x n_exp each, exposures in caller order; any may be NULL):
+ *   px, py  0-based pixel coordinates (FP64), ix, iy nearest pixel,
+ *   flags   bit0 in front, bit1 inside image, bit2 valid (phi > 0),
+ *   psi, phi the gathered plane values (0 when not valid), tau light time (days). */
+dt_status dt_debug_samples(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, int64_t m,
+                           double *d_px, double *d_py, int32_t *d_ix, int32_t *d_iy,
+                           int32_t *d_flags, float *d_psi, float *d_phi, double *d_tau);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DTRACK_H */

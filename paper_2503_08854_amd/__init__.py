@@ -1,0 +1,12 @@
+"""MI355X-native non-linear digital tracking (HIP / gfx950).
+
+Thin Python binding of ``libdtrack.so`` (declared in ``include/dtrack.h``).
+It marshals arguments only: every step of the tracking path runs in the
+library's HIP kernels.  PyTorch supplies device memory and the stream.
+There is no fallback: if the library is missing, importing the binding's
+functions raises.
+"""
+from .binding import (  # noqa: F401
+    DtrackError, Context, Patch, OrbitSet, lib, stack, topk, debug_samples, validate_orbits,
+    exposure_struct, LIB_PATH,
+)

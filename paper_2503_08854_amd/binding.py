@@ -1,0 +1,286 @@
+"""ctypes binding of libdtrack: argument marshalling only.
+
+Torch tensors provide device memory; their ``data_ptr()`` values cross the
+C ABI as plain pointers and the current torch stream is the library's stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdtrack.so")
+
+DT_OK, DT_E_ARG, DT_E_DOMAIN, DT_E_OOM, DT_E_HIP, DT_E_STATE = 0, -1, -2, -3, -4, -5
+DT_F32, DT_F16 = 0, 1
+_NAMES = {DT_E_ARG: "DT_E_ARG", DT_E_DOMAIN: "DT_E_DOMAIN", DT_E_OOM: "DT_E_OOM", DT_E_HIP: "DT_E_HIP",
+          DT_E_STATE: "DT_E_STATE"}
+
+
+class DtrackError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class DtExposure(C.Structure):
+    _fields_ = [("t", C.c_double), ("obs_xyz_au", C.c_double * 3), ("crval_deg", C.c_double * 2),
+                ("crpix", C.c_double * 2), ("cd_deg", C.c_double * 4), ("width", C.c_int32),
+                ("height", C.c_int32), ("psf_fwhm_px", C.c_float), ("reserved", C.c_float)]
+
+
+class DtOrbits(C.Structure):
+    _fields_ = [("n", C.c_int64), ("epoch", C.c_double), ("a", C.c_void_p), ("e", C.c_void_p),
+                ("inc", C.c_void_p), ("node", C.c_void_p), ("peri", C.c_void_p), ("m0", C.c_void_p)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libdtrack.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "dt_last_error": ([], C.c_char_p),
+        "dt_version": ([], C.c_char_p),
+        "dt_ctx_create": ([C.c_int, _P, C.POINTER(_P)], C.c_int),
+        "dt_ctx_set_stream": ([_P, _P], C.c_int),
+        "dt_ctx_set_mem_limit": ([_P, C.c_size_t], C.c_int),
+        "dt_ctx_mem_used": ([_P, C.POINTER(C.c_size_t)], C.c_int),
+        "dt_ctx_destroy": ([_P], C.c_int),
+        "dt_patch_create": ([_P, C.POINTER(DtExposure), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.c_int,
+                             C.POINTER(_P)], C.c_int),
+        "dt_patch_refresh": ([_P], C.c_int),
+        "dt_patch_destroy": ([_P], C.c_int),
+        "dt_patch_plane": ([_P, C.c_int32, _P], C.c_int),
+        "dt_stack": ([_P, C.POINTER(DtOrbits), _P, _P, _P], C.c_int),
+        "dt_orbits_validate": ([_P, C.POINTER(DtOrbits), C.POINTER(C.c_int64)], C.c_int),
+        "dt_topk": ([_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P, _P], C.c_int),
+        "dt_debug_samples": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != DT_OK:
+        raise DtrackError(st, lib().dt_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def exposure_struct(exps):
+    """List of exposure dicts (t, obs, crval, crpix, cd, width, height, fwhm) -> dt_exposure array."""
+    arr = (DtExposure * len(exps))()
+    for k, x in enumerate(exps):
+        r = arr[k]
+        r.t = float(x["t"])
+        r.obs_xyz_au[:] = [float(v) for v in x["obs"]]
+        r.crval_deg[:] = [float(v) for v in x["crval"]]
+        r.crpix[:] = [float(v) for v in x["crpix"]]
+        r.cd_deg[:] = [float(v) for v in x["cd"]]
+        r.width = int(x["width"])
+        r.height = int(x["height"])
+        r.psf_fwhm_px = float(x["fwhm"])
+        r.reserved = 0.0
+    return arr
+
+
+class Context:
+    """A dt_ctx bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        self._h = _P()
+        with torch.cuda.device(device):
+            s = C.c_void_p(stream.cuda_stream) if stream is not None else _stream_handle()
+            _check(lib().dt_ctx_create(device, s, C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream):
+        _check(lib().dt_ctx_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def set_mem_limit(self, nbytes: int):
+        _check(lib().dt_ctx_set_mem_limit(self._h, int(nbytes)))
+
+    def mem_used(self) -> int:
+        v = C.c_size_t()
+        _check(lib().dt_ctx_mem_used(self._h, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if self._h:
+            _check(lib().dt_ctx_destroy(self._h))
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().dt_ctx_destroy(self._h)
+        except Exception:
+            pass
+
+
+class Patch:
+    """Exposures + borrowed device images; owns the matched-filter planes."""
+
+    def __init__(self, ctx: Context, exps, flux, var):
+        import torch
+        if len(exps) != len(flux) or len(exps) != len(var):
+            raise ValueError("exposures, flux and variance lists differ in length")
+        dt = flux[0].dtype
+        if dt not in (torch.float32, torch.float16):
+            raise TypeError("images must be float32 or float16")
+        for x, d, v in zip(exps, flux, var):
+            if d.dtype != dt or v.dtype != dt or not d.is_cuda or not v.is_cuda:
+                raise TypeError("all images must be CUDA tensors of one dtype")
+            if tuple(d.shape) != (int(x["height"]), int(x["width"])) or d.shape != v.shape:
+                raise ValueError("image shape does not match its exposure")
+            if not d.is_contiguous() or not v.is_contiguous():
+                raise ValueError("images must be contiguous")
+        self.ctx = ctx
+        self.exps = list(exps)
+        self._flux = list(flux)   # borrowed: keep alive
+        self._var = list(var)
+        n = len(exps)
+        xs = exposure_struct(exps)
+        fp = (_P * n)(*[d.data_ptr() for d in flux])
+        vp = (_P * n)(*[v.data_ptr() for v in var])
+        self._h = _P()
+        _check(lib().dt_patch_create(ctx.handle, xs, n, fp, vp, DT_F32 if dt == torch.float32 else DT_F16,
+                                     C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_exp(self):
+        return len(self.exps)
+
+    def refresh(self):
+        _check(lib().dt_patch_refresh(self._h))
+
+    def plane(self, e: int):
+        import torch
+        x = self.exps[e]
+        out = torch.empty((int(x["height"]), int(x["width"]), 2), dtype=torch.float32,
+                          device=self._flux[0].device)
+        _check(lib().dt_patch_plane(self._h, int(e), _ptr(out)))
+        return out
+
+    def close(self):
+        if self._h:
+            _check(lib().dt_patch_destroy(self._h))
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().dt_patch_destroy(self._h)
+        except Exception:
+            pass
+
+
+class OrbitSet:
+    """SoA FP64 element arrays on the device (a, e, i, node, peri, M0) + epoch."""
+
+    def __init__(self, elements, epoch: float, device="cuda"):
+        import torch
+        el = elements
+        if isinstance(el, np.ndarray):
+            el = torch.from_numpy(np.ascontiguousarray(el, dtype=np.float64))
+        el = el.to(device=device, dtype=torch.float64)
+        if el.dim() != 2 or el.shape[1] != 6:
+            raise ValueError("elements must be (n, 6)")
+        self.soa = el.t().contiguous()      # (6, n)
+        self.n = int(el.shape[0])
+        self.epoch = float(epoch)
+
+    def struct(self):
+        s = DtOrbits()
+        s.n = self.n
+        s.epoch = self.epoch
+        base = self.soa.data_ptr()
+        stride = self.n * 8
+        for k, name in enumerate(("a", "e", "inc", "node", "peri", "m0")):
+            setattr(s, name, base + k * stride if self.n else None)
+        return s
+
+
+def stack(patch: Patch, orbits: OrbitSet, out=None):
+    """S/N, flux, n_valid per orbit (float32, float32, int32 device tensors)."""
+    import torch
+    dev = orbits.soa.device
+    if out is None:
+        out = (torch.empty(orbits.n, dtype=torch.float32, device=dev),
+               torch.empty(orbits.n, dtype=torch.float32, device=dev),
+               torch.empty(orbits.n, dtype=torch.int32, device=dev))
+    snr, flux, nv = out
+    s = orbits.struct()
+    _check(lib().dt_stack(patch.handle, C.byref(s), _ptr(snr), _ptr(flux), _ptr(nv)))
+    return snr, flux, nv
+
+
+def validate_orbits(ctx: Context, orbits: OrbitSet) -> int:
+    n_bad = C.c_int64()
+    st = lib().dt_orbits_validate(ctx.handle, C.byref(orbits.struct()), C.byref(n_bad))
+    if st not in (DT_OK, DT_E_DOMAIN):
+        _check(st)
+    return n_bad.value
+
+
+def topk(ctx: Context, snr, k: int, threshold: float = float("-inf")):
+    """(idx int64[k], val float32[k], count int32[1]) device tensors."""
+    import torch
+    dev = snr.device
+    idx = torch.empty(k, dtype=torch.int64, device=dev)
+    val = torch.empty(k, dtype=torch.float32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().dt_topk(ctx.handle, _ptr(snr), int(snr.numel()), int(k), float(threshold), _ptr(idx), _ptr(val),
+                         _ptr(cnt)))
+    return idx, val, cnt
+
+
+def debug_samples(patch: Patch, orbits: OrbitSet, ids):
+    """Per-sample table (m x n_exp, caller exposure order) computed by the stack's device code."""
+    import torch
+    dev = orbits.soa.device
+    ids = torch.as_tensor(ids, dtype=torch.int64).to(dev)
+    m, n = int(ids.numel()), patch.n_exp
+    o = dict(px=torch.empty((m, n), dtype=torch.float64, device=dev),
+             py=torch.empty((m, n), dtype=torch.float64, device=dev),
+             ix=torch.empty((m, n), dtype=torch.int32, device=dev),
+             iy=torch.empty((m, n), dtype=torch.int32, device=dev),
+             flags=torch.empty((m, n), dtype=torch.int32, device=dev),
+             psi=torch.empty((m, n), dtype=torch.float32, device=dev),
+             phi=torch.empty((m, n), dtype=torch.float32, device=dev),
+             tau=torch.empty((m, n), dtype=torch.float64, device=dev))
+    s = orbits.struct()
+    _check(lib().dt_debug_samples(patch.handle, C.byref(s), _ptr(ids), m, _ptr(o["px"]), _ptr(o["py"]),
+                                  _ptr(o["ix"]), _ptr(o["iy"]), _ptr(o["flags"]), _ptr(o["psi"]), _ptr(o["phi"]),
+                                  _ptr(o["tau"])))
+    return o

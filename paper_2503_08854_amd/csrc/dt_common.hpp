@@ -1,0 +1,93 @@
+// dt_common.hpp -- structures and helpers shared by the host API and the HIP
+// kernels of libdtrack (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dtrack.h"
+
+namespace dtk {
+
+// Gaussian gravitational constant k (AU^1.5/day); GM_sun = k^2 (Sec. 3:
+// two-body motion about the Sun, the asteroid's mass neglected).
+constexpr double K_GAUSS = 0.01720209895;
+constexpr double MU_SUN = K_GAUSS * K_GAUSS;
+// Speed of light in AU/day from the SI metre, second and the IAU astronomical unit.
+constexpr double C_AU_DAY = 299792458.0 * 86400.0 / 149597870700.0;
+// Mean obliquity of the ecliptic at J2000 (IAU 2006), arcseconds.
+constexpr double OBLIQUITY_ARCSEC = 84381.448;
+constexpr double PI = 3.14159265358979323846;
+
+// Per-exposure constants, prepared on the device from a dt_exposure.
+// Everything is expressed in the heliocentric ecliptic frame so no rotation
+// is needed per sample: the TAN basis is rotated once per exposure instead.
+struct alignas(16) ExpMeta {
+  double t;                 // epoch (days)
+  double ox, oy, oz;        // observer (AU, ecliptic)
+  double cx, cy, cz;        // tangent-point direction (ecliptic)
+  double a0x, a0y, a0z;     // row 0 of (180/pi) CD^-1 [east; north] (px per unit, ecliptic)
+  double a1x, a1y, a1z;     // row 1
+  double px0, py0;          // CRPIX - 1
+  int64_t plane_off;        // offset of this exposure's plane (in float2 units)
+  int32_t W, H;             // image size
+  int32_t src;              // caller's index of this exposure
+  float fwhm;               // PSF FWHM (px)
+  int32_t R;                // stamp half-width ceil(3 sigma)
+  int32_t pad;
+};
+static_assert(sizeof(ExpMeta) == 160, "ExpMeta layout");
+
+// One tile of the matched-filter pre-pass.
+struct PrepTile {
+  int32_t e;       // exposure (sorted index)
+  int32_t x0, y0;  // tile origin
+  int32_t pad;
+};
+
+constexpr int PREP_TX = 64;   // tile width  (output pixels)
+constexpr int PREP_TY = 32;   // tile height (output pixels)
+constexpr int PREP_RMAX = 12; // largest stamp half-width supported (FWHM <= 8 px gives R = 11)
+
+// Launchers (defined in the .hip files; all enqueue on `s`).
+hipError_t launch_exposure_prep(const dt_exposure* d_in, const int64_t* d_plane_off, const int32_t* d_src,
+                                const int32_t* d_R, int n, ExpMeta* d_out, hipStream_t s);
+hipError_t launch_prepass(const ExpMeta* d_meta, const PrepTile* d_tiles, int64_t n_tiles,
+                          const void* const* d_flux, const void* const* d_var, dt_dtype dtype,
+                          float2* d_planes, int rmax, hipStream_t s);
+
+// Stamp half-width for a PSF FWHM: R = ceil(3 sigma), sigma = FWHM / (2 sqrt(2 ln 2)).
+inline int stamp_radius(double fwhm) {
+  double sig = fwhm / (2.0 * __builtin_sqrt(2.0 * __builtin_log(2.0)));
+  return (int)__builtin_ceil(3.0 * sig);
+}
+
+struct StackArgs {
+  const ExpMeta* meta;
+  int32_t n_exp;
+  const float2* planes;
+  int64_t n;
+  double epoch;
+  const double *a, *e, *inc, *node, *peri, *m0;
+  float* snr;
+  float* flux;
+  int32_t* nvalid;
+};
+
+struct DebugArgs {
+  const int64_t* ids;
+  int64_t m;
+  double *px, *py, *tau;
+  int32_t *ix, *iy, *flags;
+  float *psi, *phi;
+};
+
+hipError_t launch_stack(const StackArgs& a, hipStream_t s);
+hipError_t launch_debug(const StackArgs& a, const DebugArgs& d, hipStream_t s);
+hipError_t launch_validate(const StackArgs& a, unsigned long long* d_bad, hipStream_t s);
+
+// Top-k scratch requirement (bytes) for n inputs and k outputs.
+size_t topk_scratch_bytes(int64_t n, int32_t k);
+hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,
+                       int32_t* d_count, void* d_scratch, hipStream_t s);
+
+}  // namespace dtk

@@ -1,0 +1,127 @@
+// k_topk.hip -- detection: threshold + top-k of the per-orbit S/N
+// (Algorithm 1, FindSignificantResults).
+//
+// Each orbit becomes one 64-bit key: the order-preserving bits of its S/N in
+// the high word and (2^32 - 1 - index) in the low word, so sorting keys in
+// descending order sorts by S/N descending with ties to the lower index, and
+// every key is distinct.  Orbits below the threshold (or NaN) get key 0.
+// A tournament of LDS bitonic sorts keeps the best k of every TOPK_T-key tile
+// until a single tile remains.
+#include "dt_common.hpp"
+
+namespace dtk {
+
+constexpr int TOPK_T = 8192;       // keys per tile
+constexpr int TOPK_THREADS = 512;  // 16 keys per thread
+
+__device__ __forceinline__ uint64_t make_key(float f, uint64_t i) {
+  uint32_t u = __float_as_uint(f);
+  uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)ord << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
+}
+
+__device__ __forceinline__ float key_val(uint64_t k) {
+  uint32_t ord = (uint32_t)(k >> 32);
+  uint32_t u = (ord & 0x80000000u) ? (ord & 0x7FFFFFFFu) : ~ord;
+  return __uint_as_float(u);
+}
+
+__device__ __forceinline__ int64_t key_idx(uint64_t k) { return (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFu)); }
+
+// Sort TOPK_T keys in LDS, descending.
+__device__ __forceinline__ void bitonic_desc(uint64_t* s) {
+  const int tid = threadIdx.x;
+  for (int k = 2; k <= TOPK_T; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int p = tid; p < TOPK_T / 2; p += TOPK_THREADS) {
+        int lo = 2 * j * (p / j) + (p % j);
+        int hi = lo + j;
+        uint64_t a = s[lo], b = s[hi];
+        bool desc = (lo & k) == 0;
+        if (desc ? (a < b) : (a > b)) {
+          s[lo] = b;
+          s[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One tournament round.  Input either S/N values (snr != null, key built from
+// value and index) or keys from the previous round.
+__global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __restrict__ snr,
+                                                             const uint64_t* __restrict__ keys_in, int64_t n_in,
+                                                             float thr, int kk, uint64_t* __restrict__ keys_out) {
+  __shared__ uint64_t s[TOPK_T];
+  const int64_t base = (int64_t)blockIdx.x * TOPK_T;
+  for (int j = threadIdx.x; j < TOPK_T; j += TOPK_THREADS) {
+    int64_t i = base + j;
+    uint64_t key = 0;
+    if (i < n_in) {
+      if (snr) {
+        float f = snr[i];
+        if (f >= thr) key = make_key(f, (uint64_t)i);  // false for NaN
+      } else {
+        key = keys_in[i];
+      }
+    }
+    s[j] = key;
+  }
+  __syncthreads();
+  bitonic_desc(s);
+  for (int j = threadIdx.x; j < kk; j += TOPK_THREADS) keys_out[(int64_t)blockIdx.x * kk + j] = s[j];
+}
+
+__global__ void k_topk_emit(const uint64_t* __restrict__ keys, int k, int64_t* __restrict__ idx,
+                            float* __restrict__ val, int32_t* __restrict__ count) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int local = 0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    uint64_t key = keys[j];
+    if (key != 0) {
+      idx[j] = key_idx(key);
+      val[j] = key_val(key);
+      local++;
+    } else {
+      idx[j] = -1;
+      val[j] = __builtin_nanf("");
+    }
+  }
+  atomicAdd(&cnt, local);
+  __syncthreads();
+  if (threadIdx.x == 0) *count = cnt;
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t topk_scratch_bytes(int64_t n, int32_t k) {
+  int64_t tiles = ceil_div(n > 0 ? n : 1, TOPK_T);
+  int64_t kk = k < TOPK_T ? k : TOPK_T;
+  return (size_t)(2 * tiles * kk + TOPK_T) * sizeof(uint64_t);
+}
+
+hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,
+                       int32_t* d_count, void* d_scratch, hipStream_t s) {
+  if (k < 1 || k > TOPK_T / 2) return hipErrorInvalidValue;
+  int64_t tiles = ceil_div(n > 0 ? n : 1, TOPK_T);
+  uint64_t* buf[2] = {static_cast<uint64_t*>(d_scratch), static_cast<uint64_t*>(d_scratch) + tiles * k};
+  int cur = 0;
+  int64_t n_in = n > 0 ? n : 0;
+  hipLaunchKernelGGL(k_topk_round, dim3((unsigned)tiles), dim3(TOPK_THREADS), 0, s, d_snr, nullptr, n_in, thr, k,
+                     buf[cur]);
+  n_in = tiles * k;
+  while (tiles > 1) {
+    tiles = ceil_div(n_in, TOPK_T);
+    hipLaunchKernelGGL(k_topk_round, dim3((unsigned)tiles), dim3(TOPK_THREADS), 0, s, nullptr, buf[cur], n_in,
+                       thr, k, buf[cur ^ 1]);
+    cur ^= 1;
+    n_in = tiles * k;
+  }
+  hipLaunchKernelGGL(k_topk_emit, dim3(1), dim3(256), 0, s, buf[cur], k, d_idx, d_val, d_count);
+  return hipGetLastError();
+}
+
+}  // namespace dtk
