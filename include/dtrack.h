@@ -142,6 +142,54 @@ dt_status dt_orbits_validate(dt_ctx *ctx, const dt_orbits *orbits, int64_t *n_ba
 dt_status dt_topk(dt_ctx *ctx, const float *d_snr, int64_t n, int32_t k, float threshold,
                   int64_t *d_idx, float *d_val, int32_t *d_count);
 
+/* Launch shape of the batched stack: orbits per work item (multiple of 256
+ * in [256, 65536]) and persistent workgroups per compute unit ([1, 16]). */
+typedef struct {
+  int32_t chunk;
+  int32_t wg_per_cu;
+} dt_batch_config;
+
+enum {
+  DT_BATCH_PREPASS = 1, /* run every patch's matched-filter pre-pass first */
+  DT_BATCH_EAGER = 2    /* launch directly instead of capturing / replaying a graph */
+};
+
+/* Many patches, each with its own exposures and orbit set, stacked by one
+ * persistent launch (the same per-orbit computation as dt_stack, Sec. 3):
+ * every patch's orbits are cut into work items of cfg->chunk orbits, ordered
+ * largest first (exposures x orbits) and pulled from a device counter by a
+ * grid of cfg->wg_per_cu workgroups per CU.  Then, if k > 0, the top-k of
+ * every patch (as dt_topk) is written to d_topk_idx / d_topk_val
+ * [n_patches * k] and d_topk_count [n_patches] (device).  patches, sets and
+ * the output arrays are host arrays of n_patches entries; d_snr / d_flux /
+ * d_nvalid entries are device pointers (n floats / ints each; NULL allowed
+ * unless k > 0 needs the S/N).  cfg NULL = {1024, 4}.
+ * Unless DT_BATCH_EAGER, the sequence is captured once into a HIP graph kept
+ * by the context and replayed by later calls with identical arguments
+ * (patches, orbit pointers and sizes, outputs, k, threshold, cfg, flags);
+ * any change re-captures.  The graph is dropped when a patch it uses is
+ * destroyed or releases its images, and with the context. */
+dt_status dt_stack_batched(dt_ctx *ctx, dt_patch *const *patches, const dt_orbits *sets, int32_t n_patches,
+                           float *const *d_snr, float *const *d_flux, int32_t *const *d_nvalid,
+                           int32_t k, float threshold, int64_t *d_topk_idx, float *d_topk_val,
+                           int32_t *d_topk_count, const dt_batch_config *cfg, uint32_t flags);
+
+/* Pick the batched launch shape by timing candidate shapes on these very
+ * inputs (chunk in {256..4096}, wg_per_cu in {2, 4, 8}); writes the outputs
+ * as a side effect.  With cache_path (a text file, one "shape-class chunk
+ * wg_per_cu ms" line per entry) a cached entry for the inputs' shape class
+ * (patch count and log2 of total samples, largest orbit set and largest
+ * exposure count) is returned without timing (*best_ms = -1), and a new
+ * result is appended.  best_ms may be NULL. */
+dt_status dt_autotune_batched(dt_ctx *ctx, dt_patch *const *patches, const dt_orbits *sets, int32_t n_patches,
+                              float *const *d_snr, float *const *d_flux, int32_t *const *d_nvalid,
+                              const char *cache_path, dt_batch_config *best, double *best_ms);
+
+/* Forget the patch's image buffers (the planes stay): the caller may free
+ * the images afterwards; dt_patch_refresh and DT_BATCH_PREPASS then fail
+ * with DT_E_STATE. */
+dt_status dt_patch_release_images(dt_patch *p);
+
 /* Per-sample table for m selected orbits (device int64 ids into `orbits`),
  * computed by the same device code and in the same order as dt_stack.
  * Outputs (device, m x n_exp each, exposures in caller order; any may be NULL):

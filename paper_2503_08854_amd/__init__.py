@@ -8,5 +8,5 @@ functions raises.
 """
 from .binding import (  # noqa: F401
     DtrackError, Context, Patch, OrbitSet, lib, stack, topk, debug_samples, validate_orbits,
-    exposure_struct, LIB_PATH,
+    exposure_struct, LIB_PATH, stack_batched, autotune_batched, batch_outputs,
 )

@@ -36,6 +36,12 @@ class DtOrbits(C.Structure):
                 ("inc", C.c_void_p), ("node", C.c_void_p), ("peri", C.c_void_p), ("m0", C.c_void_p)]
 
 
+class DtBatchConfig(C.Structure):
+    _fields_ = [("chunk", C.c_int32), ("wg_per_cu", C.c_int32)]
+
+
+DT_BATCH_PREPASS, DT_BATCH_EAGER = 1, 2
+
 _lib = None
 _P = C.c_void_p
 
@@ -65,6 +71,13 @@ def lib():
         "dt_orbits_validate": ([_P, C.POINTER(DtOrbits), C.POINTER(C.c_int64)], C.c_int),
         "dt_topk": ([_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P, _P], C.c_int),
         "dt_debug_samples": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P], C.c_int),
+        "dt_stack_batched": ([_P, C.POINTER(_P), C.POINTER(DtOrbits), C.c_int32, C.POINTER(_P), C.POINTER(_P),
+                              C.POINTER(_P), C.c_int32, C.c_float, _P, _P, _P, C.POINTER(DtBatchConfig),
+                              C.c_uint32], C.c_int),
+        "dt_autotune_batched": ([_P, C.POINTER(_P), C.POINTER(DtOrbits), C.c_int32, C.POINTER(_P),
+                                 C.POINTER(_P), C.POINTER(_P), C.c_char_p, C.POINTER(DtBatchConfig),
+                                 C.POINTER(C.c_double)], C.c_int),
+        "dt_patch_release_images": ([_P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -163,6 +176,7 @@ class Patch:
                 raise ValueError("images must be contiguous")
         self.ctx = ctx
         self.exps = list(exps)
+        self.device = flux[0].device
         self._flux = list(flux)   # borrowed: keep alive
         self._var = list(var)
         n = len(exps)
@@ -187,10 +201,14 @@ class Patch:
     def plane(self, e: int):
         import torch
         x = self.exps[e]
-        out = torch.empty((int(x["height"]), int(x["width"]), 2), dtype=torch.float32,
-                          device=self._flux[0].device)
+        out = torch.empty((int(x["height"]), int(x["width"]), 2), dtype=torch.float32, device=self.device)
         _check(lib().dt_patch_plane(self._h, int(e), _ptr(out)))
         return out
+
+    def release_images(self):
+        """Drop the borrowed images (the planes stay); refresh is no longer possible."""
+        _check(lib().dt_patch_release_images(self._h))
+        self._flux = self._var = None
 
     def close(self):
         if self._h:
@@ -284,3 +302,56 @@ def debug_samples(patch: Patch, orbits: OrbitSet, ids):
                                   _ptr(o["ix"]), _ptr(o["iy"]), _ptr(o["flags"]), _ptr(o["psi"]), _ptr(o["phi"]),
                                   _ptr(o["tau"])))
     return o
+
+
+def _batch_arrays(patches, orbit_sets, outs):
+    n = len(patches)
+    ph = (_P * n)(*[p.handle.value for p in patches])
+    sets = (DtOrbits * n)(*[o.struct() for o in orbit_sets])
+    snr = (_P * n)(*[o[0].data_ptr() if o[0] is not None else None for o in outs])
+    flux = (_P * n)(*[o[1].data_ptr() if o[1] is not None else None for o in outs])
+    nv = (_P * n)(*[o[2].data_ptr() if o[2] is not None else None for o in outs])
+    return ph, sets, snr, flux, nv
+
+
+def batch_outputs(orbit_sets):
+    import torch
+    return [(torch.empty(o.n, dtype=torch.float32, device=o.soa.device),
+             torch.empty(o.n, dtype=torch.float32, device=o.soa.device),
+             torch.empty(o.n, dtype=torch.int32, device=o.soa.device)) for o in orbit_sets]
+
+
+def stack_batched(ctx: Context, patches, orbit_sets, outs=None, k: int = 0, threshold: float = float("-inf"),
+                  cfg=None, prepass: bool = False, eager: bool = False, topk_out=None):
+    """One persistent launch over many patches (graph-captured unless eager).
+    Returns (outs, (idx[n_patches, k], val[n_patches, k], count[n_patches]) or None)."""
+    import torch
+    if outs is None:
+        outs = batch_outputs(orbit_sets)
+    n = len(patches)
+    dev = orbit_sets[0].soa.device
+    if k > 0 and topk_out is None:
+        topk_out = (torch.empty((n, k), dtype=torch.int64, device=dev),
+                    torch.empty((n, k), dtype=torch.float32, device=dev),
+                    torch.empty(n, dtype=torch.int32, device=dev))
+    ph, sets, snr, flux, nv = _batch_arrays(patches, orbit_sets, outs)
+    c = None
+    if cfg is not None:
+        c = DtBatchConfig(int(cfg[0]), int(cfg[1]))
+    flags = (DT_BATCH_PREPASS if prepass else 0) | (DT_BATCH_EAGER if eager else 0)
+    ti, tv, tc = topk_out if k > 0 else (None, None, None)
+    _check(lib().dt_stack_batched(ctx.handle, ph, sets, n, snr, flux, nv, int(k), float(threshold), _ptr(ti),
+                                  _ptr(tv), _ptr(tc), C.byref(c) if c is not None else None, flags))
+    return outs, (topk_out if k > 0 else None)
+
+
+def autotune_batched(ctx: Context, patches, orbit_sets, outs=None, cache_path=None):
+    """Time candidate launch shapes; returns ((chunk, wg_per_cu), ms or -1 if cached)."""
+    if outs is None:
+        outs = batch_outputs(orbit_sets)
+    ph, sets, snr, flux, nv = _batch_arrays(patches, orbit_sets, outs)
+    best = DtBatchConfig()
+    ms = C.c_double()
+    _check(lib().dt_autotune_batched(ctx.handle, ph, sets, len(patches), snr, flux, nv,
+                                     cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms)))
+    return (best.chunk, best.wg_per_cu), ms.value

@@ -1,20 +1,12 @@
 // dt_api.cpp -- the C ABI of libdtrack: contexts, patches, argument
 // validation, memory accounting and stream plumbing.  All numerical work is
 // in the kernels; this file only checks arguments, sizes buffers and enqueues.
-#include <algorithm>
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <numeric>
-#include <vector>
+#include "dt_internal.hpp"
 
-#include "dt_common.hpp"
-
-using namespace dtk;
-
+namespace dtk {
 namespace {
 thread_local char g_err[512] = "";
+}
 
 dt_status fail(dt_status st, const char* fmt, ...) {
   va_list ap;
@@ -27,40 +19,8 @@ dt_status fail(dt_status st, const char* fmt, ...) {
 dt_status hip_fail(hipError_t e, const char* what) {
   return fail(DT_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
-}  // namespace
 
-struct dt_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  size_t mem_limit = 0;
-  size_t mem_used = 0;
-  int n_patches = 0;
-  void* topk_scratch = nullptr;
-  size_t topk_bytes = 0;
-  unsigned long long* d_counter = nullptr;
-  bool alive = true;
-};
-
-struct dt_patch {
-  dt_ctx* ctx = nullptr;
-  int32_t n_exp = 0;
-  dt_dtype dtype = DT_F32;
-  std::vector<int32_t> order;  // sorted position -> caller index
-  std::vector<int32_t> where;  // caller index -> sorted position
-  std::vector<int64_t> plane_off;  // caller index -> plane offset
-  std::vector<int32_t> W, H;       // caller order
-  int rmax = 0;
-  int64_t n_tiles = 0;
-  size_t plane_elems = 0;
-  ExpMeta* d_meta = nullptr;
-  float2* d_planes = nullptr;
-  PrepTile* d_tiles = nullptr;
-  const void** d_flux = nullptr;
-  const void** d_var = nullptr;
-  size_t bytes = 0;
-};
-
-namespace {
+const char* last_error() { return g_err; }
 
 dt_status ctx_alloc(dt_ctx* c, void** p, size_t bytes, const char* what) {
   *p = nullptr;
@@ -84,17 +44,7 @@ void ctx_free(dt_ctx* c, void* p, size_t bytes) {
   c->mem_used -= bytes;
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
+namespace {
 bool finite_all(const double* v, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
@@ -117,6 +67,20 @@ dt_status check_exposure(const dt_exposure& x, int i) {
     return fail(DT_E_DOMAIN, "exposure %d: PSF FWHM %g outside [0.5, 8] px", i, (double)x.psf_fwhm_px);
   return DT_OK;
 }
+
+void patch_free(dt_patch* p) {
+  dt_ctx* c = p->ctx;
+  ctx_free(c, p->d_meta, sizeof(ExpMeta) * p->n_exp);
+  ctx_free(c, p->d_planes, sizeof(float2) * p->plane_elems);
+  ctx_free(c, p->d_tiles, sizeof(PrepTile) * p->n_tiles);
+  ctx_free(c, p->d_flux, sizeof(void*) * p->n_exp);
+  ctx_free(c, p->d_var, sizeof(void*) * p->n_exp);
+  p->d_meta = nullptr;
+  p->d_planes = nullptr;
+  p->d_tiles = nullptr;
+  p->d_flux = p->d_var = nullptr;
+}
+}  // namespace
 
 dt_status check_orbits(const dt_orbits* o) {
   if (!o) return fail(DT_E_ARG, "orbits is NULL");
@@ -147,31 +111,21 @@ StackArgs stack_args(const dt_patch* p, const dt_orbits* o) {
   return a;
 }
 
-void patch_free(dt_patch* p) {
-  dt_ctx* c = p->ctx;
-  ctx_free(c, p->d_meta, sizeof(ExpMeta) * p->n_exp);
-  ctx_free(c, p->d_planes, sizeof(float2) * p->plane_elems);
-  ctx_free(c, p->d_tiles, sizeof(PrepTile) * p->n_tiles);
-  ctx_free(c, p->d_flux, sizeof(void*) * p->n_exp);
-  ctx_free(c, p->d_var, sizeof(void*) * p->n_exp);
-  p->d_meta = nullptr;
-  p->d_planes = nullptr;
-  p->d_tiles = nullptr;
-  p->d_flux = p->d_var = nullptr;
-}
-
-dt_status run_prepass(dt_patch* p) {
-  hipError_t e = launch_prepass(p->d_meta, p->d_tiles, p->n_tiles, p->d_flux, p->d_var, p->dtype, p->d_planes,
-                                p->rmax, p->ctx->stream);
+dt_status run_prepass(dt_patch* p, hipStream_t s) {
+  if (p->images_released) return fail(DT_E_STATE, "the patch's images were released; the pre-pass cannot run");
+  hipError_t e = launch_prepass(p->d_meta, p->d_tiles, p->group_off.data(), p->group_R.data(),
+                                (int)p->group_R.size(), p->d_flux, p->d_var, p->dtype, p->d_planes, s);
   if (e != hipSuccess) return hip_fail(e, "matched-filter pre-pass launch");
   return DT_OK;
 }
 
-}  // namespace
+}  // namespace dtk
+
+using namespace dtk;
 
 extern "C" {
 
-const char* dt_last_error(void) { return g_err; }
+const char* dt_last_error(void) { return dtk::last_error(); }
 const char* dt_version(void) { return "dtrack 0.1 (gfx950)"; }
 
 dt_status dt_ctx_create(int device, void* hip_stream, dt_ctx** out) {
@@ -217,6 +171,8 @@ dt_status dt_ctx_destroy(dt_ctx* c) {
   if (c->n_patches) return fail(DT_E_STATE, "context still owns %d patch(es)", c->n_patches);
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
+  batch_graph_drop(c);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   ctx_free(c, c->topk_scratch, c->topk_bytes);
   ctx_free(c, c->d_counter, sizeof(unsigned long long));
   c->alive = false;
@@ -263,16 +219,29 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
     p->H[p->order[s]] = x.height;
     rad[s] = stamp_radius((double)x.psf_fwhm_px);
     p->rmax = std::max(p->rmax, rad[s]);
-    for (int y0 = 0; y0 < x.height; y0 += PREP_TY)
-      for (int x0 = 0; x0 < x.width; x0 += PREP_TX) tiles.push_back(PrepTile{s, x0, y0, 0});
     off += (int64_t)x.width * x.height;
   }
   p->plane_elems = (size_t)off;
-  p->n_tiles = (int64_t)tiles.size();
   if (p->rmax > PREP_RMAX) {
     delete p;
     return fail(DT_E_DOMAIN, "stamp half-width %d exceeds %d", p->rmax, PREP_RMAX);
   }
+  // pre-pass tiles, grouped by stamp half-width (one kernel instance per R)
+  for (int R = 1; R <= PREP_RMAX; ++R) {
+    size_t before = tiles.size();
+    for (int s = 0; s < n_exp; ++s) {
+      if (rad[s] != R) continue;
+      const dt_exposure& x = sorted[s];
+      for (int y0 = 0; y0 < x.height; y0 += PREP_TY)
+        for (int x0 = 0; x0 < x.width; x0 += PREP_TX) tiles.push_back(PrepTile{s, x0, y0, 0});
+    }
+    if (tiles.size() > before) {
+      p->group_off.push_back((int64_t)before);
+      p->group_R.push_back(R);
+    }
+  }
+  p->group_off.push_back((int64_t)tiles.size());
+  p->n_tiles = (int64_t)tiles.size();
   dt_exposure* d_exps = nullptr;
   int64_t* d_off = nullptr;
   int32_t* d_src = nullptr;
@@ -323,7 +292,7 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
     delete p;
     return hip_fail(e, "patch upload");
   }
-  st = run_prepass(p);
+  st = run_prepass(p, c->stream);
   if (st != DT_OK) {
     patch_free(p);
     delete p;
@@ -337,13 +306,21 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
 dt_status dt_patch_refresh(dt_patch* p) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
   DeviceGuard g(p->ctx->device);
-  return run_prepass(p);
+  return run_prepass(p, p->ctx->stream);
+}
+
+dt_status dt_patch_release_images(dt_patch* p) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  if (batch_graph_uses(p->ctx, p)) batch_graph_drop(p->ctx);
+  p->images_released = true;
+  return DT_OK;
 }
 
 dt_status dt_patch_destroy(dt_patch* p) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
   DeviceGuard g(p->ctx->device);
   (void)hipStreamSynchronize(p->ctx->stream);
+  if (batch_graph_uses(p->ctx, p)) batch_graph_drop(p->ctx);
   p->ctx->n_patches--;
   patch_free(p);
   p->ctx = nullptr;

@@ -28,6 +28,7 @@ struct alignas(16) ExpMeta {
   double a0x, a0y, a0z;     // row 0 of (180/pi) CD^-1 [east; north] (px per unit, ecliptic)
   double a1x, a1y, a1z;     // row 1
   double px0, py0;          // CRPIX - 1
+  double gap, inv_gap;      // epoch step from the previous exposure (epoch order) and its reciprocal
   int64_t plane_off;        // offset of this exposure's plane (in float2 units)
   int32_t W, H;             // image size
   int32_t src;              // caller's index of this exposure
@@ -35,7 +36,7 @@ struct alignas(16) ExpMeta {
   int32_t R;                // stamp half-width ceil(3 sigma)
   int32_t pad;
 };
-static_assert(sizeof(ExpMeta) == 160, "ExpMeta layout");
+static_assert(sizeof(ExpMeta) == 176, "ExpMeta layout");
 
 // One tile of the matched-filter pre-pass.
 struct PrepTile {
@@ -44,16 +45,18 @@ struct PrepTile {
   int32_t pad;
 };
 
-constexpr int PREP_TX = 64;   // tile width  (output pixels)
-constexpr int PREP_TY = 32;   // tile height (output pixels)
+constexpr int PREP_TX = 256;  // tile width (output pixels) = threads per workgroup
+constexpr int PREP_TY = 64;   // tile height (output rows streamed per workgroup)
 constexpr int PREP_RMAX = 12; // largest stamp half-width supported (FWHM <= 8 px gives R = 11)
 
 // Launchers (defined in the .hip files; all enqueue on `s`).
 hipError_t launch_exposure_prep(const dt_exposure* d_in, const int64_t* d_plane_off, const int32_t* d_src,
                                 const int32_t* d_R, int n, ExpMeta* d_out, hipStream_t s);
-hipError_t launch_prepass(const ExpMeta* d_meta, const PrepTile* d_tiles, int64_t n_tiles,
-                          const void* const* d_flux, const void* const* d_var, dt_dtype dtype,
-                          float2* d_planes, int rmax, hipStream_t s);
+// Tiles are grouped by stamp half-width: group gi covers tiles
+// [group_off[gi], group_off[gi+1]) whose exposures all have R = group_R[gi].
+hipError_t launch_prepass(const ExpMeta* d_meta, const PrepTile* d_tiles, const int64_t* group_off,
+                          const int32_t* group_R, int n_groups, const void* const* d_flux,
+                          const void* const* d_var, dt_dtype dtype, float2* d_planes, hipStream_t s);
 
 // Stamp half-width for a PSF FWHM: R = ceil(3 sigma), sigma = FWHM / (2 sqrt(2 ln 2)).
 inline int stamp_radius(double fwhm) {
@@ -81,7 +84,17 @@ struct DebugArgs {
   float *psi, *phi;
 };
 
+// Work item of the batched persistent launch: orbits [begin, begin + count)
+// of patch `patch`.
+struct WorkItem {
+  int32_t patch;
+  int32_t count;
+  int64_t begin;
+};
+
 hipError_t launch_stack(const StackArgs& a, hipStream_t s);
+hipError_t launch_batched(const StackArgs* d_descs, const WorkItem* d_items, int n_items, unsigned int* d_counter,
+                          int n_wg, hipStream_t s);
 hipError_t launch_debug(const StackArgs& a, const DebugArgs& d, hipStream_t s);
 hipError_t launch_validate(const StackArgs& a, unsigned long long* d_bad, hipStream_t s);
 

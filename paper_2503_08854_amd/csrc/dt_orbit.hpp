@@ -13,30 +13,72 @@
 //   * Kepler's equation is solved from the previous exposure's eccentric
 //     anomaly: a second-order Taylor start in the mean-anomaly step, then
 //     Newton steps; sin E and cos E are advanced by exact small-angle
-//     rotations (series to O(d^11)) and re-anchored with a full sincos every
-//     ANCHOR exposures, so no transcendental is evaluated per sample.
-//   * Light time is solved by Newton's method on c (tau_g + D) = |rho(D)|,
-//     starting from the previous exposure's light time tau_g, with
-//     rho(D) = r(t - tau_g - D) - r_obs expanded to third order in D about the
-//     Kepler solution at t - tau_g (velocity, acceleration -mu r/|r|^3 and its
-//     time derivative).  When |D| exceeds LT_TAYLOR_MAX the orbit is re-solved
-//     at the corrected epoch instead.
+//     rotations (Taylor series whose truncation is below 1e-20) and
+//     re-anchored with a full sincos every ANCHOR solves, so no
+//     transcendental function is evaluated per sample.
+//   * The light time tau solves c tau = |r(t - tau) - r_obs|.  It is predicted
+//     by linear extrapolation of the previous exposures' light times; the
+//     orbit is solved at t - tau_pred and one Newton step on
+//     F(D) = c (tau_pred + D) - |rho - D v| gives the remaining correction D,
+//     applied to the position as rho - D v.  The neglected terms are
+//     O(D^2 |acc|) in position and O(D^2 |v|^2 / (c |rho|)) in tau; D is kept
+//     below LT_LINEAR_MAX = 1e-6 day (else the orbit is re-solved at the
+//     corrected epoch), which bounds them below 1e-15 AU.
+// The common case (small steps) runs straight-line code; the general paths
+// (cold start, long rotations, light-time re-solves) are taken per lane only
+// when a bound above is not met.
 #pragma once
 #include "dt_common.hpp"
 
 namespace dtk {
 
-constexpr int ANCHOR = 16;                 // exposures between full sincos re-anchors
-constexpr double LT_TAYLOR_MAX = 2.0e-3;   // days; larger light-time steps re-solve Kepler
+constexpr int ANCHOR = 32;                 // solves between full sincos re-anchors
+constexpr double LT_LINEAR_MAX = 1.0e-6;   // days; larger light-time corrections re-solve Kepler
+constexpr double ROT_SHORT = 0.005;        // rad; |d| <= this uses the short series
 constexpr double ROT_MAX = 0.05;           // rad; larger steps take the full-sincos path
 
+// Reciprocal from the hardware estimate refined once by Newton-Raphson
+// (relative error ~ the square of the estimate's, < 1e-13).
+__device__ __forceinline__ double rcp1(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+// Two refinements: within ~1 ulp for normal, well-scaled arguments.
+__device__ __forceinline__ double rcp2(double x) {
+  double r = rcp1(x);
+  double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+// sqrt(x) and 1/sqrt(x) for normal positive x (within ~1 ulp): one
+// Goldschmidt iteration from the hardware estimate and a final residual
+// correction.
+__device__ __forceinline__ void sqrt_rsq(double x, double& s, double& rs) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * y;
+  double g = x * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, g, x);
+  s = fma(r, h, g);
+  rs = 2.0 * h;
+}
+
+// Per-orbit constants ("orbit preparation"): with P the unit vector to
+// perihelion and Q the one 90 deg ahead in the orbit plane (ecliptic),
+// r(E) = a (cos E - e) P + b sin E Q = cos E aP + sin E bQ + c0 and
+// v(E) = n g (-sin E aP + cos E bQ), g = 1 / (1 - e cos E).
 struct Orbit {
-  double a, e, n, b, sq, m0;     // a, e, mean motion, b = a sqrt(1-e^2), sqrt(1-e^2), M0
-  double P0, P1, P2, Q0, Q1, Q2; // perihelion and semi-latus directions (ecliptic)
+  double e, n, m0, he;          // eccentricity, mean motion k a^-3/2, M0, -e/2
+  double aP0, aP1, aP2;         // a P
+  double bQ0, bQ1, bQ2;         // b Q, b = a sqrt(1 - e^2)
+  double c00, c01, c02;         // -a e P
 };
 
 struct KepState {
   double E, sE, cE, M;  // E solves E - e sin E = M; (sE, cE) ~ (sin E, cos E)
+  double g;             // 1 / (1 - e cE) at the solution
   int since_anchor;
   bool have;
 };
@@ -47,40 +89,59 @@ __device__ __forceinline__ bool orbit_ok(double a, double e, double inc, double 
   return fin && a > 0.0 && e >= 0.0 && e < 1.0;
 }
 
-// Orbit preparation: mean motion n = k a^-3/2 and the in-plane basis
-// P (to perihelion), Q (90 deg ahead) from (i, node, peri).
 __device__ __forceinline__ void orbit_prep(double a, double e, double inc, double node, double peri, double m0,
                                            Orbit& o) {
   double si, ci, sO, cO, sw, cw;
   sincos(inc, &si, &ci);
   sincos(node, &sO, &cO);
   sincos(peri, &sw, &cw);
-  o.a = a;
+  const double P0 = cO * cw - sO * sw * ci, P1 = sO * cw + cO * sw * ci, P2 = sw * si;
+  const double Q0 = -cO * sw - sO * cw * ci, Q1 = -sO * sw + cO * cw * ci, Q2 = cw * si;
+  const double b = a * sqrt((1.0 - e) * (1.0 + e));
   o.e = e;
   o.n = K_GAUSS / (a * sqrt(a));
-  o.sq = sqrt((1.0 - e) * (1.0 + e));
-  o.b = a * o.sq;
   o.m0 = m0;
-  o.P0 = cO * cw - sO * sw * ci;
-  o.P1 = sO * cw + cO * sw * ci;
-  o.P2 = sw * si;
-  o.Q0 = -cO * sw - sO * cw * ci;
-  o.Q1 = -sO * sw + cO * cw * ci;
-  o.Q2 = cw * si;
+  o.he = -0.5 * e;
+  o.aP0 = a * P0;
+  o.aP1 = a * P1;
+  o.aP2 = a * P2;
+  o.bQ0 = b * Q0;
+  o.bQ1 = b * Q1;
+  o.bQ2 = b * Q2;
+  o.c00 = -e * o.aP0;
+  o.c01 = -e * o.aP1;
+  o.c02 = -e * o.aP2;
 }
 
-// Rotate (sE, cE) by a small angle d (|d| <= ROT_MAX): sin d and cos d - 1
-// from their Taylor series (truncation < 1e-22 at |d| = 0.05).
-__device__ __forceinline__ void kep_rotate(KepState& k, double d) {
-  double d2 = d * d;
-  double s = d * (1.0 - d2 * (1.0 / 6.0) * (1.0 - d2 * (1.0 / 20.0) * (1.0 - d2 * (1.0 / 42.0) * (1.0 - d2 * (1.0 / 72.0)))));
-  double cm1 = -0.5 * d2 * (1.0 - d2 * (1.0 / 12.0) * (1.0 - d2 * (1.0 / 30.0) * (1.0 - d2 * (1.0 / 56.0) * (1.0 - d2 * (1.0 / 90.0)))));
-  double sE = fma(k.cE, s, fma(k.sE, cm1, k.sE));
-  double cE = fma(-k.sE, s, fma(k.cE, cm1, k.cE));
+// Rotate (sE, cE) by d: sin d and cos d - 1 from their Taylor series.
+// Short form for |d| <= ROT_SHORT (truncation < 2e-20), long form for
+// |d| <= ROT_MAX (< 1e-22).
+__device__ __forceinline__ void rot_apply(KepState& k, double s, double cm1, double d) {
+  const double sE = fma(k.cE, s, fma(k.sE, cm1, k.sE));
+  const double cE = fma(-k.sE, s, fma(k.cE, cm1, k.cE));
   k.sE = sE;
   k.cE = cE;
   k.E += d;
 }
+__device__ __forceinline__ void rot_short(KepState& k, double d) {
+  const double d2 = d * d;
+  const double s = fma(d * d2, fma(d2, 1.0 / 120.0, -1.0 / 6.0), d);
+  const double cm1 = d2 * fma(d2, fma(d2, -1.0 / 720.0, 1.0 / 24.0), -0.5);
+  rot_apply(k, s, cm1, d);
+}
+__device__ __forceinline__ void rot_long(KepState& k, double d) {
+  const double d2 = d * d;
+  const double s =
+      fma(d * d2,
+          fma(d2, fma(d2, fma(d2, fma(d2, -1.0 / 39916800.0, 1.0 / 362880.0), -1.0 / 5040.0), 1.0 / 120.0),
+              -1.0 / 6.0),
+          d);
+  const double cm1 =
+      d2 * fma(d2, fma(d2, fma(d2, fma(d2, -1.0 / 3628800.0, 1.0 / 40320.0), -1.0 / 720.0), 1.0 / 24.0), -0.5);
+  rot_apply(k, s, cm1, d);
+}
+// Tiny step (|d| < 1e-8): sin d = d, cos d - 1 = -d^2/2 to < 1e-24.
+__device__ __forceinline__ void rot_tiny(KepState& k, double d) { rot_apply(k, d, -0.5 * d * d, d); }
 
 // Cold solve: Newton with full sincos from E0 = M + 0.85 e sign(sin M), kept
 // inside the root bracket [M - e, M + e] by bisection.
@@ -111,20 +172,19 @@ __device__ inline void kepler_cold(double M, double e, KepState& k) {
   k.sE = s;
   k.cE = c;
   k.M = M;
+  k.g = rcp2(fma(-e, c, 1.0));
   k.since_anchor = 0;
   k.have = true;
 }
 
-// Warm solve from the previous solution (see the file comment).
-__device__ inline void kepler_solve(double M, double e, KepState& k) {
+// General warm solve (any step size the rotation series cover).
+__device__ inline void kepler_general(double M, double e, KepState& k) {
   if (!k.have) {
     kepler_cold(M, e, k);
     return;
   }
-  double dM = M - k.M;
-  double g = 1.0 / (1.0 - e * k.cE);
-  double d = dM * g;
-  d = fma(-0.5 * e * k.sE * g, d * d, d);  // E''(M) = -e sin E g^3
+  double d = (M - k.M) * k.g;
+  d = fma(-0.5 * e * k.sE * k.g, d * d, d);  // E''(M) = -e sin E g^3
   if (!(fabs(d) <= ROT_MAX)) {
     kepler_cold(M, e, k);
     return;
@@ -134,17 +194,40 @@ __device__ inline void kepler_solve(double M, double e, KepState& k) {
     sincos(k.E, &k.sE, &k.cE);
     k.since_anchor = 0;
   } else {
-    kep_rotate(k, d);
+    rot_long(k, d);
   }
   for (int it = 0; it < 8; ++it) {
-    double f = k.E - e * k.sE - M;
-    double dd = -f / (1.0 - e * k.cE);
-    kep_rotate(k, dd);
-    // quadratic convergence: the next step would be < e dd^2 / (1 - e) < 1e-16
-    if (fabs(dd) < 1e-8) break;
+    k.g = rcp1(fma(-e, k.cE, 1.0));
+    double dd = -fma(-e, k.sE, k.E - M) * k.g;
+    if (fabs(dd) < 1e-8) {
+      // quadratic convergence: the next step would be < e dd^2 / (1 - e) < 1e-16
+      rot_tiny(k, dd);
+      break;
+    }
+    rot_long(k, dd);
   }
   k.M = M;
   k.since_anchor++;
+}
+
+// Common-case warm solve: returns false (state untouched) when the step is
+// beyond the short series, a re-anchor is due, or one Newton step does not
+// converge.
+__device__ __forceinline__ bool kepler_fast(double M, double he, double e, KepState& k) {
+  double d = (M - k.M) * k.g;
+  d = fma(he * k.sE * k.g, d * d, d);
+  if (!(fabs(d) <= ROT_SHORT) || k.since_anchor >= ANCHOR) return false;
+  KepState t = k;
+  rot_short(t, d);
+  const double g = rcp1(fma(-e, t.cE, 1.0));
+  const double dd = -fma(-e, t.sE, t.E - M) * g;
+  if (!(fabs(dd) < 1e-8)) return false;
+  rot_tiny(t, dd);
+  t.g = g;
+  t.M = M;
+  t.since_anchor++;
+  k = t;
+  return true;
 }
 
 struct SampleOut {
@@ -153,85 +236,66 @@ struct SampleOut {
   bool front, inside;
 };
 
-// One (orbit, exposure) sample.  tau carries the previous light time (0 with
-// have_tau == false) and returns this one.
-__device__ inline void sample(const Orbit& o, KepState& k, double& tau, bool& have_tau, const ExpMeta& x,
-                              double epoch, SampleOut& out) {
+// Light-time history carried across exposures: last light time and its rate.
+struct LtState {
+  double tau, rate;
+  int n;  // samples solved so far
+};
+
+// One (orbit, exposure) sample.  `gap` is t_e minus the epoch of the previous
+// sample of this orbit and inv_gap its reciprocal (0 when gap == 0).
+__device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt, const ExpMeta& x, double epoch,
+                                       double gap, double inv_gap, SampleOut& out) {
   const double dt = x.t - epoch;
-  double tg = have_tau ? tau : 0.0;
-  double rho0, rho1, rho2, D = 0.0;
-  double v0, v1, v2, h0, h1, h2, j0, j1, j2, dist = 0.0;
-  for (int pass = 0; pass < 3; ++pass) {
-    kepler_solve(fma(o.n, dt - tg, o.m0), o.e, k);
-    // state at t - tg
-    const double X = o.a * (k.cE - o.e), Y = o.b * k.sE;
-    const double r0 = X * o.P0 + Y * o.Q0, r1 = X * o.P1 + Y * o.Q1, r2 = X * o.P2 + Y * o.Q2;
-    const double ir = 1.0 / (o.a * (1.0 - o.e * k.cE));       // 1/|r|
-    const double vf = o.n * o.a * o.a * ir;                    // sqrt(mu a)/|r|
-    const double vs = -vf * k.sE, vc = vf * o.sq * k.cE;
-    v0 = vs * o.P0 + vc * o.Q0;
-    v1 = vs * o.P1 + vc * o.Q1;
-    v2 = vs * o.P2 + vc * o.Q2;
-    const double g3 = MU_SUN * ir * ir * ir;                  // mu/|r|^3
-    const double rv3 = 3.0 * (r0 * v0 + r1 * v1 + r2 * v2) * ir * ir;
-    // half acceleration and one sixth of its time derivative
-    h0 = -0.5 * g3 * r0;
-    h1 = -0.5 * g3 * r1;
-    h2 = -0.5 * g3 * r2;
-    j0 = -(g3 / 6.0) * (v0 - rv3 * r0);
-    j1 = -(g3 / 6.0) * (v1 - rv3 * r1);
-    j2 = -(g3 / 6.0) * (v2 - rv3 * r2);
-    rho0 = r0 - x.ox;
-    rho1 = r1 - x.oy;
-    rho2 = r2 - x.oz;
-    // Newton on F(D) = c (tg + D) - |rho(D)|, rho(D) = rho - D v + D^2 h - D^3 j
-    const double d0 = sqrt(rho0 * rho0 + rho1 * rho1 + rho2 * rho2);
-    const double iFp = 1.0 / (C_AU_DAY + (rho0 * v0 + rho1 * v1 + rho2 * v2) / d0);
-    D = 0.0;
-    dist = d0;
-    for (int it = 0; it < 6; ++it) {
-      double F = C_AU_DAY * (tg + D) - dist;
-      double dD = -F * iFp;
-      D += dD;
-      double q0 = fma(D, fma(D, fma(-D, j0, h0), -v0), rho0);
-      double q1 = fma(D, fma(D, fma(-D, j1, h1), -v1), rho1);
-      double q2 = fma(D, fma(D, fma(-D, j2, h2), -v2), rho2);
-      dist = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
-      // chord-Newton: the next step is ~ (|v|^2/|rho|)/(2c) dD^2, < 1e-14 day
-      // for |dD| < 1e-5 day down to 0.01 AU range
-      if (fabs(dD) < 1e-5) break;
-    }
-    if (fabs(D) <= LT_TAYLOR_MAX || pass == 2) break;
-    tg += D;  // large correction: re-solve Kepler at the corrected epoch
+  double tg = lt.n == 0 ? 0.0 : fma(lt.rate, gap, lt.tau);
+  const double b0 = o.c00 - x.ox, b1 = o.c01 - x.oy, b2 = o.c02 - x.oz;
+  double rho0, rho1, rho2, v0, v1, v2, D, dist;
+  int pass = 0;
+  while (true) {
+    const double M = fma(o.n, dt - tg, o.m0);
+    if (!(k.have && kepler_fast(M, o.he, o.e, k))) kepler_general(M, o.e, k);
+    // rho = r(t - tg) - r_obs, v = dr/dt
+    const double ng = o.n * k.g;
+    const double vs = -ng * k.sE, vc = ng * k.cE;
+    v0 = fma(vc, o.bQ0, vs * o.aP0);
+    v1 = fma(vc, o.bQ1, vs * o.aP1);
+    v2 = fma(vc, o.bQ2, vs * o.aP2);
+    rho0 = fma(k.cE, o.aP0, fma(k.sE, o.bQ0, b0));
+    rho1 = fma(k.cE, o.aP1, fma(k.sE, o.bQ1, b1));
+    rho2 = fma(k.cE, o.aP2, fma(k.sE, o.bQ2, b2));
+    double rdist;
+    sqrt_rsq(fma(rho0, rho0, fma(rho1, rho1, rho2 * rho2)), dist, rdist);
+    // Newton step on F(D) = c (tg + D) - |rho - D v| from D = 0
+    const double rv = fma(rho0, v0, fma(rho1, v1, rho2 * v2)) * rdist;
+    D = fma(-C_AU_DAY, tg, dist) * rcp1(C_AU_DAY + rv);
+    if (fabs(D) <= LT_LINEAR_MAX || ++pass == 4) break;
+    tg += D;  // poor prediction: solve the orbit again at the corrected epoch
   }
-  const double q0 = fma(D, fma(D, fma(-D, j0, h0), -v0), rho0);
-  const double q1 = fma(D, fma(D, fma(-D, j1, h1), -v1), rho1);
-  const double q2 = fma(D, fma(D, fma(-D, j2, h2), -v2), rho2);
-  tau = tg + D;
-  have_tau = true;
+  const double q0 = fma(-D, v0, rho0), q1 = fma(-D, v1, rho1), q2 = fma(-D, v2, rho2);
+  const double tau = tg + D;
+  lt.rate = lt.n > 0 ? (tau - lt.tau) * inv_gap : 0.0;
+  lt.tau = tau;
+  lt.n++;
   out.tau = tau;
-  // TAN projection: p = CRPIX - 1 + (A . rho) / (c . rho)
-  const double w = x.cx * q0 + x.cy * q1 + x.cz * q2;
+  // TAN projection: p = CRPIX - 1 + (A . q) / (c . q)
+  const double w = fma(x.cx, q0, fma(x.cy, q1, x.cz * q2));
+  const double iw = rcp2(w);
+  out.px = fma(fma(x.a0x, q0, fma(x.a0y, q1, x.a0z * q2)), iw, x.px0);
+  out.py = fma(fma(x.a1x, q0, fma(x.a1y, q1, x.a1z * q2)), iw, x.py0);
   out.front = (w > 0.0) && (dist >= 1e-9);
-  out.inside = false;
-  out.ix = out.iy = (int)0x80000000;
-  out.px = out.py = __builtin_nan("");
-  if (!out.front) return;
-  const double iw = 1.0 / w;
-  out.px = fma(x.a0x * q0 + x.a0y * q1 + x.a0z * q2, iw, x.px0);
-  out.py = fma(x.a1x * q0 + x.a1y * q1 + x.a1z * q2, iw, x.py0);
+  // nearest pixel floor(p + 0.5), clamped into int range before conversion
   const double fx = floor(out.px + 0.5), fy = floor(out.py + 0.5);
-  if (fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H) {
-    out.ix = (int)fx;
-    out.iy = (int)fy;
-    out.inside = true;
-  } else if (fabs(fx) < 2.0e9 && fabs(fy) < 2.0e9) {
-    out.ix = (int)fx;
-    out.iy = (int)fy;
+  out.ix = (int)fmin(fmax(fx, -2147483648.0), 2147483647.0);
+  out.iy = (int)fmin(fmax(fy, -2147483648.0), 2147483647.0);
+  out.inside = out.front && (unsigned)out.ix < (unsigned)x.W && (unsigned)out.iy < (unsigned)x.H;
+  if (!out.front) {
+    out.px = out.py = __builtin_nan("");
+    out.ix = out.iy = (int)0x80000000;
   }
 }
 
-// FP32 Kahan summation (the benchmark spec precision scheme): sum ~ s - c.
+// FP32 Kahan summation (precision scheme: FP32 gathers, compensated FP32
+// accumulation): the sum is s - c.
 struct Kahan {
   float s, c;
   __device__ __forceinline__ void init() { s = c = 0.f; }

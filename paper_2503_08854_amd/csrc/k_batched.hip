@@ -1,0 +1,49 @@
+// k_batched.hip -- many patches with uneven exposure counts, image sizes and
+// orbit-set sizes in one persistent launch.
+//
+// The host splits every patch's orbit set into work items of up to `chunk`
+// orbits and orders them by cost (exposures x orbits, largest first).  A
+// grid sized to the machine, not to the work, then pulls items from one
+// device counter: each workgroup takes the next item, runs the same per-orbit
+// stack as the single-patch kernel over that patch's exposures, and asks for
+// another until the counter passes the end.  Large and small patches share
+// the CUs, and the tail is made of the cheapest items.  The counter is zeroed
+// by a one-thread kernel so the whole sequence can be captured in a graph.
+#include "dt_stack.hpp"
+
+namespace dtk {
+
+__global__ void k_reset_counter(unsigned int* counter) { *counter = 0u; }
+
+__global__ __launch_bounds__(256) void k_stack_persistent(const StackArgs* __restrict__ descs,
+                                                          const WorkItem* __restrict__ items, int n_items,
+                                                          unsigned int* __restrict__ counter) {
+  __shared__ int s_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();  // every lane has read s_item before it is overwritten
+    if (it >= n_items) break;
+    const WorkItem w = items[it];
+    const StackArgs A = descs[w.patch];
+    for (int64_t o = w.begin + threadIdx.x; o < w.begin + w.count; o += blockDim.x) {
+      float snr, flux;
+      int nv;
+      stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);
+      if (A.snr) A.snr[o] = snr;
+      if (A.flux) A.flux[o] = flux;
+      if (A.nvalid) A.nvalid[o] = nv;
+    }
+  }
+}
+
+hipError_t launch_batched(const StackArgs* d_descs, const WorkItem* d_items, int n_items, unsigned int* d_counter,
+                          int n_wg, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, d_counter);
+  hipLaunchKernelGGL(k_stack_persistent, dim3(n_wg), dim3(256), 0, s, d_descs, d_items, n_items, d_counter);
+  return hipGetLastError();
+}
+
+}  // namespace dtk

@@ -9,6 +9,8 @@
 // gives exactly the per-intersection filter.  The Gaussian stamp is
 // separable, so each plane is a row pass followed by a column pass of a 1-D
 // kernel over LDS-staged tiles.
+#include <algorithm>
+
 #include "dt_common.hpp"
 
 namespace dtk {
@@ -68,6 +70,8 @@ __global__ void k_exposure_prep(const dt_exposure* __restrict__ in, const int64_
   m.a1z = r2d * (i10 * eE[2] + i11 * nE[2]);
   m.px0 = x.crpix[0] - 1.0;
   m.py0 = x.crpix[1] - 1.0;
+  m.gap = i > 0 ? x.t - in[i - 1].t : 0.0;  // input is in epoch order
+  m.inv_gap = m.gap > 0.0 ? 1.0 / m.gap : 0.0;
   m.plane_off = plane_off[i];
   m.W = x.width;
   m.H = x.height;
@@ -87,9 +91,14 @@ hipError_t launch_exposure_prep(const dt_exposure* d_in, const int64_t* d_plane_
 }
 
 // ----------------------------------------------------------------------------
-// Matched-filter planes.  One workgroup per PREP_TX x PREP_TY output tile.
-// LDS holds the haloed input as {D*w, w} with w = 1/V (0 where masked), then
-// the row-filtered intermediate.  Stamp half-width R = ceil(3 sigma).
+// Matched-filter planes.  One workgroup of PREP_TX threads per PREP_TX-wide
+// column strip and PREP_TY output rows.  The workgroup streams the input rows
+// y0 - R .. y0 + TY + R - 1: each row is loaded once (coalesced, the next row
+// prefetched into registers), turned into {D w, w} with w = 1/V (0 where the
+// pixel is masked or off the image) in a double-buffered LDS row, filtered
+// along x with the 1-D Gaussian, and pushed into a (2R+1)-row register window
+// per column that is filtered along y to give one output row.  R is a
+// template parameter so the window lives in registers.
 // ----------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ float load_px(const void* p, int64_t k);
@@ -102,111 +111,132 @@ __device__ __forceinline__ float load_px<_Float16>(const void* p, int64_t k) {
   return (float)__builtin_nontemporal_load(static_cast<const _Float16*>(p) + k);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_prepass(const ExpMeta* __restrict__ meta, const PrepTile* __restrict__ tiles,
-                                                 const void* const* __restrict__ flux,
-                                                 const void* const* __restrict__ var, float2* __restrict__ planes,
-                                                 int rmax) {
-  extern __shared__ float2 lds[];
-  __shared__ float g1[2 * PREP_RMAX + 1], g2[2 * PREP_RMAX + 1];
-  __shared__ float s_norm1, s_norm2;
+__device__ __forceinline__ float2 weight_pair(float d, float v) {
+  if (__builtin_isfinite(d) && __builtin_isfinite(v) && v > 0.f) {
+    float w = 1.0f / v;
+    return make_float2(d * w, w);
+  }
+  return make_float2(0.f, 0.f);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__ meta,
+                                                     const PrepTile* __restrict__ tiles,
+                                                     const void* const* __restrict__ flux,
+                                                     const void* const* __restrict__ var,
+                                                     float2* __restrict__ planes) {
+  constexpr int K = 2 * R + 1;
+  constexpr int RW = PREP_TX + 2 * R;
+  __shared__ float2 row[2][RW];
   const PrepTile tl = tiles[blockIdx.x];
   const ExpMeta& m = meta[tl.e];
   const int W = m.W, H = m.H;
-  const double sig = (double)m.fwhm / (2.0 * sqrt(2.0 * log(2.0)));
-  const int R = m.R;  // <= rmax, checked on the host
-  const int IW = PREP_TX + 2 * rmax;        // LDS row pitch (input)
-  const int IH = PREP_TY + 2 * R;
-  float2* in = lds;                          // [IH][IW]
-  float2* hr = lds + (PREP_TY + 2 * rmax) * IW;  // [IH][PREP_TX]
   const int tid = threadIdx.x;
-  if (tid <= 2 * R) {
-    double d = tid - R;
+  // 1-D weights g and g^2; the 2-D stamp is g(dx) g(dy) / Z with Z = (sum g)^2
+  const double sig = (double)m.fwhm / (2.0 * sqrt(2.0 * log(2.0)));
+  float g1[K], g2[K];
+  double zs = 0.0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double d = (double)(j - R);
     double g = exp(-d * d / (2.0 * sig * sig));
-    g1[tid] = (float)g;
-    g2[tid] = (float)(g * g);
+    zs += g;
+    g1[j] = (float)g;
+    g2[j] = (float)(g * g);
   }
-  if (tid == 0) {
-    double z = 0.0;
-    for (int j = -R; j <= R; ++j) z += exp(-(double)(j * j) / (2.0 * sig * sig));
-    z = z * z;  // the 2-D stamp sum is the square of the 1-D sum
-    s_norm1 = (float)(1.0 / z);
-    s_norm2 = (float)(1.0 / (z * z));
-  }
+  const double z = zs * zs;
+  const float n1 = (float)(1.0 / z), n2 = (float)(1.0 / (z * z));
   const void* Dp = flux[m.src];
   const void* Vp = var[m.src];
-  const int gx0 = tl.x0 - R, gy0 = tl.y0 - R;
-  const int inw = PREP_TX + 2 * R;
-  for (int k = tid; k < IH * inw; k += 256) {
-    int r = k / inw, c = k - r * inw;
-    int gx = gx0 + c, gy = gy0 + r;
-    float2 v2 = make_float2(0.f, 0.f);
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      int64_t q = (int64_t)gy * W + gx;
-      float d = load_px<T>(Dp, q);
-      float v = load_px<T>(Vp, q);
-      if (__builtin_isfinite(d) && __builtin_isfinite(v) && v > 0.f) {
-        float w = 1.0f / v;
-        v2 = make_float2(d * w, w);
+  // this thread's input columns: x0 - R + tid, and (halo) x0 + TX - R + tid
+  const int cx = tl.x0 - R + tid;
+  const int hx = tl.x0 + PREP_TX - R + tid;
+  const bool has_h = tid < 2 * R;
+  const bool in_c = cx >= 0 && cx < W;
+  const bool in_h = has_h && hx >= 0 && hx < W;
+  const int gx = tl.x0 + tid;  // output column
+  float dc = 0.f, vc = 0.f, dh = 0.f, vh = 0.f;
+  auto fetch = [&](int gy) {
+    dc = vc = dh = vh = __builtin_nanf("");
+    if (gy >= 0 && gy < H) {
+      int64_t base = (int64_t)gy * W;
+      if (in_c) {
+        dc = load_px<T>(Dp, base + cx);
+        vc = load_px<T>(Vp, base + cx);
+      }
+      if (in_h) {
+        dh = load_px<T>(Dp, base + hx);
+        vh = load_px<T>(Vp, base + hx);
       }
     }
-    in[r * IW + c] = v2;
-  }
-  __syncthreads();
-  // row pass: hr[r][x] = sum_j g[j] in[r][x + j]
-  for (int k = tid; k < IH * PREP_TX; k += 256) {
-    int r = k / PREP_TX, x = k - r * PREP_TX;
-    const float2* row = in + r * IW + x;
+  };
+  float2 win[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) win[j] = make_float2(0.f, 0.f);
+  fetch(tl.y0 - R);
+  for (int r = 0; r < PREP_TY + 2 * R; ++r) {
+    float2* buf = row[r & 1];
+    buf[tid] = weight_pair(dc, vc);
+    if (has_h) buf[PREP_TX + tid] = weight_pair(dh, vh);
+    if (r + 1 < PREP_TY + 2 * R) fetch(tl.y0 - R + r + 1);
+    __syncthreads();
     float a = 0.f, b = 0.f;
-    for (int j = 0; j <= 2 * R; ++j) {
-      float2 v = row[j];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      float2 v = buf[tid + j];
       a = fmaf(g1[j], v.x, a);
       b = fmaf(g2[j], v.y, b);
     }
-    hr[r * PREP_TX + x] = make_float2(a, b);
-  }
-  __syncthreads();
-  const float n1 = s_norm1, n2 = s_norm2;
-  for (int k = tid; k < PREP_TY * PREP_TX; k += 256) {
-    int y = k / PREP_TX, x = k - y * PREP_TX;
-    int gx = tl.x0 + x, gy = tl.y0 + y;
-    if (gx >= W || gy >= H) continue;
-    float a = 0.f, b = 0.f;
-    for (int j = 0; j <= 2 * R; ++j) {
-      float2 v = hr[(y + j) * PREP_TX + x];
-      a = fmaf(g1[j], v.x, a);
-      b = fmaf(g2[j], v.y, b);
+#pragma unroll
+    for (int j = 0; j < K - 1; ++j) win[j] = win[j + 1];
+    win[K - 1] = make_float2(a, b);
+    const int gy = tl.y0 + r - 2 * R;  // output row centred in the window
+    if (r >= 2 * R && gy < H && gx < W) {
+      float pa = 0.f, pb = 0.f;
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        pa = fmaf(g1[j], win[j].x, pa);
+        pb = fmaf(g2[j], win[j].y, pb);
+      }
+      planes[m.plane_off + (int64_t)gy * W + gx] = make_float2(pa * n1, pb * n2);
     }
-    planes[m.plane_off + (int64_t)gy * W + gx] = make_float2(a * n1, b * n2);
   }
 }
 
-hipError_t launch_prepass(const ExpMeta* d_meta, const PrepTile* d_tiles, int64_t n_tiles,
-                          const void* const* d_flux, const void* const* d_var, dt_dtype dtype,
-                          float2* d_planes, int rmax, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  if (rmax < 0 || rmax > PREP_RMAX) return hipErrorInvalidValue;
-  size_t lds = sizeof(float2) * ((size_t)(PREP_TY + 2 * rmax) * (PREP_TX + 2 * rmax) +
-                                 (size_t)(PREP_TY + 2 * rmax) * PREP_TX);
-  if (lds > 64 * 1024) {
-    hipError_t e = dtype == DT_F32
-                       ? hipFuncSetAttribute((const void*)k_prepass<float>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                       : hipFuncSetAttribute((const void*)k_prepass<_Float16>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  const int64_t max_grid = 0x7fffffff;
-  for (int64_t off = 0; off < n_tiles; off += max_grid) {
-    unsigned int g = (unsigned int)((n_tiles - off) < max_grid ? (n_tiles - off) : max_grid);
-    if (dtype == DT_F32)
-      hipLaunchKernelGGL(k_prepass<float>, dim3(g), dim3(256), lds, s, d_meta, d_tiles + off, d_flux, d_var,
-                         d_planes, rmax);
-    else
-      hipLaunchKernelGGL(k_prepass<_Float16>, dim3(g), dim3(256), lds, s, d_meta, d_tiles + off, d_flux, d_var,
-                         d_planes, rmax);
+template <typename T>
+static hipError_t launch_prepass_t(int R, const ExpMeta* d_meta, const PrepTile* d_tiles, unsigned g,
+                                   const void* const* d_flux, const void* const* d_var, float2* d_planes,
+                                   hipStream_t s) {
+  switch (R) {
+#define DT_CASE(RR)                                                                                          \
+  case RR:                                                                                                   \
+    hipLaunchKernelGGL((k_prepass<T, RR>), dim3(g), dim3(PREP_TX), 0, s, d_meta, d_tiles, d_flux, d_var,  \
+                       d_planes);                                                                            \
+    break;
+    DT_CASE(1) DT_CASE(2) DT_CASE(3) DT_CASE(4) DT_CASE(5) DT_CASE(6)
+    DT_CASE(7) DT_CASE(8) DT_CASE(9) DT_CASE(10) DT_CASE(11) DT_CASE(12)
+#undef DT_CASE
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_prepass(const ExpMeta* d_meta, const PrepTile* d_tiles, const int64_t* group_off,
+                          const int32_t* group_R, int n_groups, const void* const* d_flux,
+                          const void* const* d_var, dt_dtype dtype, float2* d_planes, hipStream_t s) {
+  for (int gi = 0; gi < n_groups; ++gi) {
+    const int64_t beg = group_off[gi], end = group_off[gi + 1];
+    for (int64_t off = beg; off < end; off += 0x7fffffff) {
+      unsigned g = (unsigned)std::min<int64_t>(end - off, 0x7fffffff);
+      hipError_t e = dtype == DT_F32
+                         ? launch_prepass_t<float>(group_R[gi], d_meta, d_tiles + off, g, d_flux, d_var, d_planes, s)
+                         : launch_prepass_t<_Float16>(group_R[gi], d_meta, d_tiles + off, g, d_flux, d_var,
+                                                      d_planes, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 }  // namespace dtk

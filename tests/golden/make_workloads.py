@@ -171,7 +171,72 @@ def survey_small(seed=3):
                   name="survey_small", span=8.0, offsets=offs)
 
 
-WORKLOADS = {"tiny": tiny, "survey": survey, "survey_small": survey_small}
+def reference_orbit_general(rng, obs, a_rng, e_rng, inc_rng, near_earth=False):
+    """A reference orbit whose geometric position at the epoch is on a line of
+    sight from the observer at elongation 60-180 deg (opposition excluded for
+    a < 1 AU by the construction itself); near_earth puts it at r ~ 1.001 AU,
+    elongation 90 deg, i.e. ~0.05 AU from the observer."""
+    for _ in range(10000):
+        a = float(rng.uniform(*a_rng))
+        e = float(rng.uniform(*e_rng))
+        inc = math.radians(float(rng.uniform(*inc_rng)))
+        if near_earth:
+            elong = math.radians(90.0)
+        else:
+            elong = math.radians(float(rng.uniform(60.0, 180.0)))
+        lam_obs = math.atan2(obs[1], obs[0])
+        side = 1.0 if rng.random() < 0.5 else -1.0
+        lam = lam_obs + side * elong
+        beta = math.radians(float(rng.uniform(-0.5, 0.5))) * min(1.0, math.degrees(inc) / 5.0)
+        d = np.array([math.cos(beta) * math.cos(lam), math.cos(beta) * math.sin(lam), math.sin(beta)])
+        el, ok = synth.orbits_through(rng, d[None, :], obs, a, e, inc)
+        if not ok[0]:
+            continue
+        if near_earth:
+            r, _, _ = oracle.helio_state(el[0], 0.0, 0.0)
+            if not (0.02 < np.linalg.norm(r - obs) < 0.05):
+                continue
+        return el[0]
+    raise RuntimeError("no reference orbit")
+
+
+def batched(seed=4, n_patches=64, ne_rng=(30, 400), side_rng=(512, 2048), no_rng=(1e4, 1e6), span=30.0,
+            name="batched", n_near=4, width_step=64):
+    """Uneven patches: N_e log-uniform, square sides uniform on a 64-px grid,
+    N_o log-uniform, FP16 images, NEO-to-MBA elements (a 0.8-3.5 AU,
+    e 0-0.6, i 0-30 deg), one injection on each patch's reference orbit at
+    per-image S/N 1; the first n_near patches are near-Earth geometries."""
+    rng = synth.make_rng(seed, 9)
+    patches = []
+    p2 = sum_p2(3.0)
+    for p in range(n_patches):
+        ne = int(round(math.exp(rng.uniform(math.log(ne_rng[0]), math.log(ne_rng[1])))))
+        side = int(rng.integers(side_rng[0] // width_step, side_rng[1] // width_step + 1)) * width_step
+        no = int(round(math.exp(rng.uniform(math.log(no_rng[0]), math.log(no_rng[1])))))
+        prng = synth.make_rng(seed, 10, p)
+        t, t0 = make_epochs(prng, ne, span)
+        lam = float(prng.uniform(0, 2 * math.pi))
+        obs0 = synth.observer_circular([t0], t0, lam)[0]
+        el_ref = reference_orbit_general(prng, obs0, (0.8, 3.5), (0.0, 0.6), (0.0, 30.0), near_earth=p < n_near)
+        exps = make_exposures(prng, t, side, side, 0.2, el_ref, t0, lam, [(0.0, 0.0)], (0.9, 1.1), 3.0)
+        gf = grid_field(exps, t0, lam, side, side, 0.2)
+        inj = [dict(el=[float(v) for v in el_ref], s=1.0, flux=1.0 / math.sqrt(p2), hits=hits_of(el_ref, t0, exps))]
+        patches.append(dict(name=f"{name}_{p}", seed=seed * 1000 + p, t0=t0, dtype="f16", nan_frac=0.0,
+                            exposures=exps, grid_field=gf,
+                            grid=dict(n=no, a=[0.8, 3.5], e=[0.0, 0.6], inc_deg=[0.0, 30.0], cloud=0),
+                            injections=inj))
+    return dict(name=name, seed=seed, patches=patches)
+
+
+def batched_small(seed=5):
+    """Scaled-down batch for full oracle parity: 6 patches, N_e 5-40,
+    sides 128-320, N_o 300-3000, one near-Earth patch."""
+    return batched(seed=seed, n_patches=6, ne_rng=(5, 40), side_rng=(128, 320), no_rng=(300, 3000), span=6.0,
+                   name="batched_small", n_near=1, width_step=64)
+
+
+WORKLOADS = {"tiny": tiny, "survey": survey, "survey_small": survey_small, "batched": batched,
+             "batched_small": batched_small}
 
 
 def main(names):
@@ -180,8 +245,14 @@ def main(names):
         path = os.path.join(OUT, f"geom_{nm}.json")
         with open(path, "w") as f:
             json.dump(g, f, indent=None, separators=(",", ":"))
-        nh = [len(i["hits"]) for i in g["injections"]]
-        print(f"{nm}: {len(g['exposures'])} exposures, {len(g['injections'])} injections, hits {nh} -> {path}")
+        if "patches" in g:
+            ne = [len(p["exposures"]) for p in g["patches"]]
+            nh = [len(p["injections"][0]["hits"]) for p in g["patches"]]
+            print(f"{nm}: {len(ne)} patches, exposures {sum(ne)}, orbits {sum(p['grid']['n'] for p in g['patches'])}, "
+                  f"injection hits {nh} -> {path}")
+        else:
+            nh = [len(i["hits"]) for i in g["injections"]]
+            print(f"{nm}: {len(g['exposures'])} exposures, {len(g['injections'])} injections, hits {nh} -> {path}")
 
 
 if __name__ == "__main__":

@@ -88,3 +88,161 @@ def test_stack_survey_small(small):
     assert ok.all(), f"{(~ok).sum()} orbits outside tolerance, max err {np.max(np.abs(g['snr'] - snr))}"
     want = oracle.topk(g["snr"].astype(np.float64), 100)
     np.testing.assert_array_equal(g["topk_idx"][:g["topk_cnt"]], want)
+
+
+def test_fp16_images_match_oracle_on_the_same_values(small):
+    w = small
+    w16 = synth.Workload(name="f16", exps=w.exps, t0=w.t0, elements=w.elements,
+                         D=[d.astype(np.float16) for d in w.D], V=[v.astype(np.float16) for v in w.V],
+                         injections=w.injections, inj_index=w.inj_index, dtype="f16")
+    g = gpu_run(w16, k=10)
+    snr, flux, nv = oracle.stack(w16.elements, w16.t0, w16.exps, w16.D, w16.V)
+    np.testing.assert_array_equal(g["nv"], nv)
+    assert snr_close(g["snr"], snr).all()
+    # storage error of FP16 images against the FP32 images, reported
+    snr32, _, _ = oracle.stack(w.elements, w.t0, w.exps, w.D, w.V)
+    err = np.abs(g["snr"] - snr32) / np.maximum(1.0, np.abs(snr32))
+    print(f"FP16-image S/N error vs FP32 images: max {err.max():.3g}, p99 {np.percentile(err, 99):.3g}")
+
+
+def test_exposure_order_does_not_matter(small):
+    w = small
+    perm = synth.make_rng(5, 5).permutation(len(w.exps))
+    wp = synth.Workload(name="perm", exps=[w.exps[i] for i in perm], t0=w.t0, elements=w.elements,
+                        D=[w.D[i] for i in perm], V=[w.V[i] for i in perm])
+    ids = np.arange(0, w.elements.shape[0], 97)
+    a = gpu_run(w, ids=ids)
+    b = gpu_run(wp, ids=ids)
+    np.testing.assert_array_equal(a["snr"], b["snr"])
+    np.testing.assert_array_equal(a["nv"], b["nv"])
+    for key in ("ix", "iy", "flags", "px", "py"):
+        np.testing.assert_array_equal(a["dbg"][key][:, perm], b["dbg"][key])
+
+
+def test_deterministic(small):
+    a = gpu_run(small)
+    b = gpu_run(small)
+    np.testing.assert_array_equal(a["snr"], b["snr"])
+    np.testing.assert_array_equal(a["flux"], b["flux"])
+
+
+def test_invalid_orbits_and_empty_sets(tiny):
+    import torch
+    import paper_2503_08854_amd as dt
+    w = tiny
+    el = w.elements[:8].copy()
+    el[1, 0] = np.nan
+    el[3, 1] = 1.2
+    el[5, 0] = -1.0
+    el[6, 1] = 1.0
+    g = gpu_run(synth.Workload(name="bad", exps=w.exps, t0=w.t0, elements=el, D=w.D, V=w.V), k=4)
+    bad = np.array([1, 3, 5, 6])
+    assert np.all(np.isnan(g["snr"][bad])) and np.all(g["nv"][bad] == -1)
+    good = np.setdiff1d(np.arange(8), bad)
+    snr, _, nv = oracle.stack(el[good], w.t0, w.exps, w.D, w.V)
+    assert snr_close(g["snr"][good], snr).all() and np.array_equal(g["nv"][good], nv)
+    assert not np.isin(g["topk_idx"][:g["topk_cnt"]], bad).any()
+    ctx, patch, orb, _, _ = g["_keep"]
+    assert dt.validate_orbits(ctx, orb) == 4
+    # empty orbit set
+    e = dt.OrbitSet(np.zeros((0, 6)), w.t0)
+    snr0, flux0, nv0 = dt.stack(patch, e)
+    idx, val, cnt = dt.topk(ctx, snr0, 5)
+    torch.cuda.synchronize()
+    assert snr0.numel() == 0 and int(cnt.cpu()[0]) == 0 and np.all(idx.cpu().numpy() == -1)
+
+
+def test_tiny_images_and_behind_the_plane():
+    import torch
+    import paper_2503_08854_amd as dt
+    el = np.array([[2.7, 0.1, math.radians(5), 0.4, 1.0, 0.3]])
+    t0 = 0.0
+    robs = synth.observer_circular([0.0], 0.0, 0.2)[0]
+    rho, _, _, _ = oracle.light_time(el[0], t0, 0.0, robs)
+    ra, dec = synth.vec_to_radec(oracle.ecl_to_eq(rho / np.linalg.norm(rho)))
+    s = 0.2 / 3600
+    base = dict(t=0.0, obs=list(robs), crval=[float(ra), float(dec)], cd=[-s, 0, 0, s], fwhm=3.0)
+    exps = [dict(base, crpix=[3.0, 2.0], width=5, height=3),                       # 5x3 image, hit at (2, 1)
+            dict(base, crpix=[1.0, 1.0], width=1, height=1),                       # 1x1 image
+            dict(base, crval=[(float(ra) + 180) % 360, -float(dec)], crpix=[3, 3], width=5, height=5)]  # behind
+    rng = np.random.default_rng(0)
+    D = [rng.standard_normal((x["height"], x["width"])).astype(np.float32) for x in exps]
+    V = [np.full((x["height"], x["width"]), 2.0, np.float32) for x in exps]
+    w = synth.Workload(name="edge", exps=exps, t0=t0, elements=el, D=D, V=V)
+    g = gpu_run(w, ids=[0], k=1)
+    o = oracle.samples(el, t0, exps, D, V)
+    assert list(g["dbg"]["flags"][0]) == list(o["flags"][0] & 7) == [7, 7, 0]
+    snr, flux, nv = oracle.stack(el, t0, exps, D, V)
+    assert snr_close(g["snr"], snr).all() and g["nv"][0] == nv[0] == 2
+
+
+def test_topk_edge_cases():
+    import torch
+    import paper_2503_08854_amd as dt
+    ctx = dt.Context(0)
+    rng = np.random.default_rng(1)
+    for n, k, thr in [(1, 1, -np.inf), (10, 50, -np.inf), (100000, 4096, -np.inf), (100000, 100, 2.5),
+                      (8192 * 3 + 17, 1000, 0.0), (5000, 10, 100.0)]:
+        v = np.round(rng.standard_normal(n), 2).astype(np.float32)
+        v[rng.integers(0, n, max(1, n // 100))] = np.nan
+        t = torch.from_numpy(v).cuda()
+        idx, val, cnt = dt.topk(ctx, t, k, thr)
+        torch.cuda.synchronize()
+        c = int(cnt.cpu()[0])
+        vv = np.where(np.isnan(v), -np.inf, v).astype(np.float64)
+        want = oracle.topk(vv, k, thr if np.isfinite(thr) else -1e300)
+        want = want[~np.isnan(v[want])]
+        np.testing.assert_array_equal(idx.cpu().numpy()[:c], want)
+        np.testing.assert_array_equal(val.cpu().numpy()[:c], v[want])
+        assert np.all(idx.cpu().numpy()[c:] == -1)
+
+
+def test_argument_errors():
+    import torch
+    import paper_2503_08854_amd as dt
+    ctx = dt.Context(0)
+    t = torch.zeros(10, device="cuda")
+    with pytest.raises(dt.DtrackError, match="DT_E_ARG"):
+        dt.topk(ctx, t, 0)
+    with pytest.raises(dt.DtrackError, match="DT_E_ARG"):
+        dt.topk(ctx, t, 5000)
+    x = dict(t=0.0, obs=[1, 0, 0], crval=[0, 0], crpix=[1, 1], cd=[1e-4, 0, 0, 1e-4], width=4, height=4, fwhm=9.0)
+    im = torch.zeros((4, 4), device="cuda")
+    with pytest.raises(dt.DtrackError, match="DT_E_DOMAIN"):
+        dt.Patch(ctx, [x], [im], [im])
+    with pytest.raises(dt.DtrackError, match="DT_E_DOMAIN"):
+        dt.Patch(ctx, [dict(x, fwhm=3.0, cd=[1e-4, 1e-4, 1e-4, 1e-4])], [im], [im])
+    used = ctx.mem_used()
+    ctx.set_mem_limit(used + 200)
+    with pytest.raises(dt.DtrackError, match="DT_E_OOM"):
+        dt.Patch(ctx, [dict(x, fwhm=3.0)], [im], [im])
+    assert ctx.mem_used() == used
+    ctx.set_mem_limit(0)
+    p = dt.Patch(ctx, [dict(x, fwhm=3.0)], [im], [im])
+    p.close()
+    assert ctx.mem_used() == used
+
+
+def test_survey_full_size_sampled():
+    """Bench-size survey (200 x 2048^2, 10^7 orbits) in the launch the bench
+    times; the oracle recomputes a sample of orbits one by one."""
+    import torch
+    geom = synth.load_geometry("survey")
+    w = synth.build_workload(geom, device="cuda")
+    rng = np.random.default_rng(7)
+    n = w.elements.shape[0]
+    dbg_ids = np.sort(rng.choice(n, 200, replace=False))
+    g = gpu_run(w, k=100, thr=5.0, ids=dbg_ids)
+    ids = np.unique(np.r_[rng.choice(n, 3000, replace=False), w.inj_index, g["topk_idx"][:g["topk_cnt"]]])
+    D = [d.cpu().numpy() for d in w.D]
+    V = [v.cpu().numpy() for v in w.V]
+    snr, flux, nv = oracle.stack(w.elements[ids], w.t0, w.exps, D, V)
+    np.testing.assert_array_equal(g["nv"][ids], nv)
+    ok = snr_close(g["snr"][ids], snr)
+    assert ok.all(), f"{(~ok).sum()} sampled orbits outside tolerance"
+    o = oracle.samples(w.elements[dbg_ids], w.t0, w.exps, D, V)
+    nb, nc = compare_samples(g["dbg"], o, w.exps)
+    assert o["bad"] == 0 and nb <= 2
+    # top-k: every reported orbit really has S/N >= 5 and the order is the oracle's on GPU values
+    want = oracle.topk(g["snr"].astype(np.float64), 100, 5.0)
+    np.testing.assert_array_equal(g["topk_idx"][:g["topk_cnt"]], want)
