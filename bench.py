@@ -21,10 +21,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per dense sample of the stack kernel's common
-# path (warm Kepler step, one light-time Newton iteration, projection);
-# an FMA counts 2, add/mul/div/sqrt 1.
-FLOPS_PER_SAMPLE = 214
+# FP64 operations per dense sample on the stack kernel's common path as
+# written (warm Kepler step with short rotation and one Newton step, state,
+# one light-time Newton step, TAN projection, rounding): an FMA counts 2,
+# add / mul / floor / hardware reciprocal or rsqrt estimate 1.
+FLOPS_PER_SAMPLE = 157
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
@@ -75,6 +76,8 @@ def main():
     ap.add_argument("--workload", default="survey")
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the stack shards by orbit and "
@@ -84,6 +87,12 @@ def main():
     import paper_2503_08854_amd as dt
 
     dev = torch.device("cuda:0")
+    if args.probe_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     w = workload(args.workload, dev)
     ctx = dt.Context(0)
     patch = dt.Patch(ctx, w.exps, w.D, w.V)

@@ -190,6 +190,62 @@ dt_status dt_autotune_batched(dt_ctx *ctx, dt_patch *const *patches, const dt_or
  * with DT_E_STATE. */
 dt_status dt_patch_release_images(dt_patch *p);
 
+/* ---- learned proposal (this library's extension, not part of the paper) ----
+ * Orbit-grid cells: a grid stored cell-major, cell c owning orbits
+ * [c * cell_size, (c + 1) * cell_size), its first member the representative.
+ *
+ * Coarse-stacked stamps of n representative orbits (reps, device SoA): for
+ * every offset (dx, dy) in [-10, 10]^2 the constant-flux S/N of the planes
+ * stacked along the representative's track (nearest pixel per exposure, the
+ * same device code as dt_stack) shifted by (dx, dy), i.e. the paper's stack
+ * (Sec. 3) over linear shifts; plus 16 features per cell: stamp max, centre,
+ * mean, std, coverage, offset of the max, fraction of exposures near the
+ * track, normalised a, e, i, max over the central 7x7, zeros.  Outputs
+ * (device, any may be NULL): stamps n x 441 (row dy, column dx) as BF16
+ * and/or FP32, features n x 16 as BF16 and/or FP32.  Synchronises (frees its
+ * track scratch). */
+dt_status dt_cell_stamps(dt_patch *p, const dt_orbits *reps, uint16_t *d_stamps_bf16, float *d_stamps_f32,
+                         uint16_t *d_feats_bf16, float *d_feats_f32);
+
+/* The plain stack (as dt_stack) on the orbits of n_cells selected cells
+ * (device int64 cell ids; negative ids are skipped); outputs are written at
+ * the orbits' indices in the full-grid arrays d_snr / d_flux / d_nvalid
+ * (device, grid->n each), other entries are left untouched. */
+dt_status dt_stack_cells(dt_patch *p, const dt_orbits *grid, const int64_t *d_cells, int64_t n_cells,
+                         int32_t cell_size, float *d_snr, float *d_flux, int32_t *d_nvalid);
+
+/* The scorer's GEMM on its own: C = op(A) op(B) (+ bias[n]) (ReLU if relu),
+ * BF16 inputs, FP32 accumulation and output (device, row-major with leading
+ * dimensions; op(A) is M x K and A is stored K x M when transA; op(B) is
+ * K x N and B is stored N x K when transB).  Synchronises. */
+dt_status dt_gemm_bf16(dt_ctx *ctx, const uint16_t *d_A, int32_t lda, int32_t transA, const uint16_t *d_B,
+                       int32_t ldb, int32_t transB, int32_t M, int32_t N, int32_t K, const float *d_bias,
+                       int32_t relu, float *d_C, int32_t ldc);
+
+/* The cell scorer: CNN on the 21x21 stamp + MLP on the 16 features -> one
+ * logit per cell, trained with binary cross-entropy and Adam on FP32 master
+ * weights; all GEMMs are BF16 MFMA with FP32 accumulation.  Parameters are
+ * one FP32 vector of dt_scorer_num_params() values (layer order w1 b1 ... w7
+ * b7, weights [K, N] row-major).  Inputs are device BF16 arrays: stamps
+ * B x 441, features B x 16; labels FP32 0/1.  1 <= B <= max_batch. */
+typedef struct dt_scorer dt_scorer;
+int64_t dt_scorer_num_params(void);
+/* He-normal weights from a counter-based generator seeded by `seed`, zero biases. */
+dt_status dt_scorer_create(dt_ctx *ctx, int32_t max_batch, uint64_t seed, dt_scorer **out);
+dt_status dt_scorer_destroy(dt_scorer *s);
+dt_status dt_scorer_get_params(dt_scorer *s, float *d_params);
+/* Replace the weights (device FP32) and reset the optimiser state. */
+dt_status dt_scorer_set_params(dt_scorer *s, const float *d_params);
+dt_status dt_scorer_forward(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats, int32_t B,
+                            float *d_logits);
+/* Loss (device float[1], may be NULL) and gradient (device FP32 vector of
+ * num_params values, may be NULL) of the mean BCE at the current weights. */
+dt_status dt_scorer_grad(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats, const float *d_labels,
+                         int32_t B, float *d_loss, float *d_grad);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at learning rate lr. */
+dt_status dt_scorer_train_step(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats,
+                               const float *d_labels, int32_t B, float lr, float *d_loss);
+
 /* Per-sample table for m selected orbits (device int64 ids into `orbits`),
  * computed by the same device code and in the same order as dt_stack.
  * Outputs (device, m x n_exp each, exposures in caller order; any may be NULL):

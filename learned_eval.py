@@ -1,0 +1,175 @@
+"""Training data, training and evaluation of the learned cell proposer.
+
+Used by bench.py (the learned-vs-plain recall and speedup fields) and by the
+GPU tests.  Images and injected sources come from `synth`; every tracking
+step (tracks, planes, stamps, scoring, stacking) runs in the HIP library.
+
+Evaluation protocol: a cell-structured grid (representative + perturbed
+members per cell) on the survey exposures; per realization, fresh noise and
+sources injected on member orbits at the pixel positions the oracle stored.
+The exhaustive stack over every orbit is the judge: an injection counts as
+found by a method if its own orbit's stacked S/N is >= 5 in that method's
+output.  Recall ratio = learned-found / plain-found.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+import synth
+
+
+@dataclass
+class Setup:
+    geom: dict
+    exps: list
+    t0: float
+    el: np.ndarray
+    cell_size: int
+    n_cells: int
+
+
+def load_setup(name: str = "learned") -> Setup:
+    g = synth.load_geometry(name)
+    cg = g["cell_grid"]
+    el = synth.cell_grid(g["grid_field"], cg["cells"], cg["cell_size"], cg["seed"], cg["a"], cg["e"], cg["inc_deg"],
+                         cg["da"], cg["dm"])
+    return Setup(g, synth.exposures_of(g), float(g["t0"]), el, int(cg["cell_size"]), int(cg["cells"]))
+
+
+def _sum_p2(fwhm: float) -> float:
+    sig = fwhm / (2 * math.sqrt(2 * math.log(2)))
+    R = math.ceil(3 * sig)
+    y, x = np.mgrid[-R:R + 1, -R:R + 1]
+    P = np.exp(-(x * x + y * y) / (2 * sig * sig))
+    P /= P.sum()
+    return float((P ** 2).sum())
+
+
+class Bench:
+    """Device state for one setup: images (refilled per realization), patch, grids."""
+
+    def __init__(self, s: Setup, ctx, device="cuda"):
+        import paper_2503_08854_amd as dt
+        self.s = s
+        self.ctx = ctx
+        self.dev = device
+        self.D, self.V = synth.noise_images(s.exps, 1, s.geom.get("nan_frac", 0.0), "f32", device)
+        self.patch = dt.Patch(ctx, s.exps, self.D, self.V)
+        self.grid = dt.OrbitSet(s.el, s.t0, device)
+        self.reps = dt.OrbitSet(s.el[::s.cell_size], s.t0, device)
+
+    def realize(self, seed: int, hits):
+        """Fresh noise (seeded) in place, then sources at hits (e, px, py, flux), then the pre-pass."""
+        D, V = synth.noise_images(self.s.exps, seed, self.s.geom.get("nan_frac", 0.0), "f32", self.dev)
+        for a, b in zip(self.D, D):
+            a.copy_(b)
+        for a, b in zip(self.V, V):
+            a.copy_(b)
+        synth.render_sources_fast(self.D, self.s.exps, hits, self.dev)
+        self.patch.refresh()
+
+
+def training_set(bench: Bench, n_real: int, seed: int, pos_frac: float = 0.5, snr_rng=(3.0, 10.0), log=None):
+    """Method-generated stacks: per realization, sources on random members of
+    pos_frac of the cells (stacked S/N target U(snr_rng) over their hits, the
+    tracks from the stack's own debug table); stamps of every cell; labels
+    1 for injected cells.  Returns device tensors (stamps, feats, labels)."""
+    import torch
+    import paper_2503_08854_amd as dt
+    from paper_2503_08854_amd import proposer
+    s = bench.s
+    p2 = _sum_p2(s.exps[0]["fwhm"])
+    rng = np.random.default_rng(seed)
+    S, F, Y = [], [], []
+    for r in range(n_real):
+        n_pos = int(s.n_cells * pos_frac)
+        cells = rng.choice(s.n_cells, n_pos, replace=False)
+        members = cells * s.cell_size + rng.integers(1, s.cell_size, n_pos)
+        px, py, fl = proposer.member_tracks(bench.patch, bench.grid, members)
+        inside = (fl & 2) != 0
+        nh = inside.sum(1)
+        target = rng.uniform(*snr_rng, n_pos)
+        flux = np.where(nh > 0, target / np.sqrt(np.maximum(nh, 1)) / math.sqrt(p2), 0.0)
+        ii, ee = np.nonzero(inside)
+        hits = np.stack([ee, px[ii, ee], py[ii, ee], flux[ii]], axis=1)
+        bench.realize(seed * 7919 + r, hits)
+        st = dt.cell_stamps(bench.patch, bench.reps, bf16=True, f32=False)
+        lab = np.zeros(s.n_cells, np.float32)
+        lab[cells[nh > 0]] = 1.0
+        S.append(st["stamps_bf16"])
+        F.append(st["feats_bf16"])
+        Y.append(torch.from_numpy(lab).to(bench.dev))
+        if log and (r % 10 == 0 or r == n_real - 1):
+            log(f"training realization {r + 1}/{n_real}: {int(lab.sum())} positive cells")
+    return torch.cat(S), torch.cat(F), torch.cat(Y)
+
+
+def train_scorer(ctx, stamps, feats, labels, epochs: int = 2, batch: int = 512, lr: float = 1e-3, seed: int = 0,
+                 log=None):
+    import paper_2503_08854_amd as dt
+    from paper_2503_08854_amd import proposer
+    sc = dt.Scorer(ctx, max_batch=max(batch, 16384), seed=seed)
+    hist = proposer.train(sc, proposer.minibatches(stamps, feats, labels, batch, epochs, seed), lr=lr, log=log)
+    return sc, hist
+
+
+def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None, log=None):
+    """Recall of plain / learned / coarse-max selection over stored realizations, and timings."""
+    import torch
+    import paper_2503_08854_amd as dt
+    from paper_2503_08854_amd import proposer
+    s = bench.s
+    reals = s.geom["realizations"][:n_real] if n_real else s.geom["realizations"]
+    budget = max(1, int(round(budget_frac * s.n_cells)))
+    n = bench.grid.n
+    out_full = dt.batch_outputs([bench.grid])[0]
+    out_sel = tuple(torch.empty_like(t) for t in out_full)
+    found = dict(plain=0, learned=0, coarse=0)
+    tot = 0
+    t_plain, t_learn = [], []
+    for r, injs in enumerate(reals):
+        hits = np.array([[h[0], h[1], h[2], inj["flux"]] for inj in injs for h in inj["hits"]])
+        bench.realize(10_000 + r, hits)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dt.stack(bench.patch, bench.grid, out_full)
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
+        for t in out_sel:
+            t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, cells = proposer.run_learned(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, scorer, budget,
+                                        out=out_sel)
+        torch.cuda.synchronize()
+        t_learn.append(time.perf_counter() - t0)
+        learned_snr = out_sel[0].cpu().numpy()
+        for t in out_sel:
+            t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
+        proposer.run_coarse(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, budget, out=out_sel)
+        coarse_snr = out_sel[0].cpu().numpy()
+        plain_snr = out_full[0].cpu().numpy()
+        orbits = np.array([inj["orbit"] for inj in injs])
+        pf = plain_snr[orbits] >= 5.0
+        lf = np.nan_to_num(learned_snr[orbits], nan=-np.inf) >= 5.0
+        cf = np.nan_to_num(coarse_snr[orbits], nan=-np.inf) >= 5.0
+        found["plain"] += int(pf.sum())
+        found["learned"] += int((lf & pf).sum())
+        found["coarse"] += int((cf & pf).sum())
+        tot += len(orbits)
+    # steady-state timings: drop the first realization (warm-up)
+    tp = float(np.median(t_plain[1:] if len(t_plain) > 1 else t_plain))
+    tl = float(np.median(t_learn[1:] if len(t_learn) > 1 else t_learn))
+    res = dict(injections=tot, plain_found=found["plain"], learned_found=found["learned"],
+               coarse_found=found["coarse"], budget_cells=budget, cells=s.n_cells, budget_frac=budget / s.n_cells,
+               recall_plain=found["plain"] / max(tot, 1),
+               recall_ratio_learned=found["learned"] / max(found["plain"], 1),
+               recall_ratio_coarse=found["coarse"] / max(found["plain"], 1),
+               t_plain_ms=tp * 1e3, t_learned_ms=tl * 1e3, speedup=tp / tl, orbits=n)
+    if log:
+        log(f"learned eval: {res}")
+    return res

@@ -78,6 +78,18 @@ def lib():
                                  C.POINTER(_P), C.POINTER(_P), C.c_char_p, C.POINTER(DtBatchConfig),
                                  C.POINTER(C.c_double)], C.c_int),
         "dt_patch_release_images": ([_P], C.c_int),
+        "dt_cell_stamps": ([_P, C.POINTER(DtOrbits), _P, _P, _P, _P], C.c_int),
+        "dt_stack_cells": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, C.c_int32, _P, _P, _P], C.c_int),
+        "dt_gemm_bf16": ([_P, _P, C.c_int32, C.c_int32, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                          _P, C.c_int32, _P, C.c_int32], C.c_int),
+        "dt_scorer_num_params": ([], C.c_int64),
+        "dt_scorer_create": ([_P, C.c_int32, C.c_uint64, C.POINTER(_P)], C.c_int),
+        "dt_scorer_destroy": ([_P], C.c_int),
+        "dt_scorer_get_params": ([_P, _P], C.c_int),
+        "dt_scorer_set_params": ([_P, _P], C.c_int),
+        "dt_scorer_forward": ([_P, _P, _P, C.c_int32, _P], C.c_int),
+        "dt_scorer_grad": ([_P, _P, _P, _P, C.c_int32, _P, _P], C.c_int),
+        "dt_scorer_train_step": ([_P, _P, _P, _P, C.c_int32, C.c_float, _P], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -355,3 +367,108 @@ def autotune_batched(ctx: Context, patches, orbit_sets, outs=None, cache_path=No
     _check(lib().dt_autotune_batched(ctx.handle, ph, sets, len(patches), snr, flux, nv,
                                      cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms)))
     return (best.chunk, best.wg_per_cu), ms.value
+
+
+# ------------------------------------------------------------ learned proposal
+def cell_stamps(patch: Patch, reps: OrbitSet, bf16=True, f32=True):
+    """Coarse stamps (n x 21 x 21) and features (n x 16) of representative orbits."""
+    import torch
+    dev = reps.soa.device
+    n = reps.n
+    sb = torch.empty((n, 21, 21), dtype=torch.bfloat16, device=dev) if bf16 else None
+    sf = torch.empty((n, 21, 21), dtype=torch.float32, device=dev) if f32 else None
+    fb = torch.empty((n, 16), dtype=torch.bfloat16, device=dev) if bf16 else None
+    ff = torch.empty((n, 16), dtype=torch.float32, device=dev) if f32 else None
+    _check(lib().dt_cell_stamps(patch.handle, C.byref(reps.struct()), _ptr(sb), _ptr(sf), _ptr(fb), _ptr(ff)))
+    return dict(stamps_bf16=sb, stamps=sf, feats_bf16=fb, feats=ff)
+
+
+def stack_cells(patch: Patch, grid: OrbitSet, cells, cell_size: int, out=None):
+    """The plain stack on the orbits of the selected cells; outputs at the orbits' indices."""
+    import torch
+    dev = grid.soa.device
+    if out is None:
+        out = (torch.full((grid.n,), float("nan"), dtype=torch.float32, device=dev),
+               torch.full((grid.n,), float("nan"), dtype=torch.float32, device=dev),
+               torch.full((grid.n,), -2, dtype=torch.int32, device=dev))
+    cells = torch.as_tensor(cells, dtype=torch.int64).to(dev)
+    _check(lib().dt_stack_cells(patch.handle, C.byref(grid.struct()), _ptr(cells), int(cells.numel()),
+                                int(cell_size), _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
+    return out
+
+
+def gemm_bf16(ctx: Context, A, B, transA=False, transB=False, bias=None, relu=False):
+    """C = op(A) op(B) (+ bias) (ReLU) with the library's BF16 MFMA GEMM (FP32 out)."""
+    import torch
+    A = A.to(torch.bfloat16).contiguous()
+    B = B.to(torch.bfloat16).contiguous()
+    M, K = (A.shape[1], A.shape[0]) if transA else (A.shape[0], A.shape[1])
+    N = B.shape[0] if transB else B.shape[1]
+    Cm = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(lib().dt_gemm_bf16(ctx.handle, _ptr(A), A.shape[1], int(transA), _ptr(B), B.shape[1], int(transB),
+                              M, N, K, _ptr(bias), int(relu), _ptr(Cm), N))
+    return Cm
+
+
+class Scorer:
+    """The learned cell scorer (BF16 MFMA training and inference kernels)."""
+
+    def __init__(self, ctx: Context, max_batch: int = 512, seed: int = 0):
+        self.ctx = ctx
+        self.max_batch = max_batch
+        self._h = _P()
+        _check(lib().dt_scorer_create(ctx.handle, int(max_batch), C.c_uint64(seed), C.byref(self._h)))
+
+    @staticmethod
+    def num_params() -> int:
+        return int(lib().dt_scorer_num_params())
+
+    def params(self):
+        import torch
+        p = torch.empty(self.num_params(), dtype=torch.float32, device="cuda")
+        _check(lib().dt_scorer_get_params(self._h, _ptr(p)))
+        return p
+
+    def set_params(self, p):
+        import torch
+        p = torch.as_tensor(p, dtype=torch.float32).to("cuda").contiguous()
+        _check(lib().dt_scorer_set_params(self._h, _ptr(p)))
+
+    def forward(self, stamps_bf16, feats_bf16):
+        import torch
+        B = stamps_bf16.shape[0]
+        z = torch.empty(B, dtype=torch.float32, device=stamps_bf16.device)
+        for s in range(0, B, self.max_batch):
+            e = min(B, s + self.max_batch)
+            _check(lib().dt_scorer_forward(self._h, _ptr(stamps_bf16[s:e].contiguous()),
+                                           _ptr(feats_bf16[s:e].contiguous()), e - s, _ptr(z[s:])))
+        return z
+
+    def grad(self, stamps_bf16, feats_bf16, labels):
+        import torch
+        g = torch.empty(self.num_params(), dtype=torch.float32, device=stamps_bf16.device)
+        loss = torch.empty(1, dtype=torch.float32, device=stamps_bf16.device)
+        labels = labels.to(torch.float32).contiguous()
+        _check(lib().dt_scorer_grad(self._h, _ptr(stamps_bf16.contiguous()), _ptr(feats_bf16.contiguous()),
+                                    _ptr(labels), int(stamps_bf16.shape[0]), _ptr(loss), _ptr(g)))
+        return loss, g
+
+    def train_step(self, stamps_bf16, feats_bf16, labels, lr: float, loss_out=None):
+        import torch
+        loss = loss_out if loss_out is not None else torch.empty(1, dtype=torch.float32, device=stamps_bf16.device)
+        labels = labels.to(torch.float32).contiguous()
+        _check(lib().dt_scorer_train_step(self._h, _ptr(stamps_bf16.contiguous()), _ptr(feats_bf16.contiguous()),
+                                          _ptr(labels), int(stamps_bf16.shape[0]), float(lr), _ptr(loss)))
+        return loss
+
+    def close(self):
+        if self._h:
+            _check(lib().dt_scorer_destroy(self._h))
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().dt_scorer_destroy(self._h)
+        except Exception:
+            pass

@@ -46,7 +46,8 @@ struct PrepTile {
 };
 
 constexpr int PREP_TX = 256;  // tile width (output pixels) = threads per workgroup
-constexpr int PREP_TY = 64;   // tile height (output rows streamed per workgroup)
+constexpr int PREP_TY = 128;  // tile height (output rows streamed per workgroup)
+constexpr int PREP_DEPTH = 4; // input rows each thread keeps in flight
 constexpr int PREP_RMAX = 12; // largest stamp half-width supported (FWHM <= 8 px gives R = 11)
 
 // Launchers (defined in the .hip files; all enqueue on `s`).
@@ -97,6 +98,45 @@ hipError_t launch_batched(const StackArgs* d_descs, const WorkItem* d_items, int
                           int n_wg, hipStream_t s);
 hipError_t launch_debug(const StackArgs& a, const DebugArgs& d, hipStream_t s);
 hipError_t launch_validate(const StackArgs& a, unsigned long long* d_bad, hipStream_t s);
+
+// BF16 GEMM C = op(A) op(B) (+ bias, ReLU) with FP32 accumulation; op(A) is
+// M x K (A stored [K x M] when transA), op(B) is K x N (B stored [N x K] when
+// transB).  Outputs FP32 (Cf) and/or BF16 (Cb), each with its own leading
+// dimension; d_part is split-K scratch of part_elems floats.
+struct GemmArgs {
+  const uint16_t* A;
+  int lda, transA;
+  const uint16_t* B;
+  int ldb, transB;
+  int M, N, K;
+  const float* bias;
+  int relu;
+  float* Cf;
+  int ldcf;
+  uint16_t* Cb;
+  int ldcb;
+};
+hipError_t launch_gemm_bf16(const GemmArgs& g, float* d_part, size_t part_elems, hipStream_t s);
+hipError_t launch_im2col(const uint16_t* x, int Bn, int H, int W, int C, int stride, int Ho, int Wo, uint16_t* cols,
+                         hipStream_t s);
+hipError_t launch_col2im_mask(const float* dcols, int Bn, int H, int W, int C, int stride, int Ho, int Wo,
+                              const uint16_t* act, uint16_t* dx, float* dx_f, hipStream_t s);
+hipError_t launch_relu_mask(const float* src, int lds, const uint16_t* act, int lda, int M, int N, uint16_t* dst,
+                            float* dst_f, hipStream_t s);
+hipError_t launch_colsum(const float* d, int M, int N, float* out, hipStream_t s);
+hipError_t launch_bce(const float* z, const float* y, int Bn, float* loss, float* dz, uint16_t* dz_bf, hipStream_t s);
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, int64_t n, float lr, int64_t t, uint16_t* w_bf,
+                       hipStream_t s);
+hipError_t launch_cast_bf16(const float* x, int64_t n, uint16_t* y, hipStream_t s);
+hipError_t launch_init_params(float* w, int64_t off, int64_t n, int fan_in, uint64_t seed, int is_bias,
+                              hipStream_t s);
+
+// Coarse stamps (21 x 21) and 16 features per representative orbit; d_track
+// is n x n_exp int2 scratch.  Any output may be null.
+hipError_t launch_cell_stamps(const StackArgs& reps, int2* d_track, uint16_t* st_bf, float* st_f, uint16_t* ft_bf,
+                              float* ft_f, hipStream_t s);
+hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
+                              hipStream_t s);
 
 // Top-k scratch requirement (bytes) for n inputs and k outputs.
 size_t topk_scratch_bytes(int64_t n, int32_t k);

@@ -1,0 +1,63 @@
+// dt_learn.cpp -- C ABI of the learned-proposal path: coarse stamps of
+// orbit-grid cells and the stack restricted to selected cells.
+#include "dt_internal.hpp"
+
+using namespace dtk;
+
+extern "C" {
+
+dt_status dt_cell_stamps(dt_patch* p, const dt_orbits* reps, uint16_t* d_stamps_bf16, float* d_stamps_f32,
+                         uint16_t* d_feats_bf16, float* d_feats_f32) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  dt_status st = check_orbits(reps);
+  if (st != DT_OK) return st;
+  if (!d_stamps_bf16 && !d_stamps_f32 && !d_feats_bf16 && !d_feats_f32) return fail(DT_E_ARG, "no output");
+  DeviceGuard guard(p->ctx->device);
+  dt_ctx* c = p->ctx;
+  const size_t need = sizeof(int2) * (size_t)reps->n * p->n_exp;
+  int2* track = nullptr;
+  st = ctx_alloc(c, (void**)&track, need, "representative tracks");
+  if (st != DT_OK) return st;
+  StackArgs a = stack_args(p, reps);
+  hipError_t e = launch_cell_stamps(a, track, d_stamps_bf16, d_stamps_f32, d_feats_bf16, d_feats_f32, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the track scratch is freed below
+  ctx_free(c, track, need);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "cell stamps");
+}
+
+dt_status dt_gemm_bf16(dt_ctx* c, const uint16_t* d_A, int32_t lda, int32_t transA, const uint16_t* d_B,
+                       int32_t ldb, int32_t transB, int32_t M, int32_t N, int32_t K, const float* d_bias,
+                       int32_t relu, float* d_C, int32_t ldc) {
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  if (M < 0 || N < 0 || K < 1 || !d_A || !d_B || !d_C) return fail(DT_E_ARG, "bad GEMM shape or NULL pointer");
+  if (ldc < N || lda < (transA ? M : K) || ldb < (transB ? K : N)) return fail(DT_E_ARG, "leading dimension too small");
+  DeviceGuard guard(c->device);
+  const size_t part_elems = (size_t)1 << 22;
+  float* part = nullptr;
+  dt_status st = ctx_alloc(c, (void**)&part, sizeof(float) * part_elems, "GEMM split-K scratch");
+  if (st != DT_OK) return st;
+  GemmArgs g{d_A, lda, transA ? 1 : 0, d_B, ldb, transB ? 1 : 0, M, N, K, d_bias, relu ? 1 : 0, d_C, ldc, nullptr, 0};
+  hipError_t e = launch_gemm_bf16(g, part, part_elems, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  ctx_free(c, part, sizeof(float) * part_elems);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "GEMM");
+}
+
+dt_status dt_stack_cells(dt_patch* p, const dt_orbits* grid, const int64_t* d_cells, int64_t n_cells,
+                         int32_t cell_size, float* d_snr, float* d_flux, int32_t* d_nvalid) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  dt_status st = check_orbits(grid);
+  if (st != DT_OK) return st;
+  if (n_cells < 0 || (n_cells > 0 && !d_cells)) return fail(DT_E_ARG, "bad cell list");
+  if (cell_size < 1) return fail(DT_E_ARG, "cell_size must be >= 1");
+  if (n_cells * (int64_t)cell_size >= ((int64_t)1 << 40)) return fail(DT_E_ARG, "too many orbits");
+  DeviceGuard guard(p->ctx->device);
+  StackArgs a = stack_args(p, grid);
+  a.snr = d_snr;
+  a.flux = d_flux;
+  a.nvalid = d_nvalid;
+  hipError_t e = launch_stack_cells(a, d_cells, n_cells, cell_size, p->ctx->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "cell stack launch");
+}
+
+}  // extern "C"

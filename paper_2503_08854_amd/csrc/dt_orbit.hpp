@@ -14,7 +14,7 @@
 //     anomaly: a second-order Taylor start in the mean-anomaly step, then
 //     Newton steps; sin E and cos E are advanced by exact small-angle
 //     rotations (Taylor series whose truncation is below 1e-20) and
-//     re-anchored with a full sincos every ANCHOR solves, so no
+//     re-anchored with a full sincos every ANCHOR exposures, so no
 //     transcendental function is evaluated per sample.
 //   * The light time tau solves c tau = |r(t - tau) - r_obs|.  It is predicted
 //     by linear extrapolation of the previous exposures' light times; the
@@ -32,7 +32,7 @@
 
 namespace dtk {
 
-constexpr int ANCHOR = 32;                 // solves between full sincos re-anchors
+constexpr int ANCHOR = 32;                 // exposures between full sincos re-anchors
 constexpr double LT_LINEAR_MAX = 1.0e-6;   // days; larger light-time corrections re-solve Kepler
 constexpr double ROT_SHORT = 0.005;        // rad; |d| <= this uses the short series
 constexpr double ROT_MAX = 0.05;           // rad; larger steps take the full-sincos path
@@ -79,8 +79,6 @@ struct Orbit {
 struct KepState {
   double E, sE, cE, M;  // E solves E - e sin E = M; (sE, cE) ~ (sin E, cos E)
   double g;             // 1 / (1 - e cE) at the solution
-  int since_anchor;
-  bool have;
 };
 
 __device__ __forceinline__ bool orbit_ok(double a, double e, double inc, double node, double peri, double m0) {
@@ -173,26 +171,24 @@ __device__ inline void kepler_cold(double M, double e, KepState& k) {
   k.cE = c;
   k.M = M;
   k.g = rcp2(fma(-e, c, 1.0));
-  k.since_anchor = 0;
-  k.have = true;
 }
 
-// General warm solve (any step size the rotation series cover).
-__device__ inline void kepler_general(double M, double e, KepState& k) {
-  if (!k.have) {
+// General solve: cold start when `cold`, else warm from the previous solution
+// for any step the rotation series cover (larger steps restart cold); with
+// `anchor` the rotated (sin E, cos E) are replaced by a full sincos.
+__device__ inline void kepler_general(double M, double e, KepState& k, bool anchor, bool cold) {
+  double d = 0.0;
+  if (!cold) {
+    d = (M - k.M) * k.g;
+    d = fma(-0.5 * e * k.sE * k.g, d * d, d);  // E''(M) = -e sin E g^3
+  }
+  if (cold || !(fabs(d) <= ROT_MAX)) {
     kepler_cold(M, e, k);
     return;
   }
-  double d = (M - k.M) * k.g;
-  d = fma(-0.5 * e * k.sE * k.g, d * d, d);  // E''(M) = -e sin E g^3
-  if (!(fabs(d) <= ROT_MAX)) {
-    kepler_cold(M, e, k);
-    return;
-  }
-  if (k.since_anchor >= ANCHOR) {
+  if (anchor) {
     k.E += d;
     sincos(k.E, &k.sE, &k.cE);
-    k.since_anchor = 0;
   } else {
     rot_long(k, d);
   }
@@ -207,26 +203,27 @@ __device__ inline void kepler_general(double M, double e, KepState& k) {
     rot_long(k, dd);
   }
   k.M = M;
-  k.since_anchor++;
 }
 
-// Common-case warm solve: returns false (state untouched) when the step is
-// beyond the short series, a re-anchor is due, or one Newton step does not
-// converge.
-__device__ __forceinline__ bool kepler_fast(double M, double he, double e, KepState& k) {
+// Warm solve, common case: returns false with the state untouched when a
+// re-anchor is due or the step exceeds the short series; otherwise solves
+// (one Newton step normally suffices, more are taken if not).
+__device__ __forceinline__ bool kepler_warm(double M, double he, double e, KepState& k, bool anchor) {
   double d = (M - k.M) * k.g;
   d = fma(he * k.sE * k.g, d * d, d);
-  if (!(fabs(d) <= ROT_SHORT) || k.since_anchor >= ANCHOR) return false;
-  KepState t = k;
-  rot_short(t, d);
-  const double g = rcp1(fma(-e, t.cE, 1.0));
-  const double dd = -fma(-e, t.sE, t.E - M) * g;
-  if (!(fabs(dd) < 1e-8)) return false;
-  rot_tiny(t, dd);
-  t.g = g;
-  t.M = M;
-  t.since_anchor++;
-  k = t;
+  if (anchor || !(fabs(d) <= ROT_SHORT)) return false;
+  rot_short(k, d);
+  for (int it = 0; it < 8; ++it) {
+    const double g = rcp1(fma(-e, k.cE, 1.0));
+    const double dd = -fma(-e, k.sE, k.E - M) * g;
+    k.g = g;
+    if (fabs(dd) < 1e-8) {
+      rot_tiny(k, dd);
+      break;
+    }
+    rot_long(k, dd);
+  }
+  k.M = M;
   return true;
 }
 
@@ -239,58 +236,86 @@ struct SampleOut {
 // Light-time history carried across exposures: last light time and its rate.
 struct LtState {
   double tau, rate;
-  int n;  // samples solved so far
 };
 
-// One (orbit, exposure) sample.  `gap` is t_e minus the epoch of the previous
-// sample of this orbit and inv_gap its reciprocal (0 when gap == 0).
-__device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt, const ExpMeta& x, double epoch,
-                                       double gap, double inv_gap, SampleOut& out) {
-  const double dt = x.t - epoch;
-  double tg = lt.n == 0 ? 0.0 : fma(lt.rate, gap, lt.tau);
-  const double b0 = o.c00 - x.ox, b1 = o.c01 - x.oy, b2 = o.c02 - x.oz;
+// Heliocentric state at t - tg and the one-step light-time correction D.
+struct LtSolve {
   double rho0, rho1, rho2, v0, v1, v2, D, dist;
-  int pass = 0;
-  while (true) {
+};
+
+__device__ __forceinline__ void lt_state(const Orbit& o, const KepState& k, double b0, double b1, double b2,
+                                         double tg, LtSolve& s) {
+  // rho = r(t - tg) - r_obs, v = dr/dt
+  const double ng = o.n * k.g;
+  const double vs = -ng * k.sE, vc = ng * k.cE;
+  s.v0 = fma(vc, o.bQ0, vs * o.aP0);
+  s.v1 = fma(vc, o.bQ1, vs * o.aP1);
+  s.v2 = fma(vc, o.bQ2, vs * o.aP2);
+  s.rho0 = fma(k.cE, o.aP0, fma(k.sE, o.bQ0, b0));
+  s.rho1 = fma(k.cE, o.aP1, fma(k.sE, o.bQ1, b1));
+  s.rho2 = fma(k.cE, o.aP2, fma(k.sE, o.bQ2, b2));
+  double rdist;
+  sqrt_rsq(fma(s.rho0, s.rho0, fma(s.rho1, s.rho1, s.rho2 * s.rho2)), s.dist, rdist);
+  // Newton step on F(D) = c (tg + D) - |rho - D v| from D = 0
+  const double rv = fma(s.rho0, s.v0, fma(s.rho1, s.v1, s.rho2 * s.v2)) * rdist;
+  s.D = fma(-C_AU_DAY, tg, s.dist) * rcp1(C_AU_DAY + rv);
+}
+
+// One (orbit, exposure) sample.  FIRST: the orbit's first exposure (cold
+// Kepler start, no light-time history).  Otherwise `gap` is t_e minus the
+// previous exposure's epoch and inv_gap its reciprocal (0 when gap == 0);
+// `anchor` re-anchors sin E, cos E with a full sincos.
+template <bool FIRST>
+__device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt, const ExpMeta& x, double epoch,
+                                       double gap, double inv_gap, bool anchor, SampleOut& out) {
+  const double dt = x.t - epoch;
+  double tg = FIRST ? 0.0 : fma(lt.rate, gap, lt.tau);
+  const double b0 = o.c00 - x.ox, b1 = o.c01 - x.oy, b2 = o.c02 - x.oz;
+  LtSolve s;
+  for (int pass = 0;; ++pass) {
     const double M = fma(o.n, dt - tg, o.m0);
-    if (!(k.have && kepler_fast(M, o.he, o.e, k))) kepler_general(M, o.e, k);
-    // rho = r(t - tg) - r_obs, v = dr/dt
-    const double ng = o.n * k.g;
-    const double vs = -ng * k.sE, vc = ng * k.cE;
-    v0 = fma(vc, o.bQ0, vs * o.aP0);
-    v1 = fma(vc, o.bQ1, vs * o.aP1);
-    v2 = fma(vc, o.bQ2, vs * o.aP2);
-    rho0 = fma(k.cE, o.aP0, fma(k.sE, o.bQ0, b0));
-    rho1 = fma(k.cE, o.aP1, fma(k.sE, o.bQ1, b1));
-    rho2 = fma(k.cE, o.aP2, fma(k.sE, o.bQ2, b2));
-    double rdist;
-    sqrt_rsq(fma(rho0, rho0, fma(rho1, rho1, rho2 * rho2)), dist, rdist);
-    // Newton step on F(D) = c (tg + D) - |rho - D v| from D = 0
-    const double rv = fma(rho0, v0, fma(rho1, v1, rho2 * v2)) * rdist;
-    D = fma(-C_AU_DAY, tg, dist) * rcp1(C_AU_DAY + rv);
-    if (fabs(D) <= LT_LINEAR_MAX || ++pass == 4) break;
-    tg += D;  // poor prediction: solve the orbit again at the corrected epoch
+    const bool first_try = pass == 0;
+    if (!(!FIRST && first_try && kepler_warm(M, o.he, o.e, k, anchor)))
+      kepler_general(M, o.e, k, first_try && anchor, FIRST && first_try);
+    lt_state(o, k, b0, b1, b2, tg, s);
+    if (fabs(s.D) <= LT_LINEAR_MAX || pass == 3) break;
+    tg += s.D;  // poor prediction: solve the orbit again at the corrected epoch
   }
-  const double q0 = fma(-D, v0, rho0), q1 = fma(-D, v1, rho1), q2 = fma(-D, v2, rho2);
+  const double D = s.D;
+  const double q0 = fma(-D, s.v0, s.rho0), q1 = fma(-D, s.v1, s.rho1), q2 = fma(-D, s.v2, s.rho2);
   const double tau = tg + D;
-  lt.rate = lt.n > 0 ? (tau - lt.tau) * inv_gap : 0.0;
+  lt.rate = FIRST ? 0.0 : (tau - lt.tau) * inv_gap;
   lt.tau = tau;
-  lt.n++;
   out.tau = tau;
   // TAN projection: p = CRPIX - 1 + (A . q) / (c . q)
   const double w = fma(x.cx, q0, fma(x.cy, q1, x.cz * q2));
   const double iw = rcp2(w);
   out.px = fma(fma(x.a0x, q0, fma(x.a0y, q1, x.a0z * q2)), iw, x.px0);
   out.py = fma(fma(x.a1x, q0, fma(x.a1y, q1, x.a1z * q2)), iw, x.py0);
-  out.front = (w > 0.0) && (dist >= 1e-9);
+  out.front = (w > 0.0) && (s.dist >= 1e-9);
   // nearest pixel floor(p + 0.5), clamped into int range before conversion
   const double fx = floor(out.px + 0.5), fy = floor(out.py + 0.5);
   out.ix = (int)fmin(fmax(fx, -2147483648.0), 2147483647.0);
   out.iy = (int)fmin(fmax(fy, -2147483648.0), 2147483647.0);
   out.inside = out.front && (unsigned)out.ix < (unsigned)x.W && (unsigned)out.iy < (unsigned)x.H;
-  if (!out.front) {
-    out.px = out.py = __builtin_nan("");
-    out.ix = out.iy = (int)0x80000000;
+}
+
+// The walk over one orbit's exposures in epoch order: calls f(ex, out) for
+// every exposure after its sample.
+template <typename F>
+__device__ __forceinline__ void walk_orbit(const Orbit& o, const ExpMeta* __restrict__ meta, int n_exp, double epoch,
+                                           F&& f) {
+  KepState k;
+  LtState lt;
+  lt.tau = lt.rate = 0.0;
+  for (int ex = 0; ex < n_exp; ++ex) {
+    const ExpMeta& x = meta[ex];
+    SampleOut so;
+    if (ex == 0)
+      sample<true>(o, k, lt, x, epoch, 0.0, 0.0, false, so);
+    else
+      sample<false>(o, k, lt, x, epoch, x.gap, x.inv_gap, (ex % ANCHOR) == 0, so);
+    f(ex, so);
   }
 }
 

@@ -127,6 +127,7 @@ __global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__
                                                      float2* __restrict__ planes) {
   constexpr int K = 2 * R + 1;
   constexpr int RW = PREP_TX + 2 * R;
+  constexpr int DEPTH = PREP_DEPTH;  // input rows in flight per thread
   __shared__ float2 row[2][RW];
   const PrepTile tl = tiles[blockIdx.x];
   const ExpMeta& m = meta[tl.e];
@@ -155,14 +156,17 @@ __global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__
   const bool in_c = cx >= 0 && cx < W;
   const bool in_h = has_h && hx >= 0 && hx < W;
   const int gx = tl.x0 + tid;  // output column
-  float dc = 0.f, vc = 0.f, dh = 0.f, vh = 0.f;
-  auto fetch = [&](int gy) {
-    dc = vc = dh = vh = __builtin_nanf("");
-    if (gy >= 0 && gy < H) {
-      int64_t base = (int64_t)gy * W;
+  const int rows = PREP_TY + 2 * R;
+  // ring of DEPTH prefetched rows: (D, V) at the centre column and the halo column
+  float rd[DEPTH], rv[DEPTH], hd[DEPTH], hv[DEPTH];
+  auto fetch = [&](int r, float& d, float& v, float& dh, float& vh) {
+    d = v = dh = vh = __builtin_nanf("");
+    const int gy = tl.y0 - R + r;
+    if (r < rows && gy >= 0 && gy < H) {
+      const int64_t base = (int64_t)gy * W;
       if (in_c) {
-        dc = load_px<T>(Dp, base + cx);
-        vc = load_px<T>(Vp, base + cx);
+        d = load_px<T>(Dp, base + cx);
+        v = load_px<T>(Vp, base + cx);
       }
       if (in_h) {
         dh = load_px<T>(Dp, base + hx);
@@ -170,15 +174,23 @@ __global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__
       }
     }
   };
+#pragma unroll
+  for (int q = 0; q < DEPTH; ++q) fetch(q, rd[q], rv[q], hd[q], hv[q]);
   float2 win[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) win[j] = make_float2(0.f, 0.f);
-  fetch(tl.y0 - R);
-  for (int r = 0; r < PREP_TY + 2 * R; ++r) {
+  for (int r = 0; r < rows; ++r) {
     float2* buf = row[r & 1];
-    buf[tid] = weight_pair(dc, vc);
-    if (has_h) buf[PREP_TX + tid] = weight_pair(dh, vh);
-    if (r + 1 < PREP_TY + 2 * R) fetch(tl.y0 - R + r + 1);
+    buf[tid] = weight_pair(rd[0], rv[0]);
+    if (has_h) buf[PREP_TX + tid] = weight_pair(hd[0], hv[0]);
+#pragma unroll
+    for (int q = 0; q < DEPTH - 1; ++q) {
+      rd[q] = rd[q + 1];
+      rv[q] = rv[q + 1];
+      hd[q] = hd[q + 1];
+      hv[q] = hv[q + 1];
+    }
+    fetch(r + DEPTH, rd[DEPTH - 1], rv[DEPTH - 1], hd[DEPTH - 1], hv[DEPTH - 1]);
     __syncthreads();
     float a = 0.f, b = 0.f;
 #pragma unroll

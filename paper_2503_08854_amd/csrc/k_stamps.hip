@@ -1,0 +1,177 @@
+// k_stamps.hip -- coarse-stacked stamps of orbit-grid cells and the stack
+// restricted to selected cells (the learned-proposal path).
+//
+// A cell is a block of `cell_size` consecutive orbits of a grid whose first
+// member is the cell's representative.  The representative's track (nearest
+// pixel per exposure, same device code as the stack) is computed once; the
+// stamp is the constant-flux S/N of the matched-filter planes stacked along
+// that track shifted by every offset (dx, dy) in [-10, 10]^2, so a source on
+// any member whose track stays near a fixed offset from the representative's
+// shows as a peak.  One wavefront per cell; each lane owns 7 of the 441
+// offsets.  Per-cell features summarise the stamp and the cell's elements.
+#include "dt_stack.hpp"
+
+namespace dtk {
+
+constexpr int SH = 10;               // stamp half-width
+constexpr int SW = 2 * SH + 1;       // 21
+constexpr int SP = SW * SW;          // 441
+constexpr int NFEAT = 16;
+
+__global__ __launch_bounds__(256) void k_rep_tracks(StackArgs A, int2* __restrict__ track) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= A.n) return;
+  int2* tr = track + o * A.n_exp;
+  const double a = A.a[o], e = A.e[o], inc = A.inc[o], node = A.node[o], peri = A.peri[o], m0 = A.m0[o];
+  if (!orbit_ok(a, e, inc, node, peri, m0)) {
+    for (int ex = 0; ex < A.n_exp; ++ex) tr[ex] = make_int2((int)0x80000000, (int)0x80000000);
+    return;
+  }
+  Orbit ob;
+  orbit_prep(a, e, inc, node, peri, m0, ob);
+  walk_orbit(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
+    tr[ex] = so.front ? make_int2(so.ix, so.iy) : make_int2((int)0x80000000, (int)0x80000000);
+  });
+}
+
+__device__ __forceinline__ uint16_t f2bf_s(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_cell_stamps(const ExpMeta* __restrict__ meta, int n_exp,
+                                                    const float2* __restrict__ planes, const int2* __restrict__ track,
+                                                    int64_t n_cells, const double* __restrict__ ea,
+                                                    const double* __restrict__ ee, const double* __restrict__ ei,
+                                                    uint16_t* __restrict__ st_bf, float* __restrict__ st_f,
+                                                    uint16_t* __restrict__ ft_bf, float* __restrict__ ft_f) {
+  const int64_t cell = blockIdx.x;
+  if (cell >= n_cells) return;
+  const int lane = threadIdx.x;
+  constexpr int PER = (SP + 63) / 64;  // 7
+  float ps[PER], ph[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) ps[q] = ph[q] = 0.f;
+  int near = 0;
+  const int2* tr = track + cell * n_exp;
+  for (int ex = 0; ex < n_exp; ++ex) {
+    const int2 t = tr[ex];
+    const ExpMeta& x = meta[ex];
+    if (t.x == (int)0x80000000 || t.x < -SH || t.x >= x.W + SH || t.y < -SH || t.y >= x.H + SH) continue;
+    near++;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int j = lane + 64 * q;
+      if (j >= SP) continue;
+      const int X = t.x + j % SW - SH, Y = t.y + j / SW - SH;
+      if (X < 0 || X >= x.W || Y < 0 || Y >= x.H) continue;
+      const float2 v = planes[x.plane_off + (int64_t)Y * x.W + X];
+      if (v.y > 0.f) {
+        ps[q] += v.x;
+        ph[q] += v.y;
+      }
+    }
+  }
+  float smax = -1e30f, ssum = 0.f, ssq = 0.f, cov = 0.f, smax_c = -1e30f, center = 0.f;
+  int amax = 0;
+  for (int q = 0; q < PER; ++q) {
+    const int j = lane + 64 * q;
+    if (j >= SP) continue;
+    const float snr = ph[q] > 0.f ? ps[q] / sqrtf(ph[q]) : 0.f;
+    if (st_bf) st_bf[cell * SP + j] = f2bf_s(snr);
+    if (st_f) st_f[cell * SP + j] = snr;
+    ssum += snr;
+    ssq += snr * snr;
+    cov += ph[q] > 0.f ? 1.f : 0.f;
+    if (snr > smax) {
+      smax = snr;
+      amax = j;
+    }
+    const int dx = j % SW - SH, dy = j / SW - SH;
+    if (abs(dx) <= 3 && abs(dy) <= 3) smax_c = fmaxf(smax_c, snr);
+    if (j == SP / 2) center = snr;
+  }
+  const float gmax = wave_max(smax);
+  // offset of the maximum: the lowest index among lanes holding it
+  const unsigned long long ball = __ballot(smax == gmax);
+  const int src = __ffsll(ball) - 1;
+  const int jmax = __shfl(amax, src, 64);
+  ssum = wave_sum(ssum);
+  ssq = wave_sum(ssq);
+  cov = wave_sum(cov);
+  center = wave_sum(center);
+  smax_c = wave_max(smax_c);
+  if (lane < NFEAT) {
+    const float mean = ssum / SP;
+    const float var = fmaxf(ssq / SP - mean * mean, 0.f);
+    const float dxm = (float)(jmax % SW - SH), dym = (float)(jmax / SW - SH);
+    float f = 0.f;
+    switch (lane) {
+      case 0: f = gmax; break;
+      case 1: f = center; break;
+      case 2: f = mean; break;
+      case 3: f = sqrtf(var); break;
+      case 4: f = cov / SP; break;
+      case 5: f = sqrtf(dxm * dxm + dym * dym) / SH; break;
+      case 6: f = (float)near / (float)max(n_exp, 1); break;
+      case 7: f = (float)((ea[cell] - 2.75) / 0.75); break;
+      case 8: f = (float)(ee[cell] / 0.3); break;
+      case 9: f = (float)(ei[cell] / 0.2618); break;
+      case 10: f = smax_c; break;
+      default: f = 0.f; break;
+    }
+    if (ft_bf) ft_bf[cell * NFEAT + lane] = f2bf_s(f);
+    if (ft_f) ft_f[cell * NFEAT + lane] = f;
+  }
+}
+
+// The plain stack restricted to the orbits of selected cells: orbit
+// cells[c] * cell_size + m for m < cell_size; outputs at the orbit's index.
+__global__ __launch_bounds__(256) void k_stack_cells(StackArgs A, const int64_t* __restrict__ cells, int64_t n_sel,
+                                                     int cell_size) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_sel * cell_size) return;
+  const int64_t c = cells[t / cell_size];
+  if (c < 0) return;
+  const int64_t o = c * cell_size + t % cell_size;
+  if (o >= A.n) return;
+  float snr, flux;
+  int nv;
+  stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
+hipError_t launch_cell_stamps(const StackArgs& reps, int2* d_track, uint16_t* st_bf, float* st_f, uint16_t* ft_bf,
+                              float* ft_f, hipStream_t s) {
+  if (reps.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rep_tracks, dim3((unsigned)((reps.n + 255) / 256)), dim3(256), 0, s, reps, d_track);
+  hipLaunchKernelGGL(k_cell_stamps, dim3((unsigned)reps.n), dim3(64), 0, s, reps.meta, reps.n_exp, reps.planes,
+                     d_track, reps.n, reps.a, reps.e, reps.inc, st_bf, st_f, ft_bf, ft_f);
+  return hipGetLastError();
+}
+
+hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
+                              hipStream_t s) {
+  const int64_t n = n_sel * cell_size;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stack_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d_cells, n_sel,
+                     cell_size);
+  return hipGetLastError();
+}
+
+}  // namespace dtk

@@ -49,11 +49,16 @@ __device__ __forceinline__ void bitonic_desc(uint64_t* s) {
 }
 
 // One tournament round.  Input either S/N values (snr != null, key built from
-// value and index) or keys from the previous round.
+// value and index) or keys from the previous round.  A tile with at most kk
+// non-empty keys is not sorted unless it is the last round: its keys are
+// only compacted (in index order) since a later round sorts them.
 __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __restrict__ snr,
                                                              const uint64_t* __restrict__ keys_in, int64_t n_in,
-                                                             float thr, int kk, uint64_t* __restrict__ keys_out) {
+                                                             float thr, int kk, int final_round,
+                                                             uint64_t* __restrict__ keys_out) {
+  constexpr int PER = TOPK_T / TOPK_THREADS;  // keys owned by a thread
   __shared__ uint64_t s[TOPK_T];
+  __shared__ int scan[TOPK_THREADS];
   const int64_t base = (int64_t)blockIdx.x * TOPK_T;
   for (int j = threadIdx.x; j < TOPK_T; j += TOPK_THREADS) {
     int64_t i = base + j;
@@ -69,8 +74,34 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __rest
     s[j] = key;
   }
   __syncthreads();
+  // count the non-empty keys of this thread's PER contiguous keys, block prefix sum
+  uint64_t mine[PER];
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    mine[q] = s[threadIdx.x * PER + q];
+    cnt += mine[q] != 0;
+  }
+  scan[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 1; off < TOPK_THREADS; off <<= 1) {
+    int v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const int total = scan[TOPK_THREADS - 1];
+  uint64_t* out = keys_out + (int64_t)blockIdx.x * kk;
+  if (!final_round && total <= kk) {
+    int pos = scan[threadIdx.x] - cnt;
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      if (mine[q] != 0) out[pos++] = mine[q];
+    for (int j = total + threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = 0;
+    return;
+  }
   bitonic_desc(s);
-  for (int j = threadIdx.x; j < kk; j += TOPK_THREADS) keys_out[(int64_t)blockIdx.x * kk + j] = s[j];
+  for (int j = threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = s[j];
 }
 
 __global__ void k_topk_emit(const uint64_t* __restrict__ keys, int k, int64_t* __restrict__ idx,
@@ -111,12 +142,12 @@ hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int6
   int cur = 0;
   int64_t n_in = n > 0 ? n : 0;
   hipLaunchKernelGGL(k_topk_round, dim3((unsigned)tiles), dim3(TOPK_THREADS), 0, s, d_snr, nullptr, n_in, thr, k,
-                     buf[cur]);
+                     tiles == 1 ? 1 : 0, buf[cur]);
   n_in = tiles * k;
   while (tiles > 1) {
     tiles = ceil_div(n_in, TOPK_T);
     hipLaunchKernelGGL(k_topk_round, dim3((unsigned)tiles), dim3(TOPK_THREADS), 0, s, nullptr, buf[cur], n_in,
-                       thr, k, buf[cur ^ 1]);
+                       thr, k, tiles == 1 ? 1 : 0, buf[cur ^ 1]);
     cur ^= 1;
     n_in = tiles * k;
   }

@@ -25,7 +25,7 @@ __all__ = [
     "K_OBS", "GOLDEN_DIR", "make_rng", "sorted_epochs", "observer_circular", "unit",
     "tangent_basis", "orbits_through", "Workload", "load_geometry", "exposures_of",
     "candidate_orbits", "perturbed_cloud", "noise_images", "render_sources", "build_workload",
-    "radec_to_vec", "vec_to_radec", "hw_pixscale_deg",
+    "radec_to_vec", "vec_to_radec", "hw_pixscale_deg", "cell_grid", "render_sources_fast",
 ]
 
 # Mean motion (rad/day) of the synthetic observer on a circular 1 AU orbit.
@@ -283,3 +283,59 @@ def build_workload(geom: dict, n_orbits: int = None, seed: int = None, device=No
         render_sources(D, exps, injs, device)
         W.D, W.V = D, V
     return W
+
+
+def cell_grid(gf: dict, n_cells: int, cell_size: int, seed: int, a_rng, e_rng, inc_deg_rng,
+              da: float, dm: float):
+    """Cell-structured orbit grid, cell-major: cell c owns orbits
+    [c * cell_size, (c + 1) * cell_size).  Member 0 is the cell's
+    representative (drawn like the random candidates); the other members
+    perturb its semi-major axis by U(-da, da) AU and its mean anomaly by
+    U(-dm, dm) rad, so their tracks stay near the representative's."""
+    reps = candidate_orbits(gf, n_cells, seed, a_rng, e_rng, inc_deg_rng, stream=77)
+    rng = make_rng(seed, 505)
+    el = np.repeat(reps, cell_size, axis=0)
+    pert = rng.uniform(-1.0, 1.0, (n_cells * cell_size, 2))
+    pert[::cell_size] = 0.0
+    el[:, 0] += da * pert[:, 0]
+    el[:, 5] += dm * pert[:, 1]
+    return el
+
+
+def render_sources_fast(D, exps, hits, device=None):
+    """Vectorised render of many sources: hits is an (n, 4) array of
+    (exposure, px, py, flux); unit-integral point-sampled Gaussians as in
+    render_sources, added per exposure with one scatter-add."""
+    hits = np.asarray(hits, dtype=np.float64).reshape(-1, 4)
+    if hits.size == 0:
+        return D
+    by_e = {}
+    for e in np.unique(hits[:, 0].astype(int)):
+        by_e[e] = hits[hits[:, 0].astype(int) == e]
+    for e, h in by_e.items():
+        x = exps[e]
+        sig = float(x["fwhm"]) / (2.0 * math.sqrt(2.0 * math.log(2.0)))
+        R = int(math.ceil(5.0 * sig))
+        H, W = int(x["height"]), int(x["width"])
+        off = np.arange(-R, R + 1)
+        cx = np.floor(h[:, 1] + 0.5).astype(np.int64)
+        cy = np.floor(h[:, 2] + 0.5).astype(np.int64)
+        X = cx[:, None, None] + off[None, None, :]
+        Y = cy[:, None, None] + off[None, :, None]
+        g = np.exp(-((X - h[:, 1, None, None]) ** 2 + (Y - h[:, 2, None, None]) ** 2) / (2 * sig * sig))
+        g *= (h[:, 3] / (2.0 * math.pi * sig * sig))[:, None, None]
+        X, Y = np.broadcast_to(X, g.shape), np.broadcast_to(Y, g.shape)
+        ok = (X >= 0) & (X < W) & (Y >= 0) & (Y < H)
+        idx = (Y[ok] * W + X[ok]).ravel()
+        val = g[ok].ravel()
+        if device is not None:
+            import torch
+            t = D[e].view(-1)
+            t.index_put_((torch.from_numpy(idx).to(t.device),),
+                         torch.from_numpy(val).to(device=t.device, dtype=torch.float32).to(t.dtype), accumulate=True)
+        else:
+            flat = D[e].reshape(-1)
+            acc = flat.astype(np.float64)
+            np.add.at(acc, idx, val)
+            flat[:] = acc.astype(flat.dtype)
+    return D

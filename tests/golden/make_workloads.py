@@ -235,8 +235,46 @@ def batched_small(seed=5):
                    name="batched_small", n_near=1, width_step=64)
 
 
+def learned(seed=2, n_cells=10000, cell_size=1000, n_real=50, n_inj=20, name="learned", base=None,
+            snr_rng=(4.0, 12.0), da=2e-3, dm=5e-6):
+    """Cell-structured grid on the survey exposures for the learned proposer:
+    n_cells representatives x cell_size members (perturbed a and M0);
+    n_real realizations of n_inj injections, each on a random member of a
+    random cell, flux set for a stacked S/N target U(4, 12) over its hits."""
+    g = base if base is not None else survey(seed=seed)
+    gf = g["grid_field"]
+    grid = dict(cells=n_cells, cell_size=cell_size, a=[2.0, 3.5], e=[0.0, 0.3], inc_deg=[0.0, 15.0], da=da, dm=dm,
+                seed=seed + 100)
+    el = synth.cell_grid(gf, n_cells, cell_size, grid["seed"], grid["a"], grid["e"], grid["inc_deg"], da, dm)
+    rng = synth.make_rng(seed, 66)
+    p2 = sum_p2(3.0)
+    reals = []
+    for r in range(n_real):
+        injs = []
+        while len(injs) < n_inj:
+            c = int(rng.integers(0, n_cells))
+            m = int(rng.integers(1, cell_size))
+            o = c * cell_size + m
+            hits = hits_of(el[o], g["t0"], g["exposures"])
+            if len(hits) < 2:
+                continue
+            target = float(rng.uniform(*snr_rng))
+            s = target / math.sqrt(len(hits))
+            injs.append(dict(orbit=o, cell=c, el=[float(v) for v in el[o]], s=s, flux=s / math.sqrt(p2),
+                             target=target, hits=hits))
+        reals.append(injs)
+    return dict(name=name, seed=seed, t0=g["t0"], dtype="f32", nan_frac=g["nan_frac"], exposures=g["exposures"],
+                grid_field=gf, cell_grid=grid, realizations=reals)
+
+
+def learned_small(seed=3):
+    """Scaled-down learned-proposer geometry on the small survey."""
+    return learned(seed=seed, n_cells=200, cell_size=50, n_real=4, n_inj=10, name="learned_small",
+                   base=survey_small(seed=seed))
+
+
 WORKLOADS = {"tiny": tiny, "survey": survey, "survey_small": survey_small, "batched": batched,
-             "batched_small": batched_small}
+             "batched_small": batched_small, "learned": learned, "learned_small": learned_small}
 
 
 def main(names):
@@ -245,7 +283,11 @@ def main(names):
         path = os.path.join(OUT, f"geom_{nm}.json")
         with open(path, "w") as f:
             json.dump(g, f, indent=None, separators=(",", ":"))
-        if "patches" in g:
+        if "realizations" in g:
+            nh = [len(i["hits"]) for r in g["realizations"] for i in r]
+            print(f"{nm}: {g['cell_grid']['cells']} cells x {g['cell_grid']['cell_size']}, "
+                  f"{len(g['realizations'])} realizations, mean hits {np.mean(nh):.1f} -> {path}")
+        elif "patches" in g:
             ne = [len(p["exposures"]) for p in g["patches"]]
             nh = [len(p["injections"][0]["hits"]) for p in g["patches"]]
             print(f"{nm}: {len(ne)} patches, exposures {sum(ne)}, orbits {sum(p['grid']['n'] for p in g['patches'])}, "
