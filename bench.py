@@ -68,6 +68,78 @@ def cpu_baseline(w, gpu_snr, seconds=12.0):
                 snr_max_err=float(err.max()))
 
 
+def bench_batched(dev, steps=5):
+    """The batched-patches workload: 64 uneven FP16 patches, one graph-captured
+    persistent launch (stack + per-patch top-k) after autotuning."""
+    import tempfile
+    import torch
+    import paper_2503_08854_amd as dt
+    import synth
+    geom = synth.load_geometry("batched")
+    ctx = dt.Context(0)
+    patches, sets = [], []
+    t = time.time()
+    n_px = 0
+    for pg in geom["patches"]:
+        w = synth.build_workload(pg, device=dev)
+        p = dt.Patch(ctx, w.exps, w.D, w.V)
+        torch.cuda.synchronize()
+        p.release_images()           # planes stay; the FP16 images are freed
+        n_px += sum(x["width"] * x["height"] for x in w.exps)
+        patches.append(p)
+        sets.append(dt.OrbitSet(w.elements, w.t0, dev))
+        del w
+    torch.cuda.synchronize()
+    log(f"batched: {len(patches)} patches built ({time.time() - t:.1f} s)")
+    outs = dt.batch_outputs(sets)
+    with tempfile.TemporaryDirectory() as td:
+        cfg, ms = dt.autotune_batched(ctx, patches, sets, outs, cache_path=os.path.join(td, "tune.txt"))
+    log(f"batched: autotuned chunk={cfg[0]} wg_per_cu={cfg[1]} ({ms:.2f} ms)")
+    outs, tk = dt.stack_batched(ctx, patches, sets, outs=outs, k=10, threshold=5.0, cfg=cfg)  # capture
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        dt.stack_batched(ctx, patches, sets, outs=outs, k=10, threshold=5.0, cfg=cfg, topk_out=tk)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    samples = sum(o.n * p.n_exp for o, p in zip(sets, patches))
+    res = dict(workload=f"batched: {len(patches)} patches, {sum(p.n_exp for p in patches)} FP16 exposures, "
+                        f"{sum(o.n for o in sets)} orbits", samples=samples, ms_per_step=ms_step,
+               samples_per_s=samples / (ms_step * 1e-3), cfg={"chunk": cfg[0], "wg_per_cu": cfg[1]}, pixels=n_px)
+    for p in patches:
+        p.close()
+    ctx.close()
+    return res
+
+
+def bench_learned(dev, n_train=100, n_eval=50, budget=0.05):
+    """Learned vs plain recall at S/N >= 5 and speedup on the cell-structured survey grid."""
+    import torch
+    import learned_eval as le
+    import paper_2503_08854_amd as dt
+    t = time.time()
+    s = le.load_setup("learned")
+    ctx = dt.Context(0)
+    b = le.Bench(s, ctx, dev)
+    X, F, Y = le.training_set(b, n_train, seed=1)
+    torch.cuda.synchronize()
+    log(f"learned: {X.shape[0]} method-generated stacks ({time.time() - t:.1f} s)")
+    t = time.time()
+    sc, hist = le.train_scorer(ctx, X, F, Y, epochs=2, batch=512, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.time() - t
+    log(f"learned: trained in {t_train:.1f} s, loss {hist[0][1]:.3f} -> {hist[-1][1]:.3f}")
+    del X, F, Y
+    res = le.evaluate(b, sc, budget_frac=budget, n_real=n_eval)
+    res.update(train_stacks=n_train * s.n_cells, train_s=t_train, loss_first=hist[0][1], loss_last=hist[-1][1])
+    sc.close()
+    b.patch.close()
+    ctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +150,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe-copy", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the stack shards by orbit and "
@@ -166,9 +240,21 @@ def main():
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(w, snr)
         log(f"cpu baseline: {rec['cpu_baseline']['value']:.3g} samples/s on {rec['cpu_baseline']['cores']} threads")
-    print(json.dumps(rec), flush=True)
     patch.close()
     ctx.close()
+    del w, orb, out, patch
+    torch.cuda.empty_cache()
+    if not args.skip_batched:
+        rec["batched"] = bench_batched(dev)
+        log(f"batched: {rec['batched']['samples_per_s']:.3g} samples/s")
+        torch.cuda.empty_cache()
+    if not args.skip_learned:
+        rec["learned"] = bench_learned(dev)
+        L = rec["learned"]
+        log(f"learned: recall ratio {L['recall_ratio_learned']:.3f} (coarse {L['recall_ratio_coarse']:.3f}), "
+            f"speedup {L['speedup']:.1f}x")
+        torch.cuda.empty_cache()
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -190,6 +190,42 @@ dt_status dt_autotune_batched(dt_ctx *ctx, dt_patch *const *patches, const dt_or
  * with DT_E_STATE. */
 dt_status dt_patch_release_images(dt_patch *p);
 
+/* Candidate-orbit distribution for on-device sampling (Algorithm 1,
+ * GenerateOrbits): a, e, i uniform in their ranges (AU, -, radians); a line
+ * of sight uniform over the tangent-plane rectangle |xi| <= half_w,
+ * |eta| <= half_h (radians) about the unit vector `center` with axes
+ * `east`, `north` (ecliptic); the orbit's geometric heliocentric position at
+ * `epoch` lies on that line of sight from `obs_xyz_au`, with a uniform true
+ * anomaly and nodal branch; the inclination is raised to |latitude| when the
+ * line of sight needs it.  Orbit k is a pure function of (seed, k). */
+typedef struct {
+  double epoch;
+  double obs_xyz_au[3];
+  double center[3], east[3], north[3];
+  double half_w, half_h;
+  double a_range[2], e_range[2], inc_range[2];
+  uint64_t seed;
+} dt_orbit_sampler;
+
+/* Orbits first .. first + n - 1 of the sampler into device SoA arrays
+ * (an index whose 16 attempts all miss gets a = NaN). */
+dt_status dt_generate_orbits(dt_ctx *ctx, const dt_orbit_sampler *sampler, int64_t first, int64_t n, double *d_a,
+                             double *d_e, double *d_inc, double *d_node, double *d_peri, double *d_m0);
+/* dt_stack on orbits first .. first + n - 1 of the sampler, generated in
+ * registers (no element arrays); outputs (device, n each) as dt_stack. */
+dt_status dt_stack_generated(dt_patch *p, const dt_orbit_sampler *sampler, int64_t first, int64_t n, float *d_snr,
+                             float *d_flux, int32_t *d_nvalid);
+
+/* Per-intersection outlier trimming of candidate orbits (Sec. 5.2.3): for
+ * each of m orbits (device int64 ids into `orbits`), the valid samples'
+ * (psi_e, phi_e) from the stack's device code are clipped two-sided at
+ * |psi_e - F phi_e| / sqrt(phi_e) > kappa about F = sum psi / sum phi of the
+ * kept samples, refitting until the kept set is stable or after max_iter
+ * rounds.  Outputs (device, m each, may be NULL): S/N, flux and the kept
+ * count after trimming.  Patches of at most 512 exposures.  Synchronises. */
+dt_status dt_clip_candidates(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, int64_t m,
+                             double kappa, int32_t max_iter, float *d_snr, float *d_flux, int32_t *d_nkept);
+
 /* ---- learned proposal (this library's extension, not part of the paper) ----
  * Orbit-grid cells: a grid stored cell-major, cell c owning orbits
  * [c * cell_size, (c + 1) * cell_size), its first member the representative.

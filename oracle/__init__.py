@@ -14,6 +14,7 @@ Functions and the passages they follow (Golovich et al. 2025):
   stamp, planes         -- Sec. 3 FindLocalSignal, Gaussian matched filter
   stack                 -- Sec. 3 constant-flux combination of signals
   topk                  -- Algorithm 1 FindSignificantResults
+  sigma_clip            -- Sec. 5.2.3 outlier trimming of intersections
   linear_stack          -- Sec. 1 classic (linear) digital tracking
 """
 from __future__ import annotations
@@ -79,6 +80,7 @@ def lib():
         L.or_max_threads.restype = C.c_int
         L.or_linear_stack.argtypes = [C.c_int, dp, C.c_double, C.c_int, dp, C.c_void_p, C.c_void_p,
                                       C.c_int, dp, dp, ip]
+        L.or_sigma_clip.argtypes = [C.c_int, dp, dp, C.c_double, C.c_int, dp, dp, ip, C.POINTER(C.c_uint8)]
         L.or_topk.argtypes = [C.c_int64, dp, C.c_int64, C.c_double, C.POINTER(C.c_int64)]
         L.or_topk.restype = C.c_int64
         _lib = L
@@ -266,3 +268,16 @@ def topk(snr, k, thr=-np.inf):
     out = np.zeros(max(int(k), 1), np.int64)
     cnt = lib().or_topk(s.shape[0], ps, int(k), float(thr), out.ctypes.data_as(C.POINTER(C.c_int64)))
     return out[:cnt]
+
+
+def sigma_clip(psi, phi, kappa=3.0, max_iter=10):
+    """Outlier trimming of one orbit's intersections: (S/N, flux, n_kept, kept mask)."""
+    ps, pp = _d(psi)
+    ph, pph = _d(phi)
+    n = ps.shape[0]
+    kept = np.zeros(max(n, 1), np.uint8)
+    snr, flux = C.c_double(), C.c_double()
+    nk = C.c_int32()
+    lib().or_sigma_clip(n, pp, pph, float(kappa), int(max_iter), C.byref(snr), C.byref(flux), C.byref(nk),
+                        kept.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return snr.value, flux.value, nk.value, kept[:n].astype(bool)

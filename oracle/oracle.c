@@ -400,3 +400,38 @@ int64_t or_topk(int64_t n, const double *snr, int64_t k, double thr, int64_t *id
   free(ids);
   return cnt;
 }
+
+/* ---- per-intersection outlier trimming (Sec. 5.2.3) ------------------------ */
+/* Under the constant-flux model every valid intersection e gives an
+ * independent flux estimate psi_e / phi_e with variance 1 / phi_e.  Reading:
+ * two-sided sigma clipping of the residuals chi_e = (psi_e - F phi_e) /
+ * sqrt(phi_e) about the weighted mean F = sum psi / sum phi of the kept
+ * samples; samples with |chi_e| > kappa are dropped and the fit repeated
+ * until the kept set does not change or after max_iter rounds.  Returns the
+ * S/N, flux and count of the kept set (n_valid entries of psi/phi, phi > 0). */
+void or_sigma_clip(int n, const double *psi, const double *phi, double kappa, int max_iter,
+                   double *snr, double *flux, int32_t *n_kept, uint8_t *kept) {
+  for (int i = 0; i < n; ++i) kept[i] = phi[i] > 0.0;
+  for (int it = 0; it < max_iter; ++it) {
+    double P = 0.0, F = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (kept[i]) { P += psi[i]; F += phi[i]; }
+    if (!(F > 0.0)) break;
+    double mu = P / F;
+    int changed = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!(phi[i] > 0.0)) continue;
+      double chi = (psi[i] - mu * phi[i]) / sqrt(phi[i]);
+      uint8_t k = fabs(chi) <= kappa;
+      if (k != kept[i]) { kept[i] = k; changed = 1; }
+    }
+    if (!changed) break;
+  }
+  double P = 0.0, F = 0.0;
+  int m = 0;
+  for (int i = 0; i < n; ++i)
+    if (kept[i]) { P += psi[i]; F += phi[i]; m++; }
+  *snr = F > 0.0 ? P / sqrt(F) : 0.0;
+  *flux = F > 0.0 ? P / F : 0.0;
+  *n_kept = m;
+}

@@ -42,6 +42,13 @@ class DtBatchConfig(C.Structure):
 
 DT_BATCH_PREPASS, DT_BATCH_EAGER = 1, 2
 
+
+class DtOrbitSampler(C.Structure):
+    _fields_ = [("epoch", C.c_double), ("obs_xyz_au", C.c_double * 3), ("center", C.c_double * 3),
+                ("east", C.c_double * 3), ("north", C.c_double * 3), ("half_w", C.c_double),
+                ("half_h", C.c_double), ("a_range", C.c_double * 2), ("e_range", C.c_double * 2),
+                ("inc_range", C.c_double * 2), ("seed", C.c_uint64)]
+
 _lib = None
 _P = C.c_void_p
 
@@ -79,6 +86,11 @@ def lib():
                                  C.POINTER(C.c_double)], C.c_int),
         "dt_patch_release_images": ([_P], C.c_int),
         "dt_cell_stamps": ([_P, C.POINTER(DtOrbits), _P, _P, _P, _P], C.c_int),
+        "dt_generate_orbits": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P],
+                               C.c_int),
+        "dt_stack_generated": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P], C.c_int),
+        "dt_clip_candidates": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, C.c_double, C.c_int32, _P, _P, _P],
+                               C.c_int),
         "dt_stack_cells": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, C.c_int32, _P, _P, _P], C.c_int),
         "dt_gemm_bf16": ([_P, _P, C.c_int32, C.c_int32, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                           _P, C.c_int32, _P, C.c_int32], C.c_int),
@@ -367,6 +379,56 @@ def autotune_batched(ctx: Context, patches, orbit_sets, outs=None, cache_path=No
     _check(lib().dt_autotune_batched(ctx.handle, ph, sets, len(patches), snr, flux, nv,
                                      cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms)))
     return (best.chunk, best.wg_per_cu), ms.value
+
+
+def orbit_sampler(field: dict, epoch: float, a_range, e_range, inc_deg_range, seed: int):
+    """A dt_orbit_sampler from a grid-field description (center/east/north/obs/half_w/half_h)."""
+    import math
+    s = DtOrbitSampler()
+    s.epoch = float(epoch)
+    s.obs_xyz_au[:] = [float(v) for v in field["obs"]]
+    s.center[:] = [float(v) for v in field["center"]]
+    s.east[:] = [float(v) for v in field["east"]]
+    s.north[:] = [float(v) for v in field["north"]]
+    s.half_w, s.half_h = float(field["half_w"]), float(field["half_h"])
+    s.a_range[:] = [float(v) for v in a_range]
+    s.e_range[:] = [float(v) for v in e_range]
+    s.inc_range[:] = [math.radians(float(v)) for v in inc_deg_range]
+    s.seed = int(seed)
+    return s
+
+
+def generate_orbits(ctx: Context, sampler, first: int, n: int):
+    """(n, 6) device tensor of sampled elements (also usable as OrbitSet)."""
+    import torch
+    soa = torch.empty((6, n), dtype=torch.float64, device="cuda")
+    ptrs = [soa[k].data_ptr() if n else None for k in range(6)]
+    _check(lib().dt_generate_orbits(ctx.handle, C.byref(sampler), int(first), int(n), *ptrs))
+    return soa.t()
+
+
+def stack_generated(patch: Patch, sampler, first: int, n: int):
+    import torch
+    snr = torch.empty(n, dtype=torch.float32, device=patch.device)
+    flux = torch.empty(n, dtype=torch.float32, device=patch.device)
+    nv = torch.empty(n, dtype=torch.int32, device=patch.device)
+    _check(lib().dt_stack_generated(patch.handle, C.byref(sampler), int(first), int(n), _ptr(snr), _ptr(flux),
+                                    _ptr(nv)))
+    return snr, flux, nv
+
+
+def clip_candidates(patch: Patch, orbits: OrbitSet, ids, kappa: float = 3.0, max_iter: int = 10):
+    """Outlier trimming of candidate orbits: (S/N, flux, kept count) after sigma clipping."""
+    import torch
+    dev = orbits.soa.device
+    ids = torch.as_tensor(ids, dtype=torch.int64).to(dev)
+    m = int(ids.numel())
+    snr = torch.empty(m, dtype=torch.float32, device=dev)
+    flux = torch.empty(m, dtype=torch.float32, device=dev)
+    nk = torch.empty(m, dtype=torch.int32, device=dev)
+    _check(lib().dt_clip_candidates(patch.handle, C.byref(orbits.struct()), _ptr(ids), m, float(kappa),
+                                    int(max_iter), _ptr(snr), _ptr(flux), _ptr(nk)))
+    return snr, flux, nk
 
 
 # ------------------------------------------------------------ learned proposal

@@ -138,6 +138,15 @@ hipError_t launch_cell_stamps(const StackArgs& reps, int2* d_track, uint16_t* st
 hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
                               hipStream_t s);
 
+// Outlier trimming of m candidate orbits (n_exp <= 512); d_buf is m x n_exp float2 scratch.
+hipError_t launch_clip(const StackArgs& a, const int64_t* d_ids, int64_t m, double kappa, int max_iter,
+                       float2* d_buf, float* snr, float* flux, int32_t* nkept, hipStream_t s);
+
+// Device-side orbit sampling (GenerateOrbits) and generate-and-stack.
+hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, double* a, double* e, double* inc,
+                           double* node, double* peri, double* m0, hipStream_t s);
+hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s);
+
 // Top-k scratch requirement (bytes) for n inputs and k outputs.
 size_t topk_scratch_bytes(int64_t n, int32_t k);
 hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,

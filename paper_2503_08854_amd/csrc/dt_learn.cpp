@@ -43,6 +43,78 @@ dt_status dt_gemm_bf16(dt_ctx* c, const uint16_t* d_A, int32_t lda, int32_t tran
   return e == hipSuccess ? DT_OK : hip_fail(e, "GEMM");
 }
 
+dt_status dt_clip_candidates(dt_patch* p, const dt_orbits* orbits, const int64_t* d_ids, int64_t m, double kappa,
+                             int32_t max_iter, float* d_snr, float* d_flux, int32_t* d_nkept) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  dt_status st = check_orbits(orbits);
+  if (st != DT_OK) return st;
+  if (m < 0 || (m > 0 && !d_ids)) return fail(DT_E_ARG, "bad id array");
+  if (!(kappa > 0.0) || max_iter < 1) return fail(DT_E_ARG, "kappa must be > 0 and max_iter >= 1");
+  if (p->n_exp > 512) return fail(DT_E_ARG, "outlier trimming supports at most 512 exposures per patch");
+  if (m == 0) return DT_OK;
+  DeviceGuard guard(p->ctx->device);
+  dt_ctx* c = p->ctx;
+  const size_t need = sizeof(float2) * (size_t)m * p->n_exp;
+  float2* buf = nullptr;
+  st = ctx_alloc(c, (void**)&buf, need, "outlier-trimming scratch");
+  if (st != DT_OK) return st;
+  StackArgs a = stack_args(p, orbits);
+  hipError_t e = launch_clip(a, d_ids, m, kappa, max_iter, buf, d_snr, d_flux, d_nkept, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the scratch is freed below
+  ctx_free(c, buf, need);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "outlier trimming");
+}
+
+namespace {
+dt_status check_sampler(const dt_orbit_sampler* S) {
+  if (!S) return fail(DT_E_ARG, "sampler is NULL");
+  const double* v[] = {&S->epoch, S->obs_xyz_au, S->center, S->east, S->north, &S->half_w, &S->half_h,
+                       S->a_range, S->e_range, S->inc_range};
+  const int nv[] = {1, 3, 3, 3, 3, 1, 1, 2, 2, 2};
+  for (int k = 0; k < 10; ++k)
+    for (int j = 0; j < nv[k]; ++j)
+      if (!std::isfinite(v[k][j])) return fail(DT_E_DOMAIN, "sampler has a non-finite value");
+  if (!(S->a_range[0] > 0.0 && S->a_range[1] >= S->a_range[0])) return fail(DT_E_DOMAIN, "bad a range");
+  if (!(S->e_range[0] >= 0.0 && S->e_range[1] >= S->e_range[0] && S->e_range[1] < 1.0))
+    return fail(DT_E_DOMAIN, "bad e range");
+  if (!(S->inc_range[0] >= 0.0 && S->inc_range[1] >= S->inc_range[0])) return fail(DT_E_DOMAIN, "bad i range");
+  if (!(S->half_w > 0.0 && S->half_h > 0.0)) return fail(DT_E_DOMAIN, "field half-widths must be > 0");
+  return DT_OK;
+}
+}  // namespace
+
+dt_status dt_generate_orbits(dt_ctx* c, const dt_orbit_sampler* S, int64_t first, int64_t n, double* d_a,
+                             double* d_e, double* d_inc, double* d_node, double* d_peri, double* d_m0) {
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  dt_status st = check_sampler(S);
+  if (st != DT_OK) return st;
+  if (first < 0 || n < 0) return fail(DT_E_ARG, "first and n must be >= 0");
+  if (n > 0 && (!d_a || !d_e || !d_inc || !d_node || !d_peri || !d_m0)) return fail(DT_E_ARG, "NULL output");
+  DeviceGuard guard(c->device);
+  hipError_t e = launch_generate(*S, first, n, d_a, d_e, d_inc, d_node, d_peri, d_m0, c->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "orbit generation");
+}
+
+dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t first, int64_t n, float* d_snr,
+                             float* d_flux, int32_t* d_nvalid) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  dt_status st = check_sampler(S);
+  if (st != DT_OK) return st;
+  if (first < 0 || n < 0 || n >= ((int64_t)1 << 32)) return fail(DT_E_ARG, "bad first / n");
+  DeviceGuard guard(p->ctx->device);
+  StackArgs a{};
+  a.meta = p->d_meta;
+  a.n_exp = p->n_exp;
+  a.planes = p->d_planes;
+  a.n = n;
+  a.epoch = S->epoch;
+  a.snr = d_snr;
+  a.flux = d_flux;
+  a.nvalid = d_nvalid;
+  hipError_t e = launch_stack_generated(a, *S, first, p->ctx->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "generate-and-stack launch");
+}
+
 dt_status dt_stack_cells(dt_patch* p, const dt_orbits* grid, const int64_t* d_cells, int64_t n_cells,
                          int32_t cell_size, float* d_snr, float* d_flux, int32_t* d_nvalid) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");

@@ -1,0 +1,146 @@
+// k_generate.hip -- GenerateOrbits of Algorithm 1 on the device: candidate
+// orbits sampled from given distributions, as a pure function of (seed,
+// orbit index), so every orbit of a dense grid is defined without a host
+// upload and can be generated inside the stack itself.
+//
+// Sampling (this library's reading of "sample orbital parameters from
+// specified distributions", Sec. 3): (a, e, i) uniform in their ranges; a
+// line of sight uniform over a tangent-plane rectangle around a field
+// centre; the orbit is placed so that its geometric heliocentric position at
+// the epoch lies on that line of sight: with a true anomaly nu drawn uniform,
+// the distance r = a (1 - e^2) / (1 + e cos nu) fixes the point where the
+// line of sight meets the sphere |X| = r; the orbit plane through X with the
+// drawn inclination (raised to |latitude| when needed, on a random nodal
+// branch) gives the node and the argument of perihelion, and nu gives M0.
+// Up to 16 attempts per index (counter-based draws); an index whose attempts
+// all miss gets a = NaN, which the stack reports as outside the domain.
+#include "dt_stack.hpp"
+
+namespace dtk {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+// uniform in [0, 1) with 53 random bits, from (seed, index, attempt, draw)
+__device__ __forceinline__ double u01(uint64_t seed, uint64_t idx, int att, int k) {
+  const uint64_t h = mix64(seed ^ mix64(idx * 0x100000001B3ull + (uint64_t)(att * 16 + k)));
+  return (double)(h >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__device__ inline bool gen_orbit(const dt_orbit_sampler& S, uint64_t idx, double el[6]) {
+  for (int att = 0; att < 16; ++att) {
+    const double xi = (2.0 * u01(S.seed, idx, att, 0) - 1.0) * S.half_w;
+    const double eta = (2.0 * u01(S.seed, idx, att, 1) - 1.0) * S.half_h;
+    double d0 = S.center[0] + xi * S.east[0] + eta * S.north[0];
+    double d1 = S.center[1] + xi * S.east[1] + eta * S.north[1];
+    double d2 = S.center[2] + xi * S.east[2] + eta * S.north[2];
+    const double dn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    d0 *= dn;
+    d1 *= dn;
+    d2 *= dn;
+    const double a = S.a_range[0] + (S.a_range[1] - S.a_range[0]) * u01(S.seed, idx, att, 2);
+    const double e = S.e_range[0] + (S.e_range[1] - S.e_range[0]) * u01(S.seed, idx, att, 3);
+    double inc = S.inc_range[0] + (S.inc_range[1] - S.inc_range[0]) * u01(S.seed, idx, att, 4);
+    const double nu = PI * (2.0 * u01(S.seed, idx, att, 5) - 1.0);
+    const bool branch = u01(S.seed, idx, att, 6) < 0.5;
+    const double r = a * (1.0 - e * e) / (1.0 + e * cos(nu));
+    const double* O = S.obs_xyz_au;
+    const double ou = d0 * O[0] + d1 * O[1] + d2 * O[2];
+    const double disc = ou * ou - (O[0] * O[0] + O[1] * O[1] + O[2] * O[2]) + r * r;
+    if (!(disc > 0.0)) continue;
+    const double s = -ou + sqrt(disc);
+    if (!(s > 0.0)) continue;
+    const double X0 = O[0] + s * d0, X1 = O[1] + s * d1, X2 = O[2] + s * d2;
+    const double xn = sqrt(X0 * X0 + X1 * X1 + X2 * X2);
+    const double beta = asin(fmin(fmax(X2 / xn, -1.0), 1.0));
+    const double lam = atan2(X1, X0);
+    inc = fmax(inc, fabs(beta) * (1.0 + 1e-9) + 1e-12);
+    double u = asin(fmin(fmax(sin(beta) / sin(inc), -1.0), 1.0));
+    if (branch) u = PI - u;
+    const double node = lam - atan2(cos(inc) * sin(u), cos(u));
+    const double peri = u - nu;
+    const double E = 2.0 * atan2(sqrt(1.0 - e) * sin(0.5 * nu), sqrt(1.0 + e) * cos(0.5 * nu));
+    const double M0 = E - e * sin(E);
+    const double tp = 2.0 * PI;
+    el[0] = a;
+    el[1] = e;
+    el[2] = inc;
+    el[3] = node - tp * floor(node / tp);
+    el[4] = peri - tp * floor(peri / tp);
+    el[5] = (M0 + PI) - tp * floor((M0 + PI) / tp) - PI;
+    return true;
+  }
+  el[0] = __builtin_nan("");
+  el[1] = el[2] = el[3] = el[4] = el[5] = 0.0;
+  return false;
+}
+
+__global__ __launch_bounds__(256) void k_generate(dt_orbit_sampler S, int64_t first, int64_t n, double* __restrict__ a,
+                                                  double* __restrict__ e, double* __restrict__ inc,
+                                                  double* __restrict__ node, double* __restrict__ peri,
+                                                  double* __restrict__ m0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double el[6];
+  gen_orbit(S, (uint64_t)(first + i), el);
+  a[i] = el[0];
+  e[i] = el[1];
+  inc[i] = el[2];
+  node[i] = el[3];
+  peri[i] = el[4];
+  m0[i] = el[5];
+}
+
+// Generate-and-stack: orbit first + i is generated in registers and stacked;
+// no element arrays exist.
+__global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_sampler S, int64_t first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double el[6];
+  float snr = __builtin_nanf(""), flux = __builtin_nanf("");
+  int nv = -1;
+  if (gen_orbit(S, (uint64_t)(first + i), el) && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5])) {
+    Orbit ob;
+    orbit_prep(el[0], el[1], el[2], el[3], el[4], el[5], ob);
+    Kahan ps, ph;
+    ps.init();
+    ph.init();
+    int cnt = 0;
+    walk_orbit(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
+      if (!so.inside) return;
+      const ExpMeta& x = A.meta[ex];
+      const float2 v = A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix];
+      if (v.y > 0.f) {
+        ps.add(v.x);
+        ph.add(v.y);
+        cnt++;
+      }
+    });
+    const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
+    snr = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
+    flux = Phi > 0.f ? Psi / Phi : 0.f;
+    nv = cnt;
+  }
+  if (A.snr) A.snr[i] = snr;
+  if (A.flux) A.flux[i] = flux;
+  if (A.nvalid) A.nvalid[i] = nv;
+}
+
+hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, double* a, double* e, double* inc,
+                           double* node, double* peri, double* m0, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_generate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S, first, n, a, e, inc, node,
+                     peri, m0);
+  return hipGetLastError();
+}
+
+hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stack_generated, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
+  return hipGetLastError();
+}
+
+}  // namespace dtk
