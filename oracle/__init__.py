@@ -81,6 +81,8 @@ def lib():
         L.or_linear_stack.argtypes = [C.c_int, dp, C.c_double, C.c_int, dp, C.c_void_p, C.c_void_p,
                                       C.c_int, dp, dp, ip]
         L.or_sigma_clip.argtypes = [C.c_int, dp, dp, C.c_double, C.c_int, dp, dp, ip, C.POINTER(C.c_uint8)]
+        L.or_mad_noise.argtypes = [C.c_int64, C.POINTER(C.c_float), C.c_double, C.c_int, dp,
+                                   C.POINTER(C.c_int64), ip]
         L.or_topk.argtypes = [C.c_int64, dp, C.c_int64, C.c_double, C.POINTER(C.c_int64)]
         L.or_topk.restype = C.c_int64
         _lib = L
@@ -281,3 +283,12 @@ def sigma_clip(psi, phi, kappa=3.0, max_iter=10):
     lib().or_sigma_clip(n, pp, pph, float(kappa), int(max_iter), C.byref(snr), C.byref(flux), C.byref(nk),
                         kept.ctypes.data_as(C.POINTER(C.c_uint8)))
     return snr.value, flux.value, nk.value, kept[:n].astype(bool)
+
+
+def mad_noise(image, kappa=3.0, max_iter=10):
+    """Iterated-MAD noise of one image (float32 values): (sigma, n_used, iterations)."""
+    x = np.ascontiguousarray(np.asarray(image, dtype=np.float32).ravel())
+    sig, nu, it = C.c_double(), C.c_int64(), C.c_int32()
+    lib().or_mad_noise(x.size, x.ctypes.data_as(C.POINTER(C.c_float)), float(kappa), int(max_iter), C.byref(sig),
+                       C.byref(nu), C.byref(it))
+    return sig.value, nu.value, it.value

@@ -435,3 +435,69 @@ void or_sigma_clip(int n, const double *psi, const double *phi, double kappa, in
   *flux = F > 0.0 ? P / F : 0.0;
   *n_kept = m;
 }
+
+/* ------------------------------------------------------------------------
+ * Per-image noise by an iterated median absolute deviation (Sec. 3: the
+ * pixel noise variance of each image comes from an iterative MAD).  Reading:
+ * S = the finite pixels; repeat at most max_iter times:
+ *   m = median(S), MAD = median{|x - m| : x in S}, sigma = 1.4826 MAD,
+ *   S' = {finite x : |x - m| <= kappa sigma}; stop when S' == S, else S = S'.
+ * The median of an even count is the mean of the two middle values.  The
+ * result is the sigma of the last computed step, the size of the set it came
+ * from, and the number of steps.  An image with no finite pixel gives NaN.
+ * ------------------------------------------------------------------------ */
+static int or_cmp_double(const void *pa, const void *pb) {
+  double a = *(const double *)pa, b = *(const double *)pb;
+  return (a > b) - (a < b);
+}
+
+static double or_median(double *v, int64_t n) {
+  qsort(v, (size_t)n, sizeof(double), or_cmp_double);
+  return 0.5 * (v[(n - 1) / 2] + v[n / 2]);
+}
+
+void or_mad_noise(int64_t n, const float *x, double kappa, int max_iter, double *sigma_out, int64_t *n_used,
+                  int32_t *iters) {
+  uint8_t *kept = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+  double *buf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    kept[i] = isfinite(x[i]) ? 1 : 0;
+    cnt += kept[i];
+  }
+  double sigma = NAN;
+  int64_t used = 0;
+  int it = 0;
+  while (it < max_iter && cnt > 0) {
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i)
+      if (kept[i]) buf[m++] = (double)x[i];
+    double med = or_median(buf, m);
+    m = 0;
+    for (int64_t i = 0; i < n; ++i)
+      if (kept[i]) buf[m++] = fabs((double)x[i] - med);
+    double mad = or_median(buf, m);
+    sigma = 1.4826 * mad;
+    used = m;
+    it++;
+    double thr = kappa * sigma;
+    int changed = 0;
+    int64_t c2 = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      if (!isfinite(x[i])) continue;
+      uint8_t k = fabs((double)x[i] - med) <= thr;
+      if (k != kept[i]) {
+        kept[i] = k;
+        changed = 1;
+      }
+      c2 += k;
+    }
+    cnt = c2;
+    if (!changed) break;
+  }
+  *sigma_out = sigma;
+  *n_used = used;
+  *iters = it;
+  free(kept);
+  free(buf);
+}

@@ -533,3 +533,74 @@ def test_generated_distributions_and_counter_purity():
     np.testing.assert_array_equal(G.generate(S, 1000, 50), el[1000:1050])
     el2 = G.generate(dict(S, seed=4), 0, 50)
     assert not np.allclose(el2, el[:50])
+
+
+# ----------------------------------------------- per-image noise (iterated MAD)
+def _mad_fixed_point(kappa=3.0):
+    # sigma_hat / sigma for Gaussian data: the clip at kappa*sigma_hat truncates
+    # the distribution; the MAD q of the truncated normal solves
+    # 2 Phi(q) - 1 = (2 Phi(c) - 1) / 2 with c = kappa sigma_hat / sigma.
+    def f(s):
+        c = kappa * s
+        q = stats.norm.ppf(0.5 + (2 * stats.norm.cdf(c) - 1) / 4)
+        return 1.4826 * q - s
+    return optimize.brentq(f, 0.5, 1.5)
+
+
+def test_mad_noise_gaussian_quantiles_reach_truncated_fixed_point():
+    # deterministic "perfect" Gaussian sample: the quantiles themselves
+    n = 400_000
+    z = stats.norm.ppf((np.arange(n) + 0.5) / n)
+    rng = np.random.default_rng(1)
+    x = (2.5 * z)[rng.permutation(n)].astype(np.float32)
+    sig, used, it = oracle.mad_noise(x)
+    assert it >= 2
+    assert abs(sig / 2.5 - _mad_fixed_point()) < 2e-5
+    # a single MAD step without clipping would give 1.0 (0.3 % higher)
+    assert abs(sig / 2.5 - 1.0) > 2e-3
+    assert abs(used - n * (2 * stats.norm.cdf(3 * sig / 2.5) - 1)) < 3
+
+
+def test_mad_noise_brute_force_small_sets():
+    rng = np.random.default_rng(5)
+    for trial in range(200):
+        n = int(rng.integers(1, 40))
+        x = rng.normal(0, 1, n).astype(np.float32)
+        if trial % 3 == 0:
+            x[rng.random(n) < 0.2] = np.nan
+        if trial % 5 == 0:
+            x[rng.random(n) < 0.1] = 50.0
+        # library median over the finite values, clip, repeat
+        s = np.isfinite(x)
+        want, steps = float("nan"), 0
+        for _ in range(10):
+            if not s.any():
+                break
+            v = x[s].astype(np.float64)
+            m = float(np.median(v))
+            want = 1.4826 * float(np.median(np.abs(v - m)))
+            steps += 1
+            s2 = np.isfinite(x) & (np.abs(x.astype(np.float64) - m) <= 3.0 * want)
+            if np.array_equal(s2, s):
+                break
+            s = s2
+        sig, used, it = oracle.mad_noise(x)
+        assert it == steps
+        if math.isnan(want):
+            assert math.isnan(sig)
+        else:
+            assert sig == want
+
+
+def test_mad_noise_outliers_scale_and_degenerate_cases():
+    n = 100_000
+    z = stats.norm.ppf((np.arange(n) + 0.5) / n).astype(np.float32)
+    clean, _, _ = oracle.mad_noise(z)
+    dirty = np.concatenate([z, np.full(n // 100, 1e3, np.float32), np.full(n // 200, np.nan, np.float32)])
+    sig, used, _ = oracle.mad_noise(dirty)
+    assert abs(sig - clean) < 1e-3 * clean and used <= n
+    s2, _, _ = oracle.mad_noise(4 * z)   # power-of-two scaling is exact
+    assert s2 == 4 * clean
+    assert oracle.mad_noise(np.full(50, 7.0, np.float32))[0] == 0.0
+    assert math.isnan(oracle.mad_noise(np.full(5, np.nan, np.float32))[0])
+    assert oracle.mad_noise(np.zeros(0, np.float32))[2] == 0
