@@ -103,10 +103,32 @@ dt_status dt_ctx_destroy(dt_ctx *ctx);
  * the unit-sum Gaussian P (sigma = FWHM / 2.3548, R = ceil(3 sigma)), pixels
  * off the image, non-finite or with V <= 0 carrying no weight.  By linearity
  * this equals the filter applied at the nearest pixel of any intersection.
- * Image buffers are borrowed until dt_patch_destroy; the planes are owned. */
+ * Image buffers are borrowed until dt_patch_destroy; the planes are owned.
+ * d_var == NULL: no variance planes; every pre-pass (here and in
+ * dt_patch_refresh) first estimates each image's noise sigma by the iterated
+ * MAD of dt_image_noise (kappa = 3, at most 10 steps) and uses V = sigma^2
+ * (rounded to FP32) at every pixel. */
 dt_status dt_patch_create(dt_ctx *ctx, const dt_exposure *exps, int32_t n_exp,
                           const void *const *d_flux, const void *const *d_var, dt_dtype dtype,
                           dt_patch **out);
+/* Per-image noise by an iterated median absolute deviation (Sec. 3: the
+ * pixel noise of each image comes from an iterative MAD).  For each image i
+ * (host arrays: d_images[i] a device pointer to n_pixels[i] values of
+ * `dtype`): S = its finite pixels; repeat at most max_iter times: m =
+ * median(S), sigma = 1.4826 median{|x - m| : x in S}, S' = {finite x :
+ * |x - m| <= kappa sigma}; stop when S' == S, else S = S'.  The median of an
+ * even count is the mean of the two middle values; m, |x - m|, sigma and the
+ * clip test are FP64, so the result is exact.  Outputs (device, n_img each,
+ * any may be NULL): sigma of the last step (NaN for an image with no finite
+ * pixel), the size of the set it came from, the number of steps.  Enqueued
+ * on the context stream; the host arrays are not read after return. */
+dt_status dt_image_noise(dt_ctx *ctx, int32_t n_img, const void *const *d_images, const int64_t *n_pixels,
+                         dt_dtype dtype, double kappa, int32_t max_iter, double *d_sigma, int64_t *d_n_used,
+                         int32_t *d_iters);
+/* Copy the noise sigma of a patch created without variance planes (device,
+ * n_exp doubles, caller order; valid after the pre-pass has run). */
+dt_status dt_patch_noise(dt_patch *p, double *d_sigma);
+
 /* Re-run the pre-pass after the caller changed the borrowed images in place. */
 dt_status dt_patch_refresh(dt_patch *p);
 dt_status dt_patch_destroy(dt_patch *p);

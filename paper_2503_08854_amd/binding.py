@@ -86,6 +86,8 @@ def lib():
                                  C.POINTER(C.c_double)], C.c_int),
         "dt_patch_release_images": ([_P], C.c_int),
         "dt_cell_stamps": ([_P, C.POINTER(DtOrbits), _P, _P, _P, _P], C.c_int),
+        "dt_image_noise": ([_P, C.c_int32, _P, _P, C.c_int, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
+        "dt_patch_noise": ([_P, _P], C.c_int),
         "dt_generate_orbits": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P],
                                C.c_int),
         "dt_stack_generated": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P], C.c_int),
@@ -184,14 +186,17 @@ class Context:
 class Patch:
     """Exposures + borrowed device images; owns the matched-filter planes."""
 
-    def __init__(self, ctx: Context, exps, flux, var):
+    def __init__(self, ctx: Context, exps, flux, var=None):
+        """var=None: no variance planes; each pre-pass estimates every image's
+        noise by the iterated MAD and uses V = sigma^2 (see noise())."""
         import torch
-        if len(exps) != len(flux) or len(exps) != len(var):
+        if len(exps) != len(flux) or (var is not None and len(exps) != len(var)):
             raise ValueError("exposures, flux and variance lists differ in length")
         dt = flux[0].dtype
         if dt not in (torch.float32, torch.float16):
             raise TypeError("images must be float32 or float16")
-        for x, d, v in zip(exps, flux, var):
+        for k, (x, d) in enumerate(zip(exps, flux)):
+            v = var[k] if var is not None else d
             if d.dtype != dt or v.dtype != dt or not d.is_cuda or not v.is_cuda:
                 raise TypeError("all images must be CUDA tensors of one dtype")
             if tuple(d.shape) != (int(x["height"]), int(x["width"])) or d.shape != v.shape:
@@ -202,11 +207,11 @@ class Patch:
         self.exps = list(exps)
         self.device = flux[0].device
         self._flux = list(flux)   # borrowed: keep alive
-        self._var = list(var)
+        self._var = list(var) if var is not None else None
         n = len(exps)
         xs = exposure_struct(exps)
         fp = (_P * n)(*[d.data_ptr() for d in flux])
-        vp = (_P * n)(*[v.data_ptr() for v in var])
+        vp = (_P * n)(*[v.data_ptr() for v in var]) if var is not None else None
         self._h = _P()
         _check(lib().dt_patch_create(ctx.handle, xs, n, fp, vp, DT_F32 if dt == torch.float32 else DT_F16,
                                      C.byref(self._h)))
@@ -227,6 +232,13 @@ class Patch:
         x = self.exps[e]
         out = torch.empty((int(x["height"]), int(x["width"]), 2), dtype=torch.float32, device=self.device)
         _check(lib().dt_patch_plane(self._h, int(e), _ptr(out)))
+        return out
+
+    def noise(self):
+        """Per-exposure noise sigma (FP64, caller order) of a patch without variance planes."""
+        import torch
+        out = torch.empty(self.n_exp, dtype=torch.float64, device=self.device)
+        _check(lib().dt_patch_noise(self._h, _ptr(out)))
         return out
 
     def release_images(self):
@@ -379,6 +391,27 @@ def autotune_batched(ctx: Context, patches, orbit_sets, outs=None, cache_path=No
     _check(lib().dt_autotune_batched(ctx.handle, ph, sets, len(patches), snr, flux, nv,
                                      cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms)))
     return (best.chunk, best.wg_per_cu), ms.value
+
+
+def image_noise(ctx: Context, images, kappa: float = 3.0, max_iter: int = 10):
+    """Iterated-MAD noise of device images: (sigma f64, n_used i64, steps i32) device tensors."""
+    import torch
+    n = len(images)
+    if n == 0:
+        e = torch.empty(0, device="cuda")
+        return e.double(), e.long(), e.int()
+    dt = images[0].dtype
+    if dt not in (torch.float32, torch.float16) or any(x.dtype != dt or not x.is_contiguous() for x in images):
+        raise TypeError("images must be contiguous float32 or float16 tensors of one dtype")
+    dev = images[0].device
+    sig = torch.empty(n, dtype=torch.float64, device=dev)
+    used = torch.empty(n, dtype=torch.int64, device=dev)
+    it = torch.empty(n, dtype=torch.int32, device=dev)
+    ptrs = (_P * n)(*[x.data_ptr() if x.numel() else None for x in images])
+    npx = (C.c_int64 * n)(*[x.numel() for x in images])
+    _check(lib().dt_image_noise(ctx.handle, n, ptrs, npx, DT_F32 if dt == torch.float32 else DT_F16, float(kappa),
+                                int(max_iter), _ptr(sig), _ptr(used), _ptr(it)))
+    return sig, used, it
 
 
 def orbit_sampler(field: dict, epoch: float, a_range, e_range, inc_deg_range, seed: int):

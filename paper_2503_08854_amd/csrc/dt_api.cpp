@@ -75,6 +75,12 @@ void patch_free(dt_patch* p) {
   ctx_free(c, p->d_tiles, sizeof(PrepTile) * p->n_tiles);
   ctx_free(c, p->d_flux, sizeof(void*) * p->n_exp);
   ctx_free(c, p->d_var, sizeof(void*) * p->n_exp);
+  ctx_free(c, p->d_npix, sizeof(int64_t) * p->n_exp);
+  ctx_free(c, p->d_sigma, sizeof(double) * p->n_exp);
+  ctx_free(c, p->noise_ws, noise_scratch_bytes(p->n_exp));
+  p->d_npix = nullptr;
+  p->d_sigma = nullptr;
+  p->noise_ws = nullptr;
   p->d_meta = nullptr;
   p->d_planes = nullptr;
   p->d_tiles = nullptr;
@@ -113,6 +119,11 @@ StackArgs stack_args(const dt_patch* p, const dt_orbits* o) {
 
 dt_status run_prepass(dt_patch* p, hipStream_t s) {
   if (p->images_released) return fail(DT_E_STATE, "the patch's images were released; the pre-pass cannot run");
+  if (p->est_noise) {
+    hipError_t e = launch_noise(p->d_flux, p->d_npix, p->max_pix, p->n_exp, p->dtype, NOISE_KAPPA, NOISE_MAX_ITER,
+                                p->noise_ws, p->d_sigma, nullptr, nullptr, p->d_meta, s);
+    if (e != hipSuccess) return hip_fail(e, "noise estimate launch");
+  }
   hipError_t e = launch_prepass(p->d_meta, p->d_tiles, p->group_off.data(), p->group_R.data(),
                                 (int)p->group_R.size(), p->d_flux, p->d_var, p->dtype, p->d_planes, s);
   if (e != hipSuccess) return hip_fail(e, "matched-filter pre-pass launch");
@@ -174,6 +185,7 @@ dt_status dt_ctx_destroy(dt_ctx* c) {
   batch_graph_drop(c);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   ctx_free(c, c->topk_scratch, c->topk_bytes);
+  ctx_free(c, c->noise_ws, c->noise_bytes);
   ctx_free(c, c->d_counter, sizeof(unsigned long long));
   c->alive = false;
   delete c;
@@ -185,18 +197,19 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
   if (!out) return fail(DT_E_ARG, "out is NULL");
   *out = nullptr;
   if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
-  if (n_exp <= 0 || !exps || !d_flux || !d_var) return fail(DT_E_ARG, "need n_exp > 0 and non-NULL arrays");
+  if (n_exp <= 0 || !exps || !d_flux) return fail(DT_E_ARG, "need n_exp > 0 and non-NULL arrays");
   if (dtype != DT_F32 && dtype != DT_F16) return fail(DT_E_ARG, "unknown dtype %d", (int)dtype);
   for (int i = 0; i < n_exp; ++i) {
     dt_status st = check_exposure(exps[i], i);
     if (st != DT_OK) return st;
-    if (!d_flux[i] || !d_var[i]) return fail(DT_E_ARG, "exposure %d: image pointer is NULL", i);
+    if (!d_flux[i] || (d_var && !d_var[i])) return fail(DT_E_ARG, "exposure %d: image pointer is NULL", i);
   }
   DeviceGuard g(c->device);
   dt_patch* p = new dt_patch();
   p->ctx = c;
   p->n_exp = n_exp;
   p->dtype = dtype;
+  p->est_noise = d_var == nullptr;
   p->order.resize(n_exp);
   std::iota(p->order.begin(), p->order.end(), 0);
   std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) { return exps[a].t < exps[b].t; });
@@ -255,6 +268,17 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
   A((void**)&p->d_tiles, sizeof(PrepTile) * p->n_tiles, "pre-pass tiles");
   A((void**)&p->d_flux, sizeof(void*) * n_exp, "flux pointers");
   A((void**)&p->d_var, sizeof(void*) * n_exp, "variance pointers");
+  std::vector<int64_t> npix(n_exp);
+  for (int i = 0; i < n_exp; ++i) {
+    npix[i] = (int64_t)exps[i].width * exps[i].height;
+    p->max_pix = std::max(p->max_pix, npix[i]);
+  }
+  std::vector<const void*> no_var(n_exp, nullptr);
+  if (p->est_noise) {
+    A((void**)&p->d_npix, sizeof(int64_t) * n_exp, "noise pixel counts");
+    A((void**)&p->d_sigma, sizeof(double) * n_exp, "noise estimates");
+    A(&p->noise_ws, noise_scratch_bytes(n_exp), "noise selection state");
+  }
   A((void**)&d_exps, sizeof(dt_exposure) * n_exp, "staging");
   A((void**)&d_off, sizeof(int64_t) * n_exp, "staging");
   A((void**)&d_src, sizeof(int32_t) * n_exp, "staging");
@@ -282,7 +306,8 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
   H2D(d_rad, rad.data(), sizeof(int32_t) * n_exp);
   H2D(p->d_tiles, tiles.data(), sizeof(PrepTile) * p->n_tiles);
   H2D(p->d_flux, d_flux, sizeof(void*) * n_exp);
-  H2D(p->d_var, d_var, sizeof(void*) * n_exp);
+  H2D(p->d_var, d_var ? (const void*)d_var : (const void*)no_var.data(), sizeof(void*) * n_exp);
+  if (p->est_noise) H2D(p->d_npix, npix.data(), sizeof(int64_t) * n_exp);
   if (e == hipSuccess) e = launch_exposure_prep(d_exps, d_off, d_src, d_rad, n_exp, p->d_meta, s);
   // staging buffers must outlive the async copies
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -307,6 +332,58 @@ dt_status dt_patch_refresh(dt_patch* p) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
   DeviceGuard g(p->ctx->device);
   return run_prepass(p, p->ctx->stream);
+}
+
+dt_status dt_patch_noise(dt_patch* p, double* d_sigma) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  if (!p->est_noise) return fail(DT_E_STATE, "the patch was created with variance planes");
+  if (!d_sigma) return fail(DT_E_ARG, "d_sigma is NULL");
+  DeviceGuard g(p->ctx->device);
+  hipError_t e = hipMemcpyAsync(d_sigma, p->d_sigma, sizeof(double) * p->n_exp, hipMemcpyDeviceToDevice,
+                                p->ctx->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "noise copy");
+}
+
+dt_status dt_image_noise(dt_ctx* c, int32_t n_img, const void* const* d_images, const int64_t* n_pixels,
+                         dt_dtype dtype, double kappa, int32_t max_iter, double* d_sigma, int64_t* d_n_used,
+                         int32_t* d_iters) {
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  if (n_img < 0) return fail(DT_E_ARG, "n_img < 0");
+  if (n_img == 0) return DT_OK;
+  if (!d_images || !n_pixels) return fail(DT_E_ARG, "NULL image or size array");
+  if (dtype != DT_F32 && dtype != DT_F16) return fail(DT_E_ARG, "unknown dtype %d", (int)dtype);
+  if (!(kappa > 0.0) || !std::isfinite(kappa)) return fail(DT_E_DOMAIN, "kappa must be finite and > 0");
+  if (max_iter < 1 || max_iter > 100) return fail(DT_E_ARG, "max_iter must be in [1, 100]");
+  int64_t max_pix = 0;
+  for (int i = 0; i < n_img; ++i) {
+    if (n_pixels[i] < 0) return fail(DT_E_ARG, "image %d: negative pixel count", i);
+    if (n_pixels[i] > 0 && !d_images[i]) return fail(DT_E_ARG, "image %d: NULL pointer", i);
+    max_pix = std::max(max_pix, n_pixels[i]);
+  }
+  DeviceGuard g(c->device);
+  const size_t stage = ((sizeof(void*) + sizeof(int64_t)) * (size_t)n_img + 255) / 256 * 256;
+  const size_t need = stage + noise_scratch_bytes(n_img);
+  if (need > c->noise_bytes) {
+    (void)hipStreamSynchronize(c->stream);
+    ctx_free(c, c->noise_ws, c->noise_bytes);
+    c->noise_ws = nullptr;
+    c->noise_bytes = 0;
+    dt_status st = ctx_alloc(c, &c->noise_ws, need, "noise scratch");
+    if (st != DT_OK) return st;
+    c->noise_bytes = need;
+  }
+  char* ws = static_cast<char*>(c->noise_ws);
+  const void** d_ptrs = reinterpret_cast<const void**>(ws);
+  int64_t* d_npix = reinterpret_cast<int64_t*>(ws + sizeof(void*) * (size_t)n_img);
+  hipError_t e = hipMemcpyAsync(d_ptrs, d_images, sizeof(void*) * n_img, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_npix, n_pixels, sizeof(int64_t) * n_img, hipMemcpyHostToDevice, c->stream);
+  // the caller's host arrays must not be read after return
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess)
+    e = launch_noise(d_ptrs, d_npix, max_pix, n_img, dtype, kappa, max_iter, ws + stage, d_sigma, d_n_used, d_iters,
+                     nullptr, c->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "noise estimate");
 }
 
 dt_status dt_patch_release_images(dt_patch* p) {

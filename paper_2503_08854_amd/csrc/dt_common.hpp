@@ -34,7 +34,7 @@ struct alignas(16) ExpMeta {
   int32_t src;              // caller's index of this exposure
   float fwhm;               // PSF FWHM (px)
   int32_t R;                // stamp half-width ceil(3 sigma)
-  int32_t pad;
+  float vs;                 // scalar pixel variance when the patch has no variance planes
 };
 static_assert(sizeof(ExpMeta) == 176, "ExpMeta layout");
 
@@ -141,6 +141,24 @@ hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_
 // Outlier trimming of m candidate orbits (n_exp <= 512); d_buf is m x n_exp float2 scratch.
 hipError_t launch_clip(const StackArgs& a, const int64_t* d_ids, int64_t m, double kappa, int max_iter,
                        float2* d_buf, float* snr, float* flux, int32_t* nkept, hipStream_t s);
+
+// Per-image iterated-MAD noise: per-image selection state.
+struct NoiseState {
+  double m_cur, thr_cur;  // current set: finite x with |x - m_cur| <= thr_cur
+  double m_new, thr_new;  // median of the set and the next clip half-width
+  double sigma;
+  double val[2];          // the two selected middle values
+  uint64_t prefix[2];     // key bits chosen so far
+  int64_t rank[2];        // target ranks among keys sharing the prefix
+  int64_t n, n_new, n_used;
+  int32_t iter, done, changed, pad;
+};
+constexpr double NOISE_KAPPA = 3.0;   // clip half-width in sigma (patches without variance planes)
+constexpr int NOISE_MAX_ITER = 10;
+size_t noise_scratch_bytes(int n_img);
+hipError_t launch_noise(const void* const* d_imgs, const int64_t* d_npix, int64_t max_pix, int n_img, dt_dtype dtype,
+                        double kappa, int max_iter, void* scratch, double* d_sigma, int64_t* d_used, int32_t* d_iters,
+                        ExpMeta* d_meta, hipStream_t s);
 
 // Device-side orbit sampling (GenerateOrbits) and generate-and-stack.
 hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, double* a, double* e, double* inc,

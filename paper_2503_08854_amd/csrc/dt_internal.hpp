@@ -25,6 +25,8 @@ struct dt_ctx {
   void* topk_scratch = nullptr;
   size_t topk_bytes = 0;
   unsigned long long* d_counter = nullptr;
+  void* noise_ws = nullptr;  // staging + selection state of dt_image_noise
+  size_t noise_bytes = 0;
   dtk::BatchGraph* graph = nullptr;  // last captured batched launch
   hipStream_t capture_stream = nullptr;
   bool alive = true;
@@ -49,6 +51,12 @@ struct dt_patch {
   const void** d_flux = nullptr;
   const void** d_var = nullptr;
   bool images_released = false;
+  // no variance planes: per-exposure noise by iterated MAD at every pre-pass
+  bool est_noise = false;
+  int64_t max_pix = 0;
+  int64_t* d_npix = nullptr;   // caller order
+  double* d_sigma = nullptr;   // caller order
+  void* noise_ws = nullptr;
 };
 
 namespace dtk {

@@ -78,7 +78,7 @@ __global__ void k_exposure_prep(const dt_exposure* __restrict__ in, const int64_
   m.src = src[i];
   m.fwhm = x.psf_fwhm_px;
   m.R = rad[i];
-  m.pad = 0;
+  m.vs = 0.f;
   out[i] = m;
 }
 
@@ -166,11 +166,11 @@ __global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__
       const int64_t base = (int64_t)gy * W;
       if (in_c) {
         d = load_px<T>(Dp, base + cx);
-        v = load_px<T>(Vp, base + cx);
+        v = Vp ? load_px<T>(Vp, base + cx) : m.vs;
       }
       if (in_h) {
         dh = load_px<T>(Dp, base + hx);
-        vh = load_px<T>(Vp, base + hx);
+        vh = Vp ? load_px<T>(Vp, base + hx) : m.vs;
       }
     }
   };

@@ -359,3 +359,90 @@ def test_generate_and_stack_matches_stack_and_oracle(small):
         inb = band_mask(o["px"], o["py"], W, H) & ((o["flags"] & 1) != 0)
         assert inb.any(axis=1).all()
     assert (nv_o > 0).sum() > 100
+
+
+def _noise_images(rng):
+    ims = []
+    x = rng.normal(0.0, 2.0, (256, 256)).astype(np.float32)
+    x[rng.random(x.shape) < 0.01] = np.nan
+    x[rng.random(x.shape) < 0.005] = 400.0          # bright outliers
+    ims.append(x)
+    ims.append(rng.normal(5.0, 0.3, (37, 1001)).astype(np.float32))   # ragged, offset
+    ims.append(np.full((3, 5), 7.0, np.float32))                     # constant: sigma 0
+    ims.append(np.full((4, 4), np.nan, np.float32))                  # no finite pixel
+    ims.append(np.array([[1.5]], np.float32))                        # one pixel
+    ims.append(np.zeros((0, 8), np.float32))                         # empty
+    ims.append(np.round(rng.normal(0, 3, (64, 80))).astype(np.float32))   # many ties
+    y = rng.standard_cauchy((128, 96)).astype(np.float32)            # heavy tails, +-0
+    y[0, :4] = [0.0, -0.0, 0.0, -0.0]
+    ims.append(y)
+    return ims
+
+
+def test_image_noise_matches_oracle_exactly():
+    import torch
+    import paper_2503_08854_amd as dt
+    rng = np.random.default_rng(17)
+    ims = _noise_images(rng)
+    ctx = dt.Context(0)
+    for kappa, max_iter in [(3.0, 10), (2.5, 10), (3.0, 1), (4.0, 3)]:
+        dev = [torch.from_numpy(x).cuda() for x in ims]
+        sig, used, it = dt.image_noise(ctx, dev, kappa, max_iter)
+        torch.cuda.synchronize()
+        sig, used, it = sig.cpu().numpy(), used.cpu().numpy(), it.cpu().numpy()
+        for i, x in enumerate(ims):
+            ws, wu, wi = oracle.mad_noise(x, kappa, max_iter)
+            assert (it[i], used[i]) == (wi, wu), (i, kappa, max_iter)
+            if math.isnan(ws):
+                assert math.isnan(sig[i])
+            else:
+                assert sig[i] == ws, (i, kappa, max_iter, sig[i], ws)
+
+
+def test_image_noise_fp16_and_many_images():
+    import torch
+    import paper_2503_08854_amd as dt
+    rng = np.random.default_rng(23)
+    ctx = dt.Context(0)
+    ims = [rng.normal(0, rng.uniform(0.5, 3), (int(rng.integers(1, 300)), int(rng.integers(1, 300))))
+           .astype(np.float16) for _ in range(40)]
+    sig, used, it = dt.image_noise(ctx, [torch.from_numpy(x).cuda() for x in ims])
+    torch.cuda.synchronize()
+    sig, used, it = sig.cpu().numpy(), used.cpu().numpy(), it.cpu().numpy()
+    for i, x in enumerate(ims):
+        ws, wu, wi = oracle.mad_noise(x.astype(np.float32))
+        assert sig[i] == ws and used[i] == wu and it[i] == wi
+
+
+def test_patch_without_variance_uses_mad_noise(small):
+    import torch
+    import paper_2503_08854_amd as dt
+    w = small
+    ctx = dt.Context(0)
+    Dt, _ = to_torch_images(w.D, w.V)
+    patch = dt.Patch(ctx, w.exps, Dt)
+    sig = patch.noise().cpu().numpy()
+    Vo = []
+    for e, d in enumerate(w.D):
+        ws, _, _ = oracle.mad_noise(d)
+        assert sig[e] == ws
+        v = np.full(d.shape, np.float32(ws * ws), np.float32)
+        Vo.append(v)
+    for e in (0, len(w.exps) // 2, len(w.exps) - 1):
+        got = patch.plane(e).cpu().numpy().astype(np.float64)
+        psi, phi = oracle.planes(w.D[e], Vo[e], w.exps[e]["fwhm"])
+        sc = np.sqrt(np.maximum(phi, 1e-30))
+        assert np.max(np.abs(got[..., 0] - psi) / np.maximum(sc, 1e-3)) < 2e-6
+        assert np.max(np.abs(got[..., 1] - phi) / np.maximum(phi, 1e-30)) < 2e-6
+    orb = dt.OrbitSet(w.elements, w.t0, "cuda")
+    snr, _, nv = dt.stack(patch, orb)
+    torch.cuda.synchronize()
+    snr_o, _, nv_o = oracle.stack(w.elements, w.t0, w.exps, w.D, Vo)
+    np.testing.assert_array_equal(nv.cpu().numpy(), nv_o)
+    assert snr_close(snr.cpu().numpy(), snr_o).all()
+    # refresh after an in-place change re-estimates the noise
+    for d in Dt:
+        d.mul_(2.0)
+    patch.refresh()
+    sig2 = patch.noise().cpu().numpy()
+    np.testing.assert_array_equal(sig2, 2.0 * sig)
