@@ -59,6 +59,8 @@ class Bench:
         self.dev = device
         self.D, self.V = synth.noise_images(s.exps, 1, s.geom.get("nan_frac", 0.0), "f32", device)
         self.patch = dt.Patch(ctx, s.exps, self.D, self.V)
+        from paper_2503_08854_amd import proposer
+        self.coarse = proposer.coarse_patch(ctx, s.exps, self.D, self.V)
         self.grid = dt.OrbitSet(s.el, s.t0, device)
         self.reps = dt.OrbitSet(s.el[::s.cell_size], s.t0, device)
 
@@ -71,6 +73,7 @@ class Bench:
             a.copy_(b)
         synth.render_sources_fast(self.D, self.s.exps, hits, self.dev)
         self.patch.refresh()
+        self.coarse.refresh()
 
 
 def training_set(bench: Bench, n_real: int, seed: int, pos_frac: float = 0.5, snr_rng=(3.0, 10.0), log=None):
@@ -118,7 +121,7 @@ def train_scorer(ctx, stamps, feats, labels, epochs: int = 2, batch: int = 512, 
 
 
 def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None, log=None):
-    """Recall of plain / learned / coarse-max selection over stored realizations, and timings."""
+    """Recall of plain / learned / coarse-max / coarse-to-fine selection over stored realizations, and timings."""
     import torch
     import paper_2503_08854_amd as dt
     from paper_2503_08854_amd import proposer
@@ -128,7 +131,7 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
     n = bench.grid.n
     out_full = dt.batch_outputs([bench.grid])[0]
     out_sel = tuple(torch.empty_like(t) for t in out_full)
-    found = dict(plain=0, learned=0, coarse=0)
+    found = dict(plain=0, learned=0, coarse=0, c2f=0)
     tot = 0
     t_plain, t_learn = [], []
     for r, injs in enumerate(reals):
@@ -152,11 +155,18 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
             t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
         proposer.run_coarse(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, budget, out=out_sel)
         coarse_snr = out_sel[0].cpu().numpy()
+        for t in out_sel:
+            t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
+        proposer.run_coarse_to_fine(bench.ctx, bench.patch, bench.coarse, bench.grid, bench.reps, s.cell_size, budget,
+                                    out=out_sel)
+        c2f_snr = out_sel[0].cpu().numpy()
         plain_snr = out_full[0].cpu().numpy()
         orbits = np.array([inj["orbit"] for inj in injs])
         pf = plain_snr[orbits] >= 5.0
         lf = np.nan_to_num(learned_snr[orbits], nan=-np.inf) >= 5.0
         cf = np.nan_to_num(coarse_snr[orbits], nan=-np.inf) >= 5.0
+        c2 = np.nan_to_num(c2f_snr[orbits], nan=-np.inf) >= 5.0
+        found["c2f"] += int((c2 & pf).sum())
         found["plain"] += int(pf.sum())
         found["learned"] += int((lf & pf).sum())
         found["coarse"] += int((cf & pf).sum())
@@ -169,6 +179,7 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
                recall_plain=found["plain"] / max(tot, 1),
                recall_ratio_learned=found["learned"] / max(found["plain"], 1),
                recall_ratio_coarse=found["coarse"] / max(found["plain"], 1),
+               recall_ratio_coarse_to_fine=found["c2f"] / max(found["plain"], 1),
                t_plain_ms=tp * 1e3, t_learned_ms=tl * 1e3, speedup=tp / tl, orbits=n)
     if log:
         log(f"learned eval: {res}")

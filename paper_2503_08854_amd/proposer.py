@@ -6,6 +6,9 @@ Pipeline, every numerical step in the library's kernels:
   3. the `budget` best cells by logit (dt_topk on the logits);
   4. the plain stack on the orbits of those cells only (dt_stack_cells).
 The exhaustive stack over every orbit stays the fallback and the judge.
+Two non-learned counterparts rank cells the same way: by the coarse stamp's
+maximum (run_coarse) and by the representatives' S/N on planes smoothed with
+a Gaussian wider than the PSF (run_coarse_to_fine).
 
 Training uses stacks the method itself produces: synthetic exposures with
 sources injected on member orbits of chosen cells (their pixel tracks from the
@@ -50,6 +53,26 @@ def run_coarse(ctx, patch, grid, reps, cell_size: int, budget: int, out=None):
     cells = select_cells(ctx, o["feats"][:, 0].contiguous(), budget)
     out = B.stack_cells(patch, grid, cells, cell_size, out=out)
     return out, cells
+
+
+def coarse_exposures(exps, factor: float, fwhm_max: float = 8.0):
+    """Exposure records whose PSF FWHM is widened by `factor` (capped at fwhm_max px)."""
+    return [dict(x, fwhm=min(float(x["fwhm"]) * factor, fwhm_max)) for x in exps]
+
+
+def coarse_patch(ctx, exps, flux, var, factor: float = 2.5):
+    """A patch over the same images whose planes use the widened Gaussian (Sec. 5.2.2 smoothing)."""
+    return B.Patch(ctx, coarse_exposures(exps, factor), flux, var)
+
+
+def run_coarse_to_fine(ctx, patch, coarse, grid, reps, cell_size: int, budget: int, out=None):
+    """Coarse-to-fine: the sparse grid (one representative per cell) stacked on
+    the widened-PSF planes, the `budget` cells of highest coarse S/N, then the
+    plain stack on every orbit of those cells.  Returns (outputs, cells, coarse S/N)."""
+    snr_c, _, _ = B.stack(coarse, reps)
+    cells = select_cells(ctx, snr_c, budget)
+    out = B.stack_cells(patch, grid, cells, cell_size, out=out)
+    return out, cells, snr_c
 
 
 def member_tracks(patch, grid, orbit_ids):

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import to_torch_images
+from helpers import snr_close, to_torch_images
 from oracle import nn_ref as nn
 
 pytestmark = pytest.mark.gpu
@@ -246,3 +246,32 @@ def test_stack_cells_equals_full_stack(cells):
         a, b = a.cpu().numpy(), b.cpu().numpy()
         np.testing.assert_array_equal(a[mask], b[mask])
     assert np.all(part[2].cpu().numpy()[~mask] == -2)
+
+
+def test_coarse_to_fine_matches_oracle(cells):
+    import torch
+    import paper_2503_08854_amd as dt
+    from paper_2503_08854_amd import proposer
+    c = cells
+    cs = c["g"]["cell_grid"]["cell_size"]
+    Dt, Vt = c["keep"]
+    coarse = proposer.coarse_patch(c["ctx"], c["exps"], Dt, Vt, factor=2.5)
+    budget = 20
+    out, sel, snr_c = proposer.run_coarse_to_fine(c["ctx"], c["patch"], coarse, c["grid"], c["reps"], cs, budget)
+    torch.cuda.synchronize()
+    snr_c = snr_c.cpu().numpy()
+    sel = sel.cpu().numpy()
+    # coarse S/N of the representatives vs the oracle on widened-PSF planes
+    reps = c["el"][::cs]
+    wide = proposer.coarse_exposures(c["exps"], 2.5)
+    snr_o, _, _ = oracle.stack(reps, c["g"]["t0"], wide, c["D"], c["V"])
+    assert snr_close(snr_c, snr_o).all()
+    # selection: the top `budget` of the GPU's coarse S/N (same precision on both sides)
+    np.testing.assert_array_equal(sel, oracle.topk(snr_c.astype(np.float64), budget))
+    # fine stack on the selected cells vs the oracle on those orbits
+    ids = (sel[:, None] * cs + np.arange(cs)[None, :]).ravel()
+    snr_f, _, nv_f = oracle.stack(c["el"][ids], c["g"]["t0"], c["exps"], c["D"], c["V"])
+    got = out[0].cpu().numpy()
+    np.testing.assert_array_equal(out[2].cpu().numpy()[ids], nv_f)
+    assert snr_close(got[ids], snr_f).all()
+    assert np.all(np.isnan(np.delete(got, ids)))
