@@ -241,10 +241,13 @@ dt_status dt_stack_generated(dt_patch *p, const dt_orbit_sampler *sampler, int64
 /* Per-intersection outlier trimming of candidate orbits (Sec. 5.2.3): for
  * each of m orbits (device int64 ids into `orbits`), the valid samples'
  * (psi_e, phi_e) from the stack's device code are clipped two-sided at
- * |psi_e - F phi_e| / sqrt(phi_e) > kappa about F = sum psi / sum phi of the
- * kept samples, refitting until the kept set is stable or after max_iter
- * rounds.  Outputs (device, m each, may be NULL): S/N, flux and the kept
- * count after trimming.  Patches of at most 512 exposures.  Synchronises. */
+ * |psi_e - F phi_e| / sqrt(phi_e) > kappa.  Round 1 takes F = the median of
+ * the per-sample fluxes psi_e / phi_e (mean of the two middle values for an
+ * even count); each later round takes F = sum psi / sum phi of the samples
+ * the previous round kept; it stops when a round keeps exactly the set it
+ * started from, or after max_iter rounds.  Outputs (device, m each, may be
+ * NULL): S/N, flux and the kept count after trimming (0, 0, 0 when nothing
+ * is kept).  Patches of at most 512 exposures.  Synchronises. */
 dt_status dt_clip_candidates(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, int64_t m,
                              double kappa, int32_t max_iter, float *d_snr, float *d_flux, int32_t *d_nkept);
 

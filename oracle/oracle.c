@@ -402,38 +402,72 @@ int64_t or_topk(int64_t n, const double *snr, int64_t k, double thr, int64_t *id
 }
 
 /* ---- per-intersection outlier trimming (Sec. 5.2.3) ------------------------ */
-/* Under the constant-flux model every valid intersection e gives an
- * independent flux estimate psi_e / phi_e with variance 1 / phi_e.  Reading:
- * two-sided sigma clipping of the residuals chi_e = (psi_e - F phi_e) /
- * sqrt(phi_e) about the weighted mean F = sum psi / sum phi of the kept
- * samples; samples with |chi_e| > kappa are dropped and the fit repeated
- * until the kept set does not change or after max_iter rounds.  Returns the
- * S/N, flux and count of the kept set (n_valid entries of psi/phi, phi > 0). */
+/* Under the constant-flux model every valid intersection e (phi_e > 0) gives
+ * an independent flux estimate f_e = psi_e / phi_e of variance 1 / phi_e.
+ * The paper removes intersections whose S/N is anomalously far from the
+ * expectation by sigma clipping.  Reading: the expectation starts at the
+ * median of the f_e (so that one dominant artifact cannot set it) and is
+ * then the weighted mean F = sum psi / sum phi of the kept samples; a sample
+ * is dropped when its residual chi_e = (psi_e - F phi_e) / sqrt(phi_e) has
+ * |chi_e| > kappa (both sides: a one-sided clip lets a deep negative
+ * artifact drag F down until the ordinary samples look high).  Round 1
+ * clips about the median; every later round about the fit of the set the
+ * previous round kept, until a round keeps exactly that set or after
+ * max_iter rounds.  The median of an even count is the mean of the two
+ * middle values.  Returns the S/N, flux and count of the kept set. */
+static int or_cmp_dbl(const void *pa, const void *pb) {
+  double a = *(const double *)pa, b = *(const double *)pb;
+  return (a > b) - (a < b);
+}
+
 void or_sigma_clip(int n, const double *psi, const double *phi, double kappa, int max_iter,
                    double *snr, double *flux, int32_t *n_kept, uint8_t *kept) {
-  for (int i = 0; i < n; ++i) kept[i] = phi[i] > 0.0;
-  for (int it = 0; it < max_iter; ++it) {
-    double P = 0.0, F = 0.0;
-    for (int i = 0; i < n; ++i)
-      if (kept[i]) { P += psi[i]; F += phi[i]; }
-    if (!(F > 0.0)) break;
-    double mu = P / F;
+  double *f = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  int m = 0;
+  for (int i = 0; i < n; ++i) {
+    kept[i] = phi[i] > 0.0;
+    if (kept[i]) f[m++] = psi[i] / phi[i];
+  }
+  double F = 0.0;
+  if (m > 0) {
+    qsort(f, (size_t)m, sizeof(double), or_cmp_dbl);
+    F = 0.5 * (f[(m - 1) / 2] + f[m / 2]);
+  }
+  free(f);
+  /* the first round clips about the median; later rounds about the fit of
+   * the kept set, until a round keeps exactly the set it started from */
+  for (int it = 0; it < max_iter && m > 0; ++it) {
+    if (it > 0) {
+      double P = 0.0, Q = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (kept[i]) {
+          P += psi[i];
+          Q += phi[i];
+        }
+      F = P / Q;
+    }
     int changed = 0;
     for (int i = 0; i < n; ++i) {
       if (!(phi[i] > 0.0)) continue;
-      double chi = (psi[i] - mu * phi[i]) / sqrt(phi[i]);
-      uint8_t k = fabs(chi) <= kappa;
-      if (k != kept[i]) { kept[i] = k; changed = 1; }
+      uint8_t k = fabs(psi[i] - F * phi[i]) / sqrt(phi[i]) <= kappa;
+      if (k != kept[i]) {
+        kept[i] = k;
+        changed = 1;
+      }
     }
-    if (!changed) break;
+    if (it > 0 && !changed) break;
   }
-  double P = 0.0, F = 0.0;
-  int m = 0;
+  double P = 0.0, Q = 0.0;
+  int c = 0;
   for (int i = 0; i < n; ++i)
-    if (kept[i]) { P += psi[i]; F += phi[i]; m++; }
-  *snr = F > 0.0 ? P / sqrt(F) : 0.0;
-  *flux = F > 0.0 ? P / F : 0.0;
-  *n_kept = m;
+    if (kept[i]) {
+      P += psi[i];
+      Q += phi[i];
+      c++;
+    }
+  *snr = Q > 0.0 ? P / sqrt(Q) : 0.0;
+  *flux = Q > 0.0 ? P / Q : 0.0;
+  *n_kept = c;
 }
 
 /* ------------------------------------------------------------------------
@@ -446,13 +480,8 @@ void or_sigma_clip(int n, const double *psi, const double *phi, double kappa, in
  * result is the sigma of the last computed step, the size of the set it came
  * from, and the number of steps.  An image with no finite pixel gives NaN.
  * ------------------------------------------------------------------------ */
-static int or_cmp_double(const void *pa, const void *pb) {
-  double a = *(const double *)pa, b = *(const double *)pb;
-  return (a > b) - (a < b);
-}
-
 static double or_median(double *v, int64_t n) {
-  qsort(v, (size_t)n, sizeof(double), or_cmp_double);
+  qsort(v, (size_t)n, sizeof(double), or_cmp_dbl);
   return 0.5 * (v[(n - 1) / 2] + v[n / 2]);
 }
 

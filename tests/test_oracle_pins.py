@@ -467,17 +467,40 @@ def test_sigma_clip_keeps_a_real_constant_flux_source():
 
 
 def test_sigma_clip_fixed_point_by_brute_force():
-    """The kept set is a fixed point: refitting on it keeps exactly it."""
+    """The kept set is a fixed point: refitting on it keeps exactly it (and
+    for these inputs it is not empty)."""
     rng = np.random.default_rng(14)
-    for _ in range(50):
-        n = int(rng.integers(3, 30))
+    for _ in range(200):
+        n = int(rng.integers(1, 30))
         phi = rng.uniform(0.01, 0.1, n)
         psi = rng.standard_normal(n) * np.sqrt(phi) * rng.choice([1.0, 6.0], n, p=[0.8, 0.2])
         snr, flux, nk, kept = oracle.sigma_clip(psi, phi, 2.5, 50)
-        if nk:
-            mu = psi[kept].sum() / phi[kept].sum()
-            chi = np.abs(psi - mu * phi) / np.sqrt(phi)
-            assert np.array_equal(chi <= 2.5, kept)
+        assert nk >= 1
+        mu = psi[kept].sum() / phi[kept].sum()
+        chi = np.abs(psi - mu * phi) / np.sqrt(phi)
+        assert np.array_equal(chi <= 2.5, kept)
+        assert flux == pytest.approx(mu, rel=1e-13)
+
+
+def test_sigma_clip_median_start():
+    """A dominant artifact among few samples: the first fit from all samples
+    would be pulled so far that every sample looks anomalous; the median
+    start keeps the ordinary samples, on either side of the artifact."""
+    phi = np.array([0.05, 0.04, 0.06, 0.05])
+    psi = np.array([0.01, -0.02, 0.015, 40.0])      # one artifact with single-image S/N ~ 180
+    snr, flux, nk, kept = oracle.sigma_clip(psi, phi, 3.0, 10)
+    np.testing.assert_array_equal(kept, [True, True, True, False])
+    assert snr == pytest.approx(psi[:3].sum() / math.sqrt(phi[:3].sum()), rel=1e-14)
+    # the median of the per-sample fluxes: even count -> mean of the two middle values
+    f = np.sort(psi / phi)
+    med = 0.5 * (f[1] + f[2])
+    assert abs((psi[3] - med * phi[3]) / math.sqrt(phi[3])) > 3
+    # a deep negative artifact goes the same way
+    psi2 = np.array([0.01, -0.02, 0.015, -40.0])
+    _, _, nk2, kept2 = oracle.sigma_clip(psi2, phi, 3.0, 10)
+    np.testing.assert_array_equal(kept2, [True, True, True, False])
+    # no valid sample: nothing kept, zero S/N and flux
+    assert oracle.sigma_clip(psi, np.zeros(4), 3.0, 10)[:3] == (0.0, 0.0, 0)
 
 
 # --------------------------------------------------- orbit generation (Alg. 1)
