@@ -68,6 +68,44 @@ def cpu_baseline(w, gpu_snr, seconds=12.0):
                 snr_max_err=float(err.max()))
 
 
+def gather_yardstick(patch, w, dev, m=1_000_000, reps=3):
+    """The stack's own gather stream replayed without the orbit arithmetic, on
+    the first m orbits: the achievable gather rate of that access pattern."""
+    import torch
+    import paper_2503_08854_amd as dt
+    m = min(m, w.elements.shape[0])
+    sub = dt.OrbitSet(w.elements[:m], w.t0, dev)
+    off = dt.record_gathers(patch, sub, torch.arange(m, device=dev))
+    out = dt.batch_outputs([sub])[0]
+    snr_r = torch.empty(m, dtype=torch.float32, device=dev)
+    dt.stack(patch, sub, out)
+    dt.gather_replay(patch, off, snr_r)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(torch.where(out[2] >= 0, out[0], torch.zeros_like(out[0])), snr_r))
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    t_stack = timed(lambda: dt.stack(patch, sub, out))
+    t_rep = timed(lambda: dt.gather_replay(patch, off, snr_r))
+    valid = int((off != -1).sum())
+    useful = 8.0 * valid
+    res = dict(orbits=m, valid_samples=valid, dense_samples=m * patch.n_exp, stack_ms=t_stack, replay_ms=t_rep,
+               stack_useful_GBs=useful / (t_stack * 1e-3) / 1e9, replay_useful_GBs=useful / (t_rep * 1e-3) / 1e9,
+               replay_index_stream_GB=4.0 * m * patch.n_exp / 1e9, frac_of_achievable_gather=t_rep / t_stack,
+               replay_equals_stack=same)
+    del off, sub, out, snr_r
+    return res
+
+
 def bench_batched(dev, steps=5):
     """The batched-patches workload: 64 uneven FP16 patches, one graph-captured
     persistent launch (stack + per-patch top-k) after autotuning."""
@@ -240,6 +278,10 @@ def main():
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(w, snr)
         log(f"cpu baseline: {rec['cpu_baseline']['value']:.3g} samples/s on {rec['cpu_baseline']['cores']} threads")
+    rec["gather"] = gather_yardstick(patch, w, dev)
+    G = rec["gather"]
+    log(f"gather yardstick: stack {G['stack_ms']:.3f} ms vs replay {G['replay_ms']:.3f} ms on {G['orbits']} orbits "
+        f"({G['frac_of_achievable_gather']:.2f} of the achievable gather rate)")
     patch.close()
     ctx.close()
     del w, orb, out, patch

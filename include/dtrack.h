@@ -212,6 +212,20 @@ dt_status dt_autotune_batched(dt_ctx *ctx, dt_patch *const *patches, const dt_or
  * with DT_E_STATE. */
 dt_status dt_patch_release_images(dt_patch *p);
 
+/* Measurement yardstick for the stack's gathers (no paper counterpart).
+ * dt_record_gathers writes, for m orbits (device int64 ids), the plane
+ * offset (uint32, float2 units) of every valid sample the stack would
+ * gather, laid out [exposure in epoch order][m], ~0u where a sample is not
+ * valid (device, n_exp * m entries; patches whose planes hold < 2^32 - 1
+ * elements).  dt_gather_replay then loads those offsets' (psi, phi) in the
+ * same order and sums them as dt_stack does (d_snr, device, m floats,
+ * equal to dt_stack's S/N on those orbits), with none of the orbit
+ * arithmetic: its rate is the achievable gather rate of the same access
+ * stream.  Both enqueue on the context stream. */
+dt_status dt_record_gathers(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, int64_t m,
+                            uint32_t *d_off);
+dt_status dt_gather_replay(dt_patch *p, const uint32_t *d_off, int64_t m, float *d_snr);
+
 /* Candidate-orbit distribution for on-device sampling (Algorithm 1,
  * GenerateOrbits): a, e, i uniform in their ranges (AU, -, radians); a line
  * of sight uniform over the tangent-plane rectangle |xi| <= half_w,

@@ -88,6 +88,8 @@ def lib():
         "dt_cell_stamps": ([_P, C.POINTER(DtOrbits), _P, _P, _P, _P], C.c_int),
         "dt_image_noise": ([_P, C.c_int32, _P, _P, C.c_int, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
         "dt_patch_noise": ([_P, _P], C.c_int),
+        "dt_record_gathers": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P], C.c_int),
+        "dt_gather_replay": ([_P, _P, C.c_int64, _P], C.c_int),
         "dt_generate_orbits": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P],
                                C.c_int),
         "dt_stack_generated": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P], C.c_int),
@@ -391,6 +393,26 @@ def autotune_batched(ctx: Context, patches, orbit_sets, outs=None, cache_path=No
     _check(lib().dt_autotune_batched(ctx.handle, ph, sets, len(patches), snr, flux, nv,
                                      cache_path.encode() if cache_path else None, C.byref(best), C.byref(ms)))
     return (best.chunk, best.wg_per_cu), ms.value
+
+
+def record_gathers(patch: Patch, orbits: OrbitSet, ids):
+    """Plane offsets of the stack's valid gathers for orbits `ids`: (n_exp, m) int32 view of uint32 (-1 = none)."""
+    import torch
+    ids = torch.as_tensor(ids, dtype=torch.int64).to(patch.device)
+    m = int(ids.numel())
+    off = torch.empty((patch.n_exp, m), dtype=torch.int32, device=patch.device)
+    _check(lib().dt_record_gathers(patch.handle, C.byref(orbits.struct()), _ptr(ids), m, _ptr(off)))
+    return off
+
+
+def gather_replay(patch: Patch, off, snr=None):
+    """Replay a recorded gather stream; returns the S/N (equal to the stack's on those orbits)."""
+    import torch
+    m = int(off.shape[1])
+    if snr is None:
+        snr = torch.empty(m, dtype=torch.float32, device=patch.device)
+    _check(lib().dt_gather_replay(patch.handle, _ptr(off), m, _ptr(snr)))
+    return snr
 
 
 def image_noise(ctx: Context, images, kappa: float = 3.0, max_iter: int = 10):

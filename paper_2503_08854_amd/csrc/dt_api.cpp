@@ -487,10 +487,31 @@ dt_status dt_debug_samples(dt_patch* p, const dt_orbits* o, const int64_t* d_ids
   if (m < 0 || (m > 0 && !d_ids)) return fail(DT_E_ARG, "bad id array");
   DeviceGuard g(p->ctx->device);
   StackArgs a = stack_args(p, o);
-  DebugArgs d{d_ids, m, d_px, d_py, d_tau, d_ix, d_iy, d_flags, d_psi, d_phi};
+  DebugArgs d{d_ids, m, d_px, d_py, d_tau, d_ix, d_iy, d_flags, d_psi, d_phi, nullptr};
   hipError_t e = launch_debug(a, d, p->ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "debug launch");
   return DT_OK;
+}
+
+dt_status dt_record_gathers(dt_patch* p, const dt_orbits* o, const int64_t* d_ids, int64_t m, uint32_t* d_off) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  dt_status st = check_orbits(o);
+  if (st != DT_OK) return st;
+  if (m < 0 || (m > 0 && (!d_ids || !d_off))) return fail(DT_E_ARG, "bad id or output array");
+  if (p->plane_elems >= 0xFFFFFFFFull) return fail(DT_E_ARG, "planes too large for 32-bit offsets");
+  DeviceGuard g(p->ctx->device);
+  StackArgs a = stack_args(p, o);
+  DebugArgs d{d_ids, m, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, d_off};
+  hipError_t e = launch_debug(a, d, p->ctx->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "gather recording launch");
+}
+
+dt_status dt_gather_replay(dt_patch* p, const uint32_t* d_off, int64_t m, float* d_snr) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  if (m < 0 || (m > 0 && (!d_off || !d_snr))) return fail(DT_E_ARG, "bad offset or output array");
+  DeviceGuard g(p->ctx->device);
+  hipError_t e = launch_gather_replay(p->d_planes, d_off, m, p->n_exp, d_snr, p->ctx->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "gather replay launch");
 }
 
 }  // extern "C"

@@ -83,6 +83,7 @@ struct DebugArgs {
   double *px, *py, *tau;
   int32_t *ix, *iy, *flags;
   float *psi, *phi;
+  uint32_t* off;  // [exposure in epoch order][m]: plane offset of a valid sample, else ~0u
 };
 
 // Work item of the batched persistent launch: orbits [begin, begin + count)
@@ -141,6 +142,10 @@ hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_
 // Outlier trimming of m candidate orbits (n_exp <= 512); d_buf is m x n_exp float2 scratch.
 hipError_t launch_clip(const StackArgs& a, const int64_t* d_ids, int64_t m, double kappa, int max_iter,
                        float2* d_buf, float* snr, float* flux, int32_t* nkept, hipStream_t s);
+
+// Replay of a recorded gather stream (measurement yardstick).
+hipError_t launch_gather_replay(const float2* planes, const uint32_t* off, int64_t m, int n_exp, float* snr,
+                                hipStream_t s);
 
 // Per-image iterated-MAD noise: per-image selection state.
 struct NoiseState {

@@ -22,6 +22,7 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
       for (int ex = 0; ex < A.n_exp; ++ex) {
         int64_t q = row * A.n_exp + A.meta[ex].src;
         if (dbg->flags) dbg->flags[q] = 0;
+        if (dbg->off) dbg->off[(int64_t)ex * dbg->m + row] = ~0u;
       }
     }
     return;
@@ -56,6 +57,8 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
       if (dbg->flags) dbg->flags[q] = (f ? 1 : 0) | (so.inside ? 2 : 0) | (valid ? 4 : 0);
       if (dbg->psi) dbg->psi[q] = valid ? v.x : 0.f;
       if (dbg->phi) dbg->phi[q] = valid ? v.y : 0.f;
+      if (dbg->off)
+        dbg->off[(int64_t)ex * dbg->m + row] = valid ? (uint32_t)(x.plane_off + (int64_t)so.iy * x.W + so.ix) : ~0u;
     }
   });
   const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;

@@ -33,8 +33,10 @@ __global__ __launch_bounds__(64) void k_stack_debug(StackArgs A, DebugArgs D) {
   if (r >= D.m) return;
   const int64_t o = D.ids[r];
   if (o < 0 || o >= A.n) {
-    for (int ex = 0; ex < A.n_exp; ++ex)
+    for (int ex = 0; ex < A.n_exp; ++ex) {
       if (D.flags) D.flags[r * A.n_exp + ex] = 0;
+      if (D.off) D.off[(int64_t)ex * D.m + r] = ~0u;
+    }
     return;
   }
   float snr, flux;
@@ -48,7 +50,39 @@ __global__ __launch_bounds__(256) void k_validate(StackArgs A, unsigned long lon
   if (!orbit_ok(A.a[o], A.e[o], A.inc[o], A.node[o], A.peri[o], A.m0[o])) atomicAdd(bad, 1ull);
 }
 
+// The stack's gather stream without its arithmetic: lane i visits the
+// recorded plane offsets of orbit i in epoch order and sums what it loads
+// exactly as k_stack does.  A yardstick for the achievable gather rate.
+__global__ __launch_bounds__(256) void k_gather_replay(const float2* __restrict__ planes,
+                                                       const uint32_t* __restrict__ off, int64_t m, int n_exp,
+                                                       float* __restrict__ snr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  Kahan ps, ph;
+  ps.init();
+  ph.init();
+  for (int ex = 0; ex < n_exp; ++ex) {
+    const uint32_t o = off[(int64_t)ex * m + i];
+    if (o != ~0u) {
+      const float2 v = planes[o];
+      if (v.y > 0.f) {
+        ps.add(v.x);
+        ph.add(v.y);
+      }
+    }
+  }
+  const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
+  snr[i] = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
+}
+
 static inline unsigned int grid_for(int64_t n, int bs) { return (unsigned int)((n + bs - 1) / bs); }
+
+hipError_t launch_gather_replay(const float2* planes, const uint32_t* off, int64_t m, int n_exp, float* snr,
+                                hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_replay, dim3(grid_for(m, 256)), dim3(256), 0, s, planes, off, m, n_exp, snr);
+  return hipGetLastError();
+}
 
 hipError_t launch_stack(const StackArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;

@@ -446,3 +446,27 @@ def test_patch_without_variance_uses_mad_noise(small):
     patch.refresh()
     sig2 = patch.noise().cpu().numpy()
     np.testing.assert_array_equal(sig2, 2.0 * sig)
+
+
+def test_gather_replay_equals_stack(small):
+    import torch
+    import paper_2503_08854_amd as dt
+    w = small
+    g = gpu_run(w, ids=np.arange(w.elements.shape[0]))
+    ctx, patch, orb, _, _ = g["_keep"]
+    ids = np.arange(orb.n)
+    off = dt.record_gathers(patch, orb, ids)
+    snr = dt.gather_replay(patch, off)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(snr.cpu().numpy(), np.where(g["nv"] >= 0, g["snr"], 0.0).astype(np.float32))
+    # offsets agree with the debug table: valid samples only, epoch order
+    o = off.cpu().numpy()
+    order = np.argsort([x["t"] for x in w.exps], kind="stable")
+    dbg = g["dbg"]
+    valid = (dbg["flags"] & 4) != 0
+    np.testing.assert_array_equal((o != -1).T, valid[:, order])
+    sizes = np.array([x["width"] * x["height"] for x in w.exps])[order]
+    base = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    W = np.array([x["width"] for x in w.exps])[order]
+    want = base[None, :] + dbg["iy"][:, order].astype(np.int64) * W[None, :] + dbg["ix"][:, order]
+    np.testing.assert_array_equal(o.T[valid[:, order]], want[valid[:, order]])
