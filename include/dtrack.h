@@ -305,7 +305,8 @@ dt_status dt_gemm_bf16(dt_ctx *ctx, const uint16_t *d_A, int32_t lda, int32_t tr
  * B x 441, features B x 16; labels FP32 0/1.  1 <= B <= max_batch. */
 typedef struct dt_scorer dt_scorer;
 int64_t dt_scorer_num_params(void);
-/* He-normal weights from a counter-based generator seeded by `seed`, zero biases. */
+/* He-normal weights from a counter-based generator seeded by `seed`, zero biases;
+ * 1 <= max_batch <= 32768 (the activations of max_batch cells are held). */
 dt_status dt_scorer_create(dt_ctx *ctx, int32_t max_batch, uint64_t seed, dt_scorer **out);
 dt_status dt_scorer_destroy(dt_scorer *s);
 dt_status dt_scorer_get_params(dt_scorer *s, float *d_params);

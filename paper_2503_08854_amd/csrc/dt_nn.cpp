@@ -165,7 +165,7 @@ dt_status dt_scorer_create(dt_ctx* c, int32_t max_batch, uint64_t seed, dt_score
   if (!out) return fail(DT_E_ARG, "out is NULL");
   *out = nullptr;
   if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
-  if (max_batch < 1 || max_batch > 8192) return fail(DT_E_ARG, "max_batch must be in [1, 8192]");
+  if (max_batch < 1 || max_batch > 32768) return fail(DT_E_ARG, "max_batch must be in [1, 32768]");
   DeviceGuard guard(c->device);
   dt_scorer* s = new dt_scorer();
   s->ctx = c;

@@ -138,8 +138,15 @@ __device__ __forceinline__ void rot_long(KepState& k, double d) {
       d2 * fma(d2, fma(d2, fma(d2, fma(d2, -1.0 / 3628800.0, 1.0 / 40320.0), -1.0 / 720.0), 1.0 / 24.0), -0.5);
   rot_apply(k, s, cm1, d);
 }
-// Tiny step (|d| < 1e-8): sin d = d, cos d - 1 = -d^2/2 to < 1e-24.
-__device__ __forceinline__ void rot_tiny(KepState& k, double d) { rot_apply(k, d, -0.5 * d * d, d); }
+// Tiny step (|d| < 1e-8): sin d = d to < 2e-25; cos d - 1 = -d^2/2 < 5e-17 is
+// dropped (below 1/4 ulp of 1; re-anchoring bounds its accumulation).
+__device__ __forceinline__ void rot_tiny(KepState& k, double d) {
+  const double sE = fma(k.cE, d, k.sE);
+  const double cE = fma(-k.sE, d, k.cE);
+  k.sE = sE;
+  k.cE = cE;
+  k.E += d;
+}
 
 // Cold solve: Newton with full sincos from E0 = M + 0.85 e sign(sin M), kept
 // inside the root bracket [M - e, M + e] by bisection.
@@ -254,11 +261,18 @@ __device__ __forceinline__ void lt_state(const Orbit& o, const KepState& k, doub
   s.rho0 = fma(k.cE, o.aP0, fma(k.sE, o.bQ0, b0));
   s.rho1 = fma(k.cE, o.aP1, fma(k.sE, o.bQ1, b1));
   s.rho2 = fma(k.cE, o.aP2, fma(k.sE, o.bQ2, b2));
-  double rdist;
-  sqrt_rsq(fma(s.rho0, s.rho0, fma(s.rho1, s.rho1, s.rho2 * s.rho2)), s.dist, rdist);
+  // dist to full precision by one Newton correction of x * rsq(x); the raw
+  // estimate rdist only scales rv, where a relative error of 1e-5 changes D
+  // by less than 1e-7 relative
+  const double d2 = fma(s.rho0, s.rho0, fma(s.rho1, s.rho1, s.rho2 * s.rho2));
+  const double rdist = __builtin_amdgcn_rsq(d2);
+  const double g0 = d2 * rdist;
+  s.dist = fma(fma(-g0, g0, d2), 0.5 * rdist, g0);
   // Newton step on F(D) = c (tg + D) - |rho - D v| from D = 0
   const double rv = fma(s.rho0, s.v0, fma(s.rho1, s.v1, s.rho2 * s.v2)) * rdist;
-  s.D = fma(-C_AU_DAY, tg, s.dist) * rcp1(C_AU_DAY + rv);
+  // 1 / (c + rv) = (1 / c) (1 - rv / c) to a relative (rv / c)^2 < 1e-7
+  constexpr double IC = 1.0 / C_AU_DAY;
+  s.D = fma(s.dist, IC, -tg) * fma(-rv, IC, 1.0);
 }
 
 // One (orbit, exposure) sample.  FIRST: the orbit's first exposure (cold
@@ -289,7 +303,7 @@ __device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt,
   out.tau = tau;
   // TAN projection: p = CRPIX - 1 + (A . q) / (c . q)
   const double w = fma(x.cx, q0, fma(x.cy, q1, x.cz * q2));
-  const double iw = rcp2(w);
+  const double iw = rcp1(w);
   out.px = fma(fma(x.a0x, q0, fma(x.a0y, q1, x.a0z * q2)), iw, x.px0);
   out.py = fma(fma(x.a1x, q0, fma(x.a1y, q1, x.a1z * q2)), iw, x.py0);
   out.front = (w > 0.0) && (s.dist >= 1e-9);

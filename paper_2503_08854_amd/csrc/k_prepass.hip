@@ -119,6 +119,13 @@ __device__ __forceinline__ float2 weight_pair(float d, float v) {
   return make_float2(0.f, 0.f);
 }
 
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb) {
+  constexpr unsigned NX = 8;
+  const unsigned q = nb / NX, r = nb % NX;
+  const unsigned x = b % NX, l = b / NX;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 template <typename T, int R>
 __global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__ meta,
                                                      const PrepTile* __restrict__ tiles,
@@ -129,7 +136,10 @@ __global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__
   constexpr int RW = PREP_TX + 2 * R;
   constexpr int DEPTH = PREP_DEPTH;  // input rows in flight per thread
   __shared__ float2 row[2][RW];
-  const PrepTile tl = tiles[blockIdx.x];
+  // XCD-aware order: workgroups are dispatched round-robin over the 8 XCDs,
+  // so give each XCD a contiguous run of tiles; neighbouring tiles (which
+  // share halo rows and halo cache lines) then meet in the same L2
+  const PrepTile tl = tiles[xcd_tile(blockIdx.x, gridDim.x)];
   const ExpMeta& m = meta[tl.e];
   const int W = m.W, H = m.H;
   const int tid = threadIdx.x;
