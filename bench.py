@@ -174,6 +174,7 @@ def bench_learned(dev, n_train=100, n_eval=50, budget=0.05):
     res.update(train_stacks=n_train * s.n_cells, train_s=t_train, loss_first=hist[0][1], loss_last=hist[-1][1])
     sc.close()
     b.patch.close()
+    b.coarse.close()
     ctx.close()
     return res
 

@@ -277,8 +277,9 @@ dt_status dt_clip_candidates(dt_patch *p, const dt_orbits *orbits, const int64_t
  * mean, std, coverage, offset of the max, fraction of exposures near the
  * track, normalised a, e, i, max over the central 7x7, zeros.  Outputs
  * (device, any may be NULL): stamps n x 441 (row dy, column dx) as BF16
- * and/or FP32, features n x 16 as BF16 and/or FP32.  Synchronises (frees its
- * track scratch). */
+ * and/or FP32, features n x 16 as BF16 and/or FP32.  Enqueued on the context
+ * stream; the representatives' tracks live in a grow-only context scratch
+ * of n * n_exp * 8 bytes. */
 dt_status dt_cell_stamps(dt_patch *p, const dt_orbits *reps, uint16_t *d_stamps_bf16, float *d_stamps_f32,
                          uint16_t *d_feats_bf16, float *d_feats_f32);
 

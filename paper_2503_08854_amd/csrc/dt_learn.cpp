@@ -14,14 +14,20 @@ dt_status dt_cell_stamps(dt_patch* p, const dt_orbits* reps, uint16_t* d_stamps_
   if (!d_stamps_bf16 && !d_stamps_f32 && !d_feats_bf16 && !d_feats_f32) return fail(DT_E_ARG, "no output");
   DeviceGuard guard(p->ctx->device);
   dt_ctx* c = p->ctx;
+  // grow-only context scratch: calls on one context's stream are ordered
   const size_t need = sizeof(int2) * (size_t)reps->n * p->n_exp;
-  int2* track = nullptr;
-  st = ctx_alloc(c, (void**)&track, need, "representative tracks");
-  if (st != DT_OK) return st;
+  if (need > c->track_bytes) {
+    (void)hipStreamSynchronize(c->stream);
+    ctx_free(c, c->track_ws, c->track_bytes);
+    c->track_ws = nullptr;
+    c->track_bytes = 0;
+    st = ctx_alloc(c, &c->track_ws, need, "representative tracks");
+    if (st != DT_OK) return st;
+    c->track_bytes = need;
+  }
   StackArgs a = stack_args(p, reps);
-  hipError_t e = launch_cell_stamps(a, track, d_stamps_bf16, d_stamps_f32, d_feats_bf16, d_feats_f32, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the track scratch is freed below
-  ctx_free(c, track, need);
+  hipError_t e = launch_cell_stamps(a, static_cast<int2*>(c->track_ws), d_stamps_bf16, d_stamps_f32, d_feats_bf16,
+                                    d_feats_f32, c->stream);
   return e == hipSuccess ? DT_OK : hip_fail(e, "cell stamps");
 }
 
