@@ -269,19 +269,26 @@ dt_status dt_clip_candidates(dt_patch *p, const dt_orbits *orbits, const int64_t
  * Orbit-grid cells: a grid stored cell-major, cell c owning orbits
  * [c * cell_size, (c + 1) * cell_size), its first member the representative.
  *
- * Coarse-stacked stamps of n representative orbits (reps, device SoA): for
- * every offset (dx, dy) in [-10, 10]^2 the constant-flux S/N of the planes
- * stacked along the representative's track (nearest pixel per exposure, the
- * same device code as dt_stack) shifted by (dx, dy), i.e. the paper's stack
- * (Sec. 3) over linear shifts; plus 16 features per cell: stamp max, centre,
- * mean, std, coverage, offset of the max, fraction of exposures near the
- * track, normalised a, e, i, max over the central 7x7, zeros.  Outputs
- * (device, any may be NULL): stamps n x 441 (row dy, column dx) as BF16
- * and/or FP32, features n x 16 as BF16 and/or FP32.  Enqueued on the context
- * stream; the representatives' tracks live in a grow-only context scratch
- * of n * n_exp * 8 bytes. */
-dt_status dt_cell_stamps(dt_patch *p, const dt_orbits *reps, uint16_t *d_stamps_bf16, float *d_stamps_f32,
-                         uint16_t *d_feats_bf16, float *d_feats_f32);
+ * Coarse-stacked stamps of n representative orbits (reps, device SoA) of
+ * cells whose members differ from the representative by at most da (AU) in
+ * semi-major axis and dm (rad) in mean anomaly.  Per exposure, three walks
+ * with the stack's device code give the pixel coordinates p (the
+ * representative), p_a (a + da) and p_m (M0 + dm); if any is behind the
+ * tangent plane the exposure is skipped.  Node (u, v) of a 21 x 21 lattice,
+ * u = (col - 10) / 10, v = (row - 10) / 10, follows
+ * q = (p + u (p_a - p)) + v (p_m - p) (FP64, in this order), rounded to the
+ * nearest pixel floor(q + 0.5); its value is the constant-flux S/N
+ * sum psi / sqrt(sum phi) over the nodes' valid pixels (inside, phi > 0),
+ * i.e. the paper's stack (Sec. 3) along the linearised tracks of the cell's
+ * members.  Plus 16 features per cell: stamp max, centre, mean, std,
+ * coverage, lattice distance of the max, fraction of exposures with the
+ * representative inside, normalised a, e, i, max over the central 7x7,
+ * zeros.  Outputs (device, any may be NULL): stamps n x 441 (row-major) as
+ * BF16 and/or FP32, features n x 16 as BF16 and/or FP32.  Enqueued on the
+ * context stream; the three walks live in a grow-only context scratch of
+ * 48 * n * n_exp bytes. */
+dt_status dt_cell_stamps(dt_patch *p, const dt_orbits *reps, double da, double dm, uint16_t *d_stamps_bf16,
+                         float *d_stamps_f32, uint16_t *d_feats_bf16, float *d_feats_f32);
 
 /* The plain stack (as dt_stack) on the orbits of n_cells selected cells
  * (device int64 cell ids; negative ids are skipped); outputs are written at

@@ -30,6 +30,8 @@ class Setup:
     el: np.ndarray
     cell_size: int
     n_cells: int
+    da: float
+    dm: float
 
 
 def load_setup(name: str = "learned") -> Setup:
@@ -37,7 +39,8 @@ def load_setup(name: str = "learned") -> Setup:
     cg = g["cell_grid"]
     el = synth.cell_grid(g["grid_field"], cg["cells"], cg["cell_size"], cg["seed"], cg["a"], cg["e"], cg["inc_deg"],
                          cg["da"], cg["dm"])
-    return Setup(g, synth.exposures_of(g), float(g["t0"]), el, int(cg["cell_size"]), int(cg["cells"]))
+    return Setup(g, synth.exposures_of(g), float(g["t0"]), el, int(cg["cell_size"]), int(cg["cells"]),
+                 float(cg["da"]), float(cg["dm"]))
 
 
 def _sum_p2(fwhm: float) -> float:
@@ -100,7 +103,7 @@ def training_set(bench: Bench, n_real: int, seed: int, pos_frac: float = 0.5, sn
         ii, ee = np.nonzero(inside)
         hits = np.stack([ee, px[ii, ee], py[ii, ee], flux[ii]], axis=1)
         bench.realize(seed * 7919 + r, hits)
-        st = dt.cell_stamps(bench.patch, bench.reps, bf16=True, f32=False)
+        st = dt.cell_stamps(bench.patch, bench.reps, s.da, s.dm, bf16=True, f32=False)
         lab = np.zeros(s.n_cells, np.float32)
         lab[cells[nh > 0]] = 1.0
         S.append(st["stamps_bf16"])
@@ -146,14 +149,15 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
             t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, cells = proposer.run_learned(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, scorer, budget,
-                                        out=out_sel)
+        _, cells = proposer.run_learned(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da, s.dm,
+                                        scorer, budget, out=out_sel)
         torch.cuda.synchronize()
         t_learn.append(time.perf_counter() - t0)
         learned_snr = out_sel[0].cpu().numpy()
         for t in out_sel:
             t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
-        proposer.run_coarse(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, budget, out=out_sel)
+        proposer.run_coarse(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da, s.dm, budget,
+                            out=out_sel)
         coarse_snr = out_sel[0].cpu().numpy()
         for t in out_sel:
             t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)

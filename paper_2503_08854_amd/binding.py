@@ -85,7 +85,7 @@ def lib():
                                  C.POINTER(_P), C.POINTER(_P), C.c_char_p, C.POINTER(DtBatchConfig),
                                  C.POINTER(C.c_double)], C.c_int),
         "dt_patch_release_images": ([_P], C.c_int),
-        "dt_cell_stamps": ([_P, C.POINTER(DtOrbits), _P, _P, _P, _P], C.c_int),
+        "dt_cell_stamps": ([_P, C.POINTER(DtOrbits), C.c_double, C.c_double, _P, _P, _P, _P], C.c_int),
         "dt_image_noise": ([_P, C.c_int32, _P, _P, C.c_int, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
         "dt_patch_noise": ([_P, _P], C.c_int),
         "dt_record_gathers": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P], C.c_int),
@@ -487,8 +487,8 @@ def clip_candidates(patch: Patch, orbits: OrbitSet, ids, kappa: float = 3.0, max
 
 
 # ------------------------------------------------------------ learned proposal
-def cell_stamps(patch: Patch, reps: OrbitSet, bf16=True, f32=True):
-    """Coarse stamps (n x 21 x 21) and features (n x 16) of representative orbits."""
+def cell_stamps(patch: Patch, reps: OrbitSet, da: float, dm: float, bf16=True, f32=True):
+    """Coarse stamps (n x 21 x 21 over the cell's (a, M0) box) and features (n x 16) of representative orbits."""
     import torch
     dev = reps.soa.device
     n = reps.n
@@ -496,7 +496,8 @@ def cell_stamps(patch: Patch, reps: OrbitSet, bf16=True, f32=True):
     sf = torch.empty((n, 21, 21), dtype=torch.float32, device=dev) if f32 else None
     fb = torch.empty((n, 16), dtype=torch.bfloat16, device=dev) if bf16 else None
     ff = torch.empty((n, 16), dtype=torch.float32, device=dev) if f32 else None
-    _check(lib().dt_cell_stamps(patch.handle, C.byref(reps.struct()), _ptr(sb), _ptr(sf), _ptr(fb), _ptr(ff)))
+    _check(lib().dt_cell_stamps(patch.handle, C.byref(reps.struct()), float(da), float(dm), _ptr(sb), _ptr(sf),
+                                _ptr(fb), _ptr(ff)))
     return dict(stamps_bf16=sb, stamps=sf, feats_bf16=fb, feats=ff)
 
 

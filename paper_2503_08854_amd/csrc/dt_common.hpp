@@ -134,8 +134,8 @@ hipError_t launch_init_params(float* w, int64_t off, int64_t n, int fan_in, uint
 
 // Coarse stamps (21 x 21) and 16 features per representative orbit; d_track
 // is n x n_exp int2 scratch.  Any output may be null.
-hipError_t launch_cell_stamps(const StackArgs& reps, int2* d_track, uint16_t* st_bf, float* st_f, uint16_t* ft_bf,
-                              float* ft_f, hipStream_t s);
+hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, double2* d_track, uint16_t* st_bf,
+                              float* st_f, uint16_t* ft_bf, float* ft_f, hipStream_t s);
 hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
                               hipStream_t s);
 

@@ -6,16 +6,18 @@ using namespace dtk;
 
 extern "C" {
 
-dt_status dt_cell_stamps(dt_patch* p, const dt_orbits* reps, uint16_t* d_stamps_bf16, float* d_stamps_f32,
-                         uint16_t* d_feats_bf16, float* d_feats_f32) {
+dt_status dt_cell_stamps(dt_patch* p, const dt_orbits* reps, double da, double dm, uint16_t* d_stamps_bf16,
+                         float* d_stamps_f32, uint16_t* d_feats_bf16, float* d_feats_f32) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
   dt_status st = check_orbits(reps);
   if (st != DT_OK) return st;
   if (!d_stamps_bf16 && !d_stamps_f32 && !d_feats_bf16 && !d_feats_f32) return fail(DT_E_ARG, "no output");
+  if (!(da > 0.0) || !(dm > 0.0) || !std::isfinite(da) || !std::isfinite(dm))
+    return fail(DT_E_DOMAIN, "cell half-widths da and dm must be finite and > 0");
   DeviceGuard guard(p->ctx->device);
   dt_ctx* c = p->ctx;
   // grow-only context scratch: calls on one context's stream are ordered
-  const size_t need = sizeof(int2) * (size_t)reps->n * p->n_exp;
+  const size_t need = sizeof(double2) * 3 * (size_t)reps->n * p->n_exp;
   if (need > c->track_bytes) {
     (void)hipStreamSynchronize(c->stream);
     ctx_free(c, c->track_ws, c->track_bytes);
@@ -26,8 +28,8 @@ dt_status dt_cell_stamps(dt_patch* p, const dt_orbits* reps, uint16_t* d_stamps_
     c->track_bytes = need;
   }
   StackArgs a = stack_args(p, reps);
-  hipError_t e = launch_cell_stamps(a, static_cast<int2*>(c->track_ws), d_stamps_bf16, d_stamps_f32, d_feats_bf16,
-                                    d_feats_f32, c->stream);
+  hipError_t e = launch_cell_stamps(a, da, dm, static_cast<double2*>(c->track_ws), d_stamps_bf16, d_stamps_f32,
+                                    d_feats_bf16, d_feats_f32, c->stream);
   return e == hipSuccess ? DT_OK : hip_fail(e, "cell stamps");
 }
 

@@ -2,13 +2,18 @@
 // restricted to selected cells (the learned-proposal path).
 //
 // A cell is a block of `cell_size` consecutive orbits of a grid whose first
-// member is the cell's representative.  The representative's track (nearest
-// pixel per exposure, same device code as the stack) is computed once; the
-// stamp is the constant-flux S/N of the matched-filter planes stacked along
-// that track shifted by every offset (dx, dy) in [-10, 10]^2, so a source on
-// any member whose track stays near a fixed offset from the representative's
-// shows as a peak.  One wavefront per cell; each lane owns 7 of the 441
-// offsets.  Per-cell features summarise the stamp and the cell's elements.
+// member is the cell's representative; the other members differ from it in
+// semi-major axis by at most da and in mean anomaly by at most dm.  Over a
+// cell, a member's pixel track is linear in (delta a / da, delta M0 / dm) to
+// a small fraction of a pixel, so the stamp is a 21 x 21 lattice in that
+// parameter box: node (u, v), u, v in {-1, -0.9, ..., 1}, follows the track
+//   p_e(u, v) = p_e + u (p_e[a + da] - p_e) + v (p_e[M0 + dm] - p_e)
+// built from three walks (representative, a + da, M0 + dm) with the stack's
+// device code, rounded to the nearest pixel; the stamp value is the
+// constant-flux S/N of the matched-filter planes stacked along it (Sec. 3).
+// A source on any member therefore shows as a peak near its (u, v).  One
+// wavefront per cell; each lane owns 7 of the 441 nodes.  Per-cell features
+// summarise the stamp and the cell's elements.
 #include "dt_stack.hpp"
 
 namespace dtk {
@@ -18,19 +23,26 @@ constexpr int SW = 2 * SH + 1;       // 21
 constexpr int SP = SW * SW;          // 441
 constexpr int NFEAT = 16;
 
-__global__ __launch_bounds__(256) void k_rep_tracks(StackArgs A, int2* __restrict__ track) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= A.n) return;
-  int2* tr = track + o * A.n_exp;
-  const double a = A.a[o], e = A.e[o], inc = A.inc[o], node = A.node[o], peri = A.peri[o], m0 = A.m0[o];
+// Three walks per cell: k = 0 the representative, k = 1 with a + da, k = 2
+// with M0 + dm; pixel coordinates per exposure (NaN behind the tangent plane
+// or for an orbit outside the domain).
+__global__ __launch_bounds__(256) void k_rep_tracks(StackArgs A, double da, double dm, double2* __restrict__ track) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * A.n) return;
+  const int64_t o = t / 3;
+  const int k = (int)(t % 3);
+  double2* tr = track + t * A.n_exp;
+  const double a = A.a[o] + (k == 1 ? da : 0.0), e = A.e[o], inc = A.inc[o], node = A.node[o], peri = A.peri[o];
+  const double m0 = A.m0[o] + (k == 2 ? dm : 0.0);
+  const double nan = __builtin_nan("");
   if (!orbit_ok(a, e, inc, node, peri, m0)) {
-    for (int ex = 0; ex < A.n_exp; ++ex) tr[ex] = make_int2((int)0x80000000, (int)0x80000000);
+    for (int ex = 0; ex < A.n_exp; ++ex) tr[ex] = make_double2(nan, nan);
     return;
   }
   Orbit ob;
   orbit_prep(a, e, inc, node, peri, m0, ob);
   walk_orbit(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
-    tr[ex] = so.front ? make_int2(so.ix, so.iy) : make_int2((int)0x80000000, (int)0x80000000);
+    tr[ex] = so.front ? make_double2(so.px, so.py) : make_double2(nan, nan);
   });
 }
 
@@ -53,35 +65,51 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 __global__ __launch_bounds__(64) void k_cell_stamps(const ExpMeta* __restrict__ meta, int n_exp,
-                                                    const float2* __restrict__ planes, const int2* __restrict__ track,
-                                                    int64_t n_cells, const double* __restrict__ ea,
-                                                    const double* __restrict__ ee, const double* __restrict__ ei,
-                                                    uint16_t* __restrict__ st_bf, float* __restrict__ st_f,
-                                                    uint16_t* __restrict__ ft_bf, float* __restrict__ ft_f) {
+                                                    const float2* __restrict__ planes,
+                                                    const double2* __restrict__ track, int64_t n_cells,
+                                                    const double* __restrict__ ea, const double* __restrict__ ee,
+                                                    const double* __restrict__ ei, uint16_t* __restrict__ st_bf,
+                                                    float* __restrict__ st_f, uint16_t* __restrict__ ft_bf,
+                                                    float* __restrict__ ft_f) {
+#pragma clang fp contract(off)
   const int64_t cell = blockIdx.x;
   if (cell >= n_cells) return;
   const int lane = threadIdx.x;
   constexpr int PER = (SP + 63) / 64;  // 7
   float ps[PER], ph[PER];
+  double u[PER], v[PER];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) ps[q] = ph[q] = 0.f;
+  for (int q = 0; q < PER; ++q) {
+    ps[q] = ph[q] = 0.f;
+    const int j = lane + 64 * q;
+    u[q] = (double)(j % SW - SH) / (double)SH;
+    v[q] = (double)(j / SW - SH) / (double)SH;
+  }
   int near = 0;
-  const int2* tr = track + cell * n_exp;
+  const double2* t0 = track + (cell * 3 + 0) * n_exp;
+  const double2* ta = track + (cell * 3 + 1) * n_exp;
+  const double2* tm = track + (cell * 3 + 2) * n_exp;
   for (int ex = 0; ex < n_exp; ++ex) {
-    const int2 t = tr[ex];
+    const double2 p0 = t0[ex], pa = ta[ex], pm = tm[ex];
     const ExpMeta& x = meta[ex];
-    if (t.x == (int)0x80000000 || t.x < -SH || t.x >= x.W + SH || t.y < -SH || t.y >= x.H + SH) continue;
-    near++;
+    const double Ax = pa.x - p0.x, Ay = pa.y - p0.y, Bx = pm.x - p0.x, By = pm.y - p0.y;
+    // skip exposures where a walk is behind the plane or the lattice misses the image
+    const double rx = fabs(Ax) + fabs(Bx) + 1.0, ry = fabs(Ay) + fabs(By) + 1.0;
+    if (!(p0.x + rx >= -0.5 && p0.x - rx < x.W - 0.5 && p0.y + ry >= -0.5 && p0.y - ry < x.H - 0.5)) continue;
+    if (!(__builtin_isfinite(pa.x) && __builtin_isfinite(pm.x))) continue;
+    near += (p0.x >= -0.5 && p0.x < x.W - 0.5 && p0.y >= -0.5 && p0.y < x.H - 0.5) ? 1 : 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int j = lane + 64 * q;
       if (j >= SP) continue;
-      const int X = t.x + j % SW - SH, Y = t.y + j / SW - SH;
-      if (X < 0 || X >= x.W || Y < 0 || Y >= x.H) continue;
-      const float2 v = planes[x.plane_off + (int64_t)Y * x.W + X];
-      if (v.y > 0.f) {
-        ps[q] += v.x;
-        ph[q] += v.y;
+      const double px = (p0.x + u[q] * Ax) + v[q] * Bx;
+      const double py = (p0.y + u[q] * Ay) + v[q] * By;
+      const double fx = floor(px + 0.5), fy = floor(py + 0.5);
+      if (!(fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H)) continue;
+      const float2 w = planes[x.plane_off + (int64_t)fy * x.W + (int64_t)fx];
+      if (w.y > 0.f) {
+        ps[q] += w.x;
+        ph[q] += w.y;
       }
     }
   }
@@ -156,10 +184,11 @@ __global__ __launch_bounds__(256) void k_stack_cells(StackArgs A, const int64_t*
   if (A.nvalid) A.nvalid[o] = nv;
 }
 
-hipError_t launch_cell_stamps(const StackArgs& reps, int2* d_track, uint16_t* st_bf, float* st_f, uint16_t* ft_bf,
-                              float* ft_f, hipStream_t s) {
+hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, double2* d_track, uint16_t* st_bf,
+                              float* st_f, uint16_t* ft_bf, float* ft_f, hipStream_t s) {
   if (reps.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rep_tracks, dim3((unsigned)((reps.n + 255) / 256)), dim3(256), 0, s, reps, d_track);
+  hipLaunchKernelGGL(k_rep_tracks, dim3((unsigned)((3 * reps.n + 255) / 256)), dim3(256), 0, s, reps, da, dm,
+                     d_track);
   hipLaunchKernelGGL(k_cell_stamps, dim3((unsigned)reps.n), dim3(64), 0, s, reps.meta, reps.n_exp, reps.planes,
                      d_track, reps.n, reps.a, reps.e, reps.inc, st_bf, st_f, ft_bf, ft_f);
   return hipGetLastError();

@@ -22,9 +22,9 @@ import numpy as np
 from . import binding as B
 
 
-def cell_inputs(patch, reps):
-    """(stamps BF16 n x 21 x 21, features BF16 n x 16, stamp max FP32 n)."""
-    out = B.cell_stamps(patch, reps, bf16=True, f32=False)
+def cell_inputs(patch, reps, da: float, dm: float):
+    """(stamps BF16 n x 21 x 21, features BF16 n x 16) over each cell's (a, M0) box."""
+    out = B.cell_stamps(patch, reps, da, dm, bf16=True, f32=False)
     return out["stamps_bf16"], out["feats_bf16"]
 
 
@@ -38,18 +38,18 @@ def select_cells(ctx, scores, budget: int):
     return idx
 
 
-def run_learned(ctx, patch, grid, reps, cell_size: int, scorer, budget: int, out=None):
+def run_learned(ctx, patch, grid, reps, cell_size: int, da: float, dm: float, scorer, budget: int, out=None):
     """Stamps -> scores -> top cells -> stack on their orbits. Returns (outputs, selected cell ids)."""
-    st, ft = cell_inputs(patch, reps)
+    st, ft = cell_inputs(patch, reps, da, dm)
     z = score_cells(scorer, st, ft)
     cells = select_cells(ctx, z, budget)
     out = B.stack_cells(patch, grid, cells, cell_size, out=out)
     return out, cells
 
 
-def run_coarse(ctx, patch, grid, reps, cell_size: int, budget: int, out=None):
+def run_coarse(ctx, patch, grid, reps, cell_size: int, da: float, dm: float, budget: int, out=None):
     """The non-learned counterpart: rank cells by the stamp maximum (feature 0)."""
-    o = B.cell_stamps(patch, reps, bf16=False, f32=True)
+    o = B.cell_stamps(patch, reps, da, dm, bf16=False, f32=True)
     cells = select_cells(ctx, o["feats"][:, 0].contiguous(), budget)
     out = B.stack_cells(patch, grid, cells, cell_size, out=out)
     return out, cells
