@@ -22,16 +22,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # FP64 operations per dense sample on the stack kernel's common path as
-# written (warm Kepler step with short rotation and one Newton step, state,
-# one light-time Newton step, TAN projection, rounding): an FMA counts 2,
-# add / mul / floor / hardware reciprocal or rsqrt estimate 1.
-FLOPS_PER_SAMPLE = 157
+# written (warm Kepler step: 2nd-order start 7, short rotation 20, one Newton
+# step with a tiny rotation 16; mean anomaly and predicted light time 6;
+# observer offset 3; position, velocity, distance and the light-time
+# correction 47; corrected position, projection with one-refinement
+# reciprocal and rounding 37): an FMA counts 2, add / mul / floor / hardware
+# reciprocal or rsqrt estimate 1.
+FLOPS_PER_SAMPLE = 136
+# HBM bytes of one full-size k_stack launch on the survey workload from the
+# committed FETCH_SIZE / WRITE_SIZE passes; reported only while the kernel's
+# sources are the ones those counters were taken on.
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_stack_survey_traffic.json")
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stack_traffic(workload_name):
+    import hashlib
+    import json as _json
+    if workload_name != "survey" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = _json.load(open(TRAFFIC_RECORD))
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update((hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() + "  " + f + "\n").encode())
+    return float(rec["traffic_bytes"]) if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def workload(name, device):
@@ -191,6 +210,7 @@ def main():
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
+    ap.add_argument("--skip-gather", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the stack shards by orbit and "
@@ -268,7 +288,7 @@ def main():
                    "orbits": n, "exposures": ne, "valid_samples": int(nv[nv > 0].sum()),
                    "phase_ms": {"prepass": pre, "stack": stk, "topk": tk}},
         "roofline": {"bound": "alu", "kernel": "k_stack", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": stack_traffic(args.workload),
                      "flops_per_sample": FLOPS_PER_SAMPLE},
         "detections": int(cnt[0]),
     }
@@ -279,10 +299,11 @@ def main():
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(w, snr)
         log(f"cpu baseline: {rec['cpu_baseline']['value']:.3g} samples/s on {rec['cpu_baseline']['cores']} threads")
-    rec["gather"] = gather_yardstick(patch, w, dev)
-    G = rec["gather"]
-    log(f"gather yardstick: stack {G['stack_ms']:.3f} ms vs replay {G['replay_ms']:.3f} ms on {G['orbits']} orbits "
-        f"({G['frac_of_achievable_gather']:.2f} of the achievable gather rate)")
+    if not args.skip_gather:
+        rec["gather"] = gather_yardstick(patch, w, dev)
+        G = rec["gather"]
+        log(f"gather yardstick: stack {G['stack_ms']:.3f} ms vs replay {G['replay_ms']:.3f} ms on {G['orbits']} "
+            f"orbits ({G['frac_of_achievable_gather']:.2f} of the achievable gather rate)")
     patch.close()
     ctx.close()
     del w, orb, out, patch
