@@ -171,7 +171,7 @@ def bench_batched(dev, steps=5):
     return res
 
 
-def bench_learned(dev, n_train=100, n_eval=50, budget=0.05):
+def bench_learned(dev, n_train=100, n_eval=50, budget=0.02, budget_wide=0.05, n_eval_wide=20):
     """Learned vs plain recall at S/N >= 5 and speedup on the cell-structured survey grid."""
     import torch
     import learned_eval as le
@@ -191,6 +191,9 @@ def bench_learned(dev, n_train=100, n_eval=50, budget=0.05):
     del X, F, Y
     res = le.evaluate(b, sc, budget_frac=budget, n_real=n_eval)
     res.update(train_stacks=n_train * s.n_cells, train_s=t_train, loss_first=hist[0][1], loss_last=hist[-1][1])
+    wide = le.evaluate(b, sc, budget_frac=budget_wide, n_real=n_eval_wide)
+    res["wider_budget"] = {k: wide[k] for k in ("budget_frac", "injections", "recall_ratio_learned",
+                                                 "recall_ratio_coarse", "recall_ratio_coarse_to_fine", "speedup")}
     sc.close()
     b.patch.close()
     b.coarse.close()

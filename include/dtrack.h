@@ -322,6 +322,14 @@ dt_status dt_scorer_get_params(dt_scorer *s, float *d_params);
 dt_status dt_scorer_set_params(dt_scorer *s, const float *d_params);
 dt_status dt_scorer_forward(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats, int32_t B,
                             float *d_logits);
+/* Inference logits of any number B >= 0 of cells in one fused kernel (no
+ * activations leave the chip; no batch limit): the same layers, BF16 rounding
+ * points and FP32 biases as dt_scorer_forward; the fully connected 1152 -> 64
+ * layer accumulates its K in one sequence, so logits may differ from
+ * dt_scorer_forward's (which may split that K) by FP32 rounding and the BF16
+ * roundings it moves.  d_logits: device, B floats. */
+dt_status dt_scorer_infer(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats, int32_t B,
+                          float *d_logits);
 /* Loss (device float[1], may be NULL) and gradient (device FP32 vector of
  * num_params values, may be NULL) of the mean BCE at the current weights. */
 dt_status dt_scorer_grad(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats, const float *d_labels,

@@ -90,6 +90,7 @@ def lib():
         "dt_patch_noise": ([_P, _P], C.c_int),
         "dt_record_gathers": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P], C.c_int),
         "dt_gather_replay": ([_P, _P, C.c_int64, _P], C.c_int),
+        "dt_scorer_infer": ([_P, _P, _P, C.c_int32, _P], C.c_int),
         "dt_generate_orbits": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P],
                                C.c_int),
         "dt_stack_generated": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P], C.c_int),
@@ -560,6 +561,15 @@ class Scorer:
             e = min(B, s + self.max_batch)
             _check(lib().dt_scorer_forward(self._h, _ptr(stamps_bf16[s:e].contiguous()),
                                            _ptr(feats_bf16[s:e].contiguous()), e - s, _ptr(z[s:])))
+        return z
+
+    def infer(self, stamps_bf16, feats_bf16, out=None):
+        """Logits of any number of cells with the fused inference kernel."""
+        import torch
+        B = stamps_bf16.shape[0]
+        z = out if out is not None else torch.empty(B, dtype=torch.float32, device=stamps_bf16.device)
+        _check(lib().dt_scorer_infer(self._h, _ptr(stamps_bf16.contiguous()), _ptr(feats_bf16.contiguous()), B,
+                                     _ptr(z)))
         return z
 
     def grad(self, stamps_bf16, feats_bf16, labels):

@@ -143,6 +143,18 @@ hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_
 hipError_t launch_clip(const StackArgs& a, const int64_t* d_ids, int64_t m, double kappa, int max_iter,
                        float2* d_buf, float* snr, float* flux, int32_t* nkept, hipStream_t s);
 
+// Fused inference forward of the cell scorer.
+struct ScorerFusedArgs {
+  const uint16_t* stamps;  // B x 441 BF16
+  const uint16_t* feats;   // B x 16 BF16
+  int B;
+  const uint16_t* wb;      // BF16 weights, layer-wise [K][N]
+  const float* w;          // FP32 master parameters (the biases are read here)
+  int64_t w_off[7], b_off[7];
+  float* z;                // B logits
+};
+hipError_t launch_scorer_fused(const ScorerFusedArgs& a, hipStream_t s);
+
 // Replay of a recorded gather stream (measurement yardstick).
 hipError_t launch_gather_replay(const float2* planes, const uint32_t* off, int64_t m, int n_exp, float* snr,
                                 hipStream_t s);

@@ -262,6 +262,28 @@ dt_status dt_scorer_forward(dt_scorer* s, const uint16_t* d_stamps, const uint16
   return e == hipSuccess ? DT_OK : hip_fail(e, "scorer forward");
 }
 
+dt_status dt_scorer_infer(dt_scorer* s, const uint16_t* d_stamps, const uint16_t* d_feats, int32_t B,
+                          float* d_logits) {
+  if (!s || !s->ctx) return fail(DT_E_ARG, "invalid scorer");
+  if (B < 0) return fail(DT_E_ARG, "B < 0");
+  if (B == 0) return DT_OK;
+  if (!d_stamps || !d_feats || !d_logits) return fail(DT_E_ARG, "NULL input or output");
+  DeviceGuard guard(s->ctx->device);
+  ScorerFusedArgs a{};
+  a.stamps = d_stamps;
+  a.feats = d_feats;
+  a.B = B;
+  a.wb = s->wb;
+  a.w = s->w;
+  for (int i = 0; i < NL; ++i) {
+    a.w_off[i] = s->L[i].w;
+    a.b_off[i] = s->L[i].b;
+  }
+  a.z = d_logits;
+  hipError_t e = launch_scorer_fused(a, s->ctx->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "scorer inference");
+}
+
 dt_status dt_scorer_grad(dt_scorer* s, const uint16_t* d_stamps, const uint16_t* d_feats, const float* d_labels,
                          int32_t B, float* d_loss, float* d_grad) {
   dt_status st = check_io(s, d_stamps, d_feats, B);

@@ -25,24 +25,33 @@ constexpr int NFEAT = 16;
 
 // Three walks per cell: k = 0 the representative, k = 1 with a + da, k = 2
 // with M0 + dm; pixel coordinates per exposure (NaN behind the tangent plane
-// or for an orbit outside the domain).
+// or for an orbit outside the domain).  Each thread walks one chunk of
+// TRACK_CHUNK exposures from a cold start, so the launch has enough threads
+// to fill the chip for a few thousand cells.
+constexpr int TRACK_CHUNK = 25;
+
 __global__ __launch_bounds__(256) void k_rep_tracks(StackArgs A, double da, double dm, double2* __restrict__ track) {
+  const int n_chunks = (A.n_exp + TRACK_CHUNK - 1) / TRACK_CHUNK;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * A.n) return;
-  const int64_t o = t / 3;
-  const int k = (int)(t % 3);
-  double2* tr = track + t * A.n_exp;
+  if (t >= 3 * A.n * n_chunks) return;
+  const int chunk = (int)(t % n_chunks);
+  const int64_t w = t / n_chunks;  // walk: orbit w / 3, variant w % 3
+  const int64_t o = w / 3;
+  const int k = (int)(w % 3);
+  const int ex0 = chunk * TRACK_CHUNK;
+  const int cnt = min(TRACK_CHUNK, A.n_exp - ex0);
+  double2* tr = track + w * A.n_exp + ex0;
   const double a = A.a[o] + (k == 1 ? da : 0.0), e = A.e[o], inc = A.inc[o], node = A.node[o], peri = A.peri[o];
   const double m0 = A.m0[o] + (k == 2 ? dm : 0.0);
   const double nan = __builtin_nan("");
   if (!orbit_ok(a, e, inc, node, peri, m0)) {
-    for (int ex = 0; ex < A.n_exp; ++ex) tr[ex] = make_double2(nan, nan);
+    for (int i = 0; i < cnt; ++i) tr[i] = make_double2(nan, nan);
     return;
   }
   Orbit ob;
   orbit_prep(a, e, inc, node, peri, m0, ob);
-  walk_orbit(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
-    tr[ex] = so.front ? make_double2(so.px, so.py) : make_double2(nan, nan);
+  walk_orbit(ob, A.meta + ex0, cnt, A.epoch, [&](int i, const SampleOut& so) {
+    tr[i] = so.front ? make_double2(so.px, so.py) : make_double2(nan, nan);
   });
 }
 
@@ -89,27 +98,49 @@ __global__ __launch_bounds__(64) void k_cell_stamps(const ExpMeta* __restrict__ 
   const double2* t0 = track + (cell * 3 + 0) * n_exp;
   const double2* ta = track + (cell * 3 + 1) * n_exp;
   const double2* tm = track + (cell * 3 + 2) * n_exp;
-  for (int ex = 0; ex < n_exp; ++ex) {
-    const double2 p0 = t0[ex], pa = ta[ex], pm = tm[ex];
+  // exposures where the three walks are in front and the lattice can touch
+  // the image, found 64 at a time (one per lane), then visited in order
+  auto usable = [&](int ex, double2& p0, double& Ax, double& Ay, double& Bx, double& By) {
+    p0 = t0[ex];
+    const double2 pa = ta[ex], pm = tm[ex];
     const ExpMeta& x = meta[ex];
-    const double Ax = pa.x - p0.x, Ay = pa.y - p0.y, Bx = pm.x - p0.x, By = pm.y - p0.y;
-    // skip exposures where a walk is behind the plane or the lattice misses the image
+    Ax = pa.x - p0.x;
+    Ay = pa.y - p0.y;
+    Bx = pm.x - p0.x;
+    By = pm.y - p0.y;
     const double rx = fabs(Ax) + fabs(Bx) + 1.0, ry = fabs(Ay) + fabs(By) + 1.0;
-    if (!(p0.x + rx >= -0.5 && p0.x - rx < x.W - 0.5 && p0.y + ry >= -0.5 && p0.y - ry < x.H - 0.5)) continue;
-    if (!(__builtin_isfinite(pa.x) && __builtin_isfinite(pm.x))) continue;
-    near += (p0.x >= -0.5 && p0.x < x.W - 0.5 && p0.y >= -0.5 && p0.y < x.H - 0.5) ? 1 : 0;
+    return __builtin_isfinite(pa.x) && __builtin_isfinite(pm.x) && p0.x + rx >= -0.5 && p0.x - rx < x.W - 0.5 &&
+           p0.y + ry >= -0.5 && p0.y - ry < x.H - 0.5;
+  };
+  for (int c0 = 0; c0 < n_exp; c0 += 64) {
+    bool use = false;
+    if (c0 + lane < n_exp) {
+      double2 p0;
+      double Ax, Ay, Bx, By;
+      use = usable(c0 + lane, p0, Ax, Ay, Bx, By);
+    }
+    uint64_t mask = __ballot(use);
+    while (mask) {
+      const int ex = c0 + __builtin_ctzll(mask);
+      mask &= mask - 1;
+      double2 p0;
+      double Ax, Ay, Bx, By;
+      (void)usable(ex, p0, Ax, Ay, Bx, By);
+      const ExpMeta& x = meta[ex];
+      near += (p0.x >= -0.5 && p0.x < x.W - 0.5 && p0.y >= -0.5 && p0.y < x.H - 0.5) ? 1 : 0;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int j = lane + 64 * q;
-      if (j >= SP) continue;
-      const double px = (p0.x + u[q] * Ax) + v[q] * Bx;
-      const double py = (p0.y + u[q] * Ay) + v[q] * By;
-      const double fx = floor(px + 0.5), fy = floor(py + 0.5);
-      if (!(fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H)) continue;
-      const float2 w = planes[x.plane_off + (int64_t)fy * x.W + (int64_t)fx];
-      if (w.y > 0.f) {
-        ps[q] += w.x;
-        ph[q] += w.y;
+      for (int q = 0; q < PER; ++q) {
+        const int j = lane + 64 * q;
+        if (j >= SP) continue;
+        const double px = (p0.x + u[q] * Ax) + v[q] * Bx;
+        const double py = (p0.y + u[q] * Ay) + v[q] * By;
+        const double fx = floor(px + 0.5), fy = floor(py + 0.5);
+        if (!(fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H)) continue;
+        const float2 w = planes[x.plane_off + (int64_t)fy * x.W + (int64_t)fx];
+        if (w.y > 0.f) {
+          ps[q] += w.x;
+          ph[q] += w.y;
+        }
       }
     }
   }
@@ -187,8 +218,8 @@ __global__ __launch_bounds__(256) void k_stack_cells(StackArgs A, const int64_t*
 hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, double2* d_track, uint16_t* st_bf,
                               float* st_f, uint16_t* ft_bf, float* ft_f, hipStream_t s) {
   if (reps.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rep_tracks, dim3((unsigned)((3 * reps.n + 255) / 256)), dim3(256), 0, s, reps, da, dm,
-                     d_track);
+  const int64_t walks = 3 * reps.n * ((reps.n_exp + TRACK_CHUNK - 1) / TRACK_CHUNK);
+  hipLaunchKernelGGL(k_rep_tracks, dim3((unsigned)((walks + 255) / 256)), dim3(256), 0, s, reps, da, dm, d_track);
   hipLaunchKernelGGL(k_cell_stamps, dim3((unsigned)reps.n), dim3(64), 0, s, reps.meta, reps.n_exp, reps.planes,
                      d_track, reps.n, reps.a, reps.e, reps.inc, st_bf, st_f, ft_bf, ft_f);
   return hipGetLastError();

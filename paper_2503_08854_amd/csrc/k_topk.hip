@@ -28,24 +28,65 @@ __device__ __forceinline__ float key_val(uint64_t k) {
 
 __device__ __forceinline__ int64_t key_idx(uint64_t k) { return (int64_t)(0xFFFFFFFFu - (uint32_t)(k & 0xFFFFFFFFu)); }
 
-// Sort TOPK_T keys in LDS, descending.
-__device__ __forceinline__ void bitonic_desc(uint64_t* s) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of the tile, descending.  Thread t holds keys
+// [PER t, PER t + PER) in r[]; a compare-exchange at distance j runs in
+// registers when j < PER, between lanes of one wavefront (shuffles) when
+// PER <= j < 64 PER, and through LDS with a barrier only when j >= 64 PER
+// (6 of the 91 stages for 8192 keys).  On return s holds the sorted tile.
+template <int PER>
+__device__ __forceinline__ void bitonic_desc(uint64_t (&r)[PER], uint64_t* s) {
+  const int t = threadIdx.x;
   for (int k = 2; k <= TOPK_T; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int p = tid; p < TOPK_T / 2; p += TOPK_THREADS) {
-        int lo = 2 * j * (p / j) + (p % j);
-        int hi = lo + j;
-        uint64_t a = s[lo], b = s[hi];
-        bool desc = (lo & k) == 0;
-        if (desc ? (a < b) : (a > b)) {
-          s[lo] = b;
-          s[hi] = a;
+    for (int j = k >> 1; j >= PER; j >>= 1) {
+      if (j >= 64 * PER) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int e = PER * t + q;
+          const uint64_t o = s[e ^ j];
+          const bool keep_max = ((e & j) == 0) == ((e & k) == 0);
+          r[q] = keep_max ? (r[q] > o ? r[q] : o) : (r[q] < o ? r[q] : o);
+        }
+        __syncthreads();
+      } else {
+        const int m = j / PER;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int e = PER * t + q;
+          const uint64_t o = shfl_xor64(r[q], m);
+          const bool keep_max = ((e & j) == 0) == ((e & k) == 0);
+          r[q] = keep_max ? (r[q] > o ? r[q] : o) : (r[q] < o ? r[q] : o);
         }
       }
-      __syncthreads();
+    }
+#pragma unroll
+    for (int jj = PER / 2; jj > 0; jj >>= 1) {
+      if (jj <= (k >> 1)) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          if (q & jj) continue;
+          const int e = PER * t + q;
+          const uint64_t a = r[q], b = r[q | jj];
+          const bool desc = (e & k) == 0;
+          if (desc ? (a < b) : (a > b)) {
+            r[q] = b;
+            r[q | jj] = a;
+          }
+        }
+      }
     }
   }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
+  __syncthreads();
 }
 
 // One tournament round.  Input either S/N values (snr != null, key built from
@@ -100,7 +141,7 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __rest
     for (int j = total + threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = 0;
     return;
   }
-  bitonic_desc(s);
+  bitonic_desc<PER>(mine, s);
   for (int j = threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = s[j];
 }
 

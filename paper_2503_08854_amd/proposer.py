@@ -2,7 +2,7 @@
 
 Pipeline, every numerical step in the library's kernels:
   1. coarse stamps + features of every cell's representative (dt_cell_stamps);
-  2. the scorer's logit per cell (BF16 MFMA forward);
+  2. the scorer's logit per cell (fused BF16 MFMA inference kernel);
   3. the `budget` best cells by logit (dt_topk on the logits);
   4. the plain stack on the orbits of those cells only (dt_stack_cells).
 The exhaustive stack over every orbit stays the fallback and the judge.
@@ -29,7 +29,7 @@ def cell_inputs(patch, reps, da: float, dm: float):
 
 
 def score_cells(scorer, stamps_bf16, feats_bf16):
-    return scorer.forward(stamps_bf16, feats_bf16)
+    return scorer.infer(stamps_bf16, feats_bf16)
 
 
 def select_cells(ctx, scores, budget: int):

@@ -136,6 +136,33 @@ def test_scorer_forward_and_gradients_vs_oracle(ctx):
     assert gu["b7"][0] == pytest.approx(np.mean(1 / (1 + np.exp(-zo)) - Y), rel=2e-2, abs=1e-4)
 
 
+def test_scorer_fused_inference_matches_forward_and_oracle(ctx):
+    """The fused inference kernel against the layer-by-layer forward (same
+    rounding points; only the 1152-deep layer's summation order may differ)
+    and the FP64 oracle, on a ragged last group and on more groups than the
+    grid has workgroups."""
+    import torch
+    import paper_2503_08854_amd as dt
+    sc, th, thb, X, F, Y, Xt, Ft, Yt = _scorer_and_batch(ctx, B=37)
+    z = sc.infer(Xt, Ft).cpu().numpy()
+    zf = sc.forward(Xt, Ft).cpu().numpy()
+    zo = nn.forward(thb, X, F)
+    assert _rel(z, zo) < 1e-2
+    assert _rel(z, zf) < 2e-3
+    # 5000 cells: 313 groups of 16 over at most one workgroup per CU
+    big = dt.Scorer(ctx, max_batch=1024, seed=5)
+    rng = np.random.default_rng(11)
+    Xb = torch.from_numpy(rng.standard_normal((5000, 21, 21))).to(torch.bfloat16).cuda()
+    Fb = torch.from_numpy(rng.standard_normal((5000, 16))).to(torch.bfloat16).cuda()
+    zi = big.infer(Xb, Fb).cpu().numpy()
+    zl = big.forward(Xb, Fb).cpu().numpy()
+    assert np.all(np.isfinite(zi))
+    assert _rel(zi, zl) < 2e-3, _rel(zi, zl)
+    assert np.max(np.abs(zi - zl)) < 2e-2 * max(1.0, np.max(np.abs(zl)))
+    assert big.infer(Xb[:0], Fb[:0]).numel() == 0
+    big.close()
+
+
 def test_adam_step_matches_oracle(ctx):
     import torch
     sc, th, thb, X, F, Y, Xt, Ft, Yt = _scorer_and_batch(ctx, seed=5)
