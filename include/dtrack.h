@@ -285,8 +285,8 @@ dt_status dt_clip_candidates(dt_patch *p, const dt_orbits *orbits, const int64_t
  * representative inside, normalised a, e, i, max over the central 7x7,
  * zeros.  Outputs (device, any may be NULL): stamps n x 441 (row-major) as
  * BF16 and/or FP32, features n x 16 as BF16 and/or FP32.  Enqueued on the
- * context stream; the three walks live in a grow-only context scratch of
- * 48 * n * n_exp bytes. */
+ * context stream; patches of at most 1024 exposures (the walks of a cell
+ * are held on chip). */
 dt_status dt_cell_stamps(dt_patch *p, const dt_orbits *reps, double da, double dm, uint16_t *d_stamps_bf16,
                          float *d_stamps_f32, uint16_t *d_feats_bf16, float *d_feats_f32);
 

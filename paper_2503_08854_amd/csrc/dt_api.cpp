@@ -186,7 +186,6 @@ dt_status dt_ctx_destroy(dt_ctx* c) {
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   ctx_free(c, c->topk_scratch, c->topk_bytes);
   ctx_free(c, c->noise_ws, c->noise_bytes);
-  ctx_free(c, c->track_ws, c->track_bytes);
   ctx_free(c, c->d_counter, sizeof(unsigned long long));
   c->alive = false;
   delete c;

@@ -134,8 +134,9 @@ hipError_t launch_init_params(float* w, int64_t off, int64_t n, int fan_in, uint
 
 // Coarse stamps (21 x 21) and 16 features per representative orbit; d_track
 // is n x n_exp int2 scratch.  Any output may be null.
-hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, double2* d_track, uint16_t* st_bf,
-                              float* st_f, uint16_t* ft_bf, float* ft_f, hipStream_t s);
+constexpr int STAMP_MAX_EXP = 1024;  // the stamps keep three walks of every exposure in LDS
+hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, uint16_t* st_bf, float* st_f,
+                              uint16_t* ft_bf, float* ft_f, hipStream_t s);
 hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
                               hipStream_t s);
 
@@ -149,8 +150,10 @@ struct ScorerFusedArgs {
   const uint16_t* feats;   // B x 16 BF16
   int B;
   const uint16_t* wb;      // BF16 weights, layer-wise [K][N]
+  uint16_t* wt;            // scratch: the BF16 weights transposed, layer i at t_off[i] as [N][K]
   const float* w;          // FP32 master parameters (the biases are read here)
-  int64_t w_off[7], b_off[7];
+  int64_t w_off[7], b_off[7], t_off[8];
+  int K[7], N[7];
   float* z;                // B logits
 };
 hipError_t launch_scorer_fused(const ScorerFusedArgs& a, hipStream_t s);

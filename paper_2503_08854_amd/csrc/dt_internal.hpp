@@ -27,8 +27,6 @@ struct dt_ctx {
   unsigned long long* d_counter = nullptr;
   void* noise_ws = nullptr;  // staging + selection state of dt_image_noise
   size_t noise_bytes = 0;
-  void* track_ws = nullptr;  // representative tracks of dt_cell_stamps
-  size_t track_bytes = 0;
   dtk::BatchGraph* graph = nullptr;  // last captured batched launch
   hipStream_t capture_stream = nullptr;
   bool alive = true;

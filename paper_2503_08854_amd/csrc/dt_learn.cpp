@@ -16,20 +16,9 @@ dt_status dt_cell_stamps(dt_patch* p, const dt_orbits* reps, double da, double d
     return fail(DT_E_DOMAIN, "cell half-widths da and dm must be finite and > 0");
   DeviceGuard guard(p->ctx->device);
   dt_ctx* c = p->ctx;
-  // grow-only context scratch: calls on one context's stream are ordered
-  const size_t need = sizeof(double2) * 3 * (size_t)reps->n * p->n_exp;
-  if (need > c->track_bytes) {
-    (void)hipStreamSynchronize(c->stream);
-    ctx_free(c, c->track_ws, c->track_bytes);
-    c->track_ws = nullptr;
-    c->track_bytes = 0;
-    st = ctx_alloc(c, &c->track_ws, need, "representative tracks");
-    if (st != DT_OK) return st;
-    c->track_bytes = need;
-  }
+  if (p->n_exp > STAMP_MAX_EXP) return fail(DT_E_ARG, "cell stamps support at most %d exposures", STAMP_MAX_EXP);
   StackArgs a = stack_args(p, reps);
-  hipError_t e = launch_cell_stamps(a, da, dm, static_cast<double2*>(c->track_ws), d_stamps_bf16, d_stamps_f32,
-                                    d_feats_bf16, d_feats_f32, c->stream);
+  hipError_t e = launch_cell_stamps(a, da, dm, d_stamps_bf16, d_stamps_f32, d_feats_bf16, d_feats_f32, c->stream);
   return e == hipSuccess ? DT_OK : hip_fail(e, "cell stamps");
 }
 

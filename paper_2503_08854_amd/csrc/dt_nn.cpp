@@ -52,6 +52,7 @@ struct dt_scorer {
   uint16_t* wb = nullptr;
   // activations (BF16) and backward buffers
   uint16_t *col1, *h1, *col2, *h2, *col3, *h3, *cat, *h6;
+  uint16_t* wt = nullptr;  // transposed BF16 weights for the fused inference kernel
   float* z;
   float *dz, *df, *dbig, *dmid;
   uint16_t *dz_b, *d_b, *d_mid_b;
@@ -182,6 +183,7 @@ dt_status dt_scorer_create(dt_ctx* c, int32_t max_batch, uint64_t seed, dt_score
   A(&s->v, s->np, "scorer Adam v");
   A(&s->g, s->np, "scorer gradients");
   A(&s->wb, s->np, "scorer BF16 weights");
+  A(&s->wt, s->np, "scorer transposed BF16 weights");
   A(&s->col1, B * 441 * 9, "scorer col1");
   A(&s->h1, B * 441 * 16, "scorer h1");
   A(&s->col2, B * 121 * 144, "scorer col2");
@@ -275,10 +277,17 @@ dt_status dt_scorer_infer(dt_scorer* s, const uint16_t* d_stamps, const uint16_t
   a.B = B;
   a.wb = s->wb;
   a.w = s->w;
+  int64_t t = 0;
   for (int i = 0; i < NL; ++i) {
     a.w_off[i] = s->L[i].w;
     a.b_off[i] = s->L[i].b;
+    a.K[i] = s->L[i].K;
+    a.N[i] = s->L[i].N;
+    a.t_off[i] = t;
+    t += (int64_t)s->L[i].K * s->L[i].N;
   }
+  a.t_off[NL] = t;
+  a.wt = s->wt;
   a.z = d_logits;
   hipError_t e = launch_scorer_fused(a, s->ctx->stream);
   return e == hipSuccess ? DT_OK : hip_fail(e, "scorer inference");

@@ -23,38 +23,6 @@ constexpr int SW = 2 * SH + 1;       // 21
 constexpr int SP = SW * SW;          // 441
 constexpr int NFEAT = 16;
 
-// Three walks per cell: k = 0 the representative, k = 1 with a + da, k = 2
-// with M0 + dm; pixel coordinates per exposure (NaN behind the tangent plane
-// or for an orbit outside the domain).  Each thread walks one chunk of
-// TRACK_CHUNK exposures from a cold start, so the launch has enough threads
-// to fill the chip for a few thousand cells.
-constexpr int TRACK_CHUNK = 25;
-
-__global__ __launch_bounds__(256) void k_rep_tracks(StackArgs A, double da, double dm, double2* __restrict__ track) {
-  const int n_chunks = (A.n_exp + TRACK_CHUNK - 1) / TRACK_CHUNK;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * A.n * n_chunks) return;
-  const int chunk = (int)(t % n_chunks);
-  const int64_t w = t / n_chunks;  // walk: orbit w / 3, variant w % 3
-  const int64_t o = w / 3;
-  const int k = (int)(w % 3);
-  const int ex0 = chunk * TRACK_CHUNK;
-  const int cnt = min(TRACK_CHUNK, A.n_exp - ex0);
-  double2* tr = track + w * A.n_exp + ex0;
-  const double a = A.a[o] + (k == 1 ? da : 0.0), e = A.e[o], inc = A.inc[o], node = A.node[o], peri = A.peri[o];
-  const double m0 = A.m0[o] + (k == 2 ? dm : 0.0);
-  const double nan = __builtin_nan("");
-  if (!orbit_ok(a, e, inc, node, peri, m0)) {
-    for (int i = 0; i < cnt; ++i) tr[i] = make_double2(nan, nan);
-    return;
-  }
-  Orbit ob;
-  orbit_prep(a, e, inc, node, peri, m0, ob);
-  walk_orbit(ob, A.meta + ex0, cnt, A.epoch, [&](int i, const SampleOut& so) {
-    tr[i] = so.front ? make_double2(so.px, so.py) : make_double2(nan, nan);
-  });
-}
-
 __device__ __forceinline__ uint16_t f2bf_s(float f) {
   uint32_t u = __float_as_uint(f);
   if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
@@ -73,17 +41,46 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
-__global__ __launch_bounds__(64) void k_cell_stamps(const ExpMeta* __restrict__ meta, int n_exp,
-                                                    const float2* __restrict__ planes,
-                                                    const double2* __restrict__ track, int64_t n_cells,
-                                                    const double* __restrict__ ea, const double* __restrict__ ee,
-                                                    const double* __restrict__ ei, uint16_t* __restrict__ st_bf,
+// One wavefront per cell.  The three walks (k = 0 the representative, k = 1
+// with a + da, k = 2 with M0 + dm) are split over 63 lanes, lane = 21 k + c
+// walking chunk c of the exposures from a cold start; their pixel
+// coordinates (NaN behind the tangent plane, or for an orbit outside the
+// domain) go to this wave's LDS, 3 x n_exp x 16 bytes.
+constexpr int STAMP_CHUNKS = 21;
+
+__global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, double dm, uint16_t* __restrict__ st_bf,
                                                     float* __restrict__ st_f, uint16_t* __restrict__ ft_bf,
                                                     float* __restrict__ ft_f) {
 #pragma clang fp contract(off)
+  extern __shared__ double2 trk[];  // [3][n_exp]
   const int64_t cell = blockIdx.x;
-  if (cell >= n_cells) return;
+  if (cell >= R.n) return;
   const int lane = threadIdx.x;
+  const ExpMeta* __restrict__ meta = R.meta;
+  const int n_exp = R.n_exp;
+  const float2* __restrict__ planes = R.planes;
+  const double nan = __builtin_nan("");
+  if (lane < 3 * STAMP_CHUNKS) {
+    const int k = lane / STAMP_CHUNKS, c = lane % STAMP_CHUNKS;
+    const int ch = (n_exp + STAMP_CHUNKS - 1) / STAMP_CHUNKS;
+    const int ex0 = c * ch;
+    const int cnt = min(ch, n_exp - ex0);
+    if (cnt > 0) {
+      double2* tr = trk + k * n_exp + ex0;
+      const double a = R.a[cell] + (k == 1 ? da : 0.0), e = R.e[cell], inc = R.inc[cell], node = R.node[cell];
+      const double peri = R.peri[cell], m0 = R.m0[cell] + (k == 2 ? dm : 0.0);
+      if (!orbit_ok(a, e, inc, node, peri, m0)) {
+        for (int i = 0; i < cnt; ++i) tr[i] = make_double2(nan, nan);
+      } else {
+        Orbit ob;
+        orbit_prep(a, e, inc, node, peri, m0, ob);
+        walk_orbit(ob, meta + ex0, cnt, R.epoch, [&](int i, const SampleOut& so) {
+          tr[i] = so.front ? make_double2(so.px, so.py) : make_double2(nan, nan);
+        });
+      }
+    }
+  }
+  __syncthreads();
   constexpr int PER = (SP + 63) / 64;  // 7
   float ps[PER], ph[PER];
   double u[PER], v[PER];
@@ -94,10 +91,13 @@ __global__ __launch_bounds__(64) void k_cell_stamps(const ExpMeta* __restrict__ 
     u[q] = (double)(j % SW - SH) / (double)SH;
     v[q] = (double)(j / SW - SH) / (double)SH;
   }
+  const double* ea = R.a;
+  const double* ee = R.e;
+  const double* ei = R.inc;
   int near = 0;
-  const double2* t0 = track + (cell * 3 + 0) * n_exp;
-  const double2* ta = track + (cell * 3 + 1) * n_exp;
-  const double2* tm = track + (cell * 3 + 2) * n_exp;
+  const double2* t0 = trk;
+  const double2* ta = trk + n_exp;
+  const double2* tm = trk + 2 * n_exp;
   // exposures where the three walks are in front and the lattice can touch
   // the image, found 64 at a time (one per lane), then visited in order
   auto usable = [&](int ex, double2& p0, double& Ax, double& Ay, double& Bx, double& By) {
@@ -215,13 +215,12 @@ __global__ __launch_bounds__(256) void k_stack_cells(StackArgs A, const int64_t*
   if (A.nvalid) A.nvalid[o] = nv;
 }
 
-hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, double2* d_track, uint16_t* st_bf,
-                              float* st_f, uint16_t* ft_bf, float* ft_f, hipStream_t s) {
+hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, uint16_t* st_bf, float* st_f,
+                              uint16_t* ft_bf, float* ft_f, hipStream_t s) {
   if (reps.n <= 0) return hipSuccess;
-  const int64_t walks = 3 * reps.n * ((reps.n_exp + TRACK_CHUNK - 1) / TRACK_CHUNK);
-  hipLaunchKernelGGL(k_rep_tracks, dim3((unsigned)((walks + 255) / 256)), dim3(256), 0, s, reps, da, dm, d_track);
-  hipLaunchKernelGGL(k_cell_stamps, dim3((unsigned)reps.n), dim3(64), 0, s, reps.meta, reps.n_exp, reps.planes,
-                     d_track, reps.n, reps.a, reps.e, reps.inc, st_bf, st_f, ft_bf, ft_f);
+  if (reps.n_exp > STAMP_MAX_EXP) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double2) * 3 * (size_t)reps.n_exp;
+  hipLaunchKernelGGL(k_cell_stamps, dim3((unsigned)reps.n), dim3(64), lds, s, reps, da, dm, st_bf, st_f, ft_bf, ft_f);
   return hipGetLastError();
 }
 

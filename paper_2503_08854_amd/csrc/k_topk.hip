@@ -48,23 +48,27 @@ __device__ __forceinline__ void bitonic_desc(uint64_t (&r)[PER], uint64_t* s) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
         __syncthreads();
+        uint64_t o[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) o[q] = s[(PER * t + q) ^ j];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
           const int e = PER * t + q;
-          const uint64_t o = s[e ^ j];
           const bool keep_max = ((e & j) == 0) == ((e & k) == 0);
-          r[q] = keep_max ? (r[q] > o ? r[q] : o) : (r[q] < o ? r[q] : o);
+          r[q] = ((o[q] > r[q]) == keep_max) ? o[q] : r[q];  // keys are distinct (or both empty)
         }
         __syncthreads();
       } else {
+        // all shuffles of the stage first, so that they are in flight together
         const int m = j / PER;
+        uint64_t o[PER];
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int e = PER * t + q;
-          const uint64_t o = shfl_xor64(r[q], m);
-          const bool keep_max = ((e & j) == 0) == ((e & k) == 0);
-          r[q] = keep_max ? (r[q] > o ? r[q] : o) : (r[q] < o ? r[q] : o);
-        }
+        for (int q = 0; q < PER; ++q) o[q] = shfl_xor64(r[q], m);
+        // the direction bits are the same for all q of a thread at these strides
+        const int e0 = PER * t;
+        const bool keep_max = ((e0 & j) == 0) == ((e0 & k) == 0);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) r[q] = ((o[q] > r[q]) == keep_max) ? o[q] : r[q];
       }
     }
 #pragma unroll
