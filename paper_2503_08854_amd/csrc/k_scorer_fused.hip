@@ -24,12 +24,9 @@ namespace {
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even (NaN kept quiet)
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// round to nearest even with the hardware conversion (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint16_t relu_bf(float v, float b) { return f2bf(fmaxf(v + b, 0.f)); }
 __device__ __forceinline__ short4_t as4(uint2 v) {
   return short4_t{(short)(v.x & 0xffffu), (short)(v.x >> 16), (short)(v.y & 0xffffu), (short)(v.y >> 16)};
 }
@@ -132,23 +129,37 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
         continue;
       }
       wave_sync();
-      // conv1: [441 x 9] x [9 x 16], one K step (taps 9..15 zero)
+      // conv1: [441 x 9] x [9 x 16], one K step (taps 9..15 zero); this lane's
+      // taps k = 4 kq + i are fixed, its output pixel advances by 16 per tile
       const short4_t bw1 = ld4(&w1s[r16 * W1K + 4 * kq]);
+      int dy[4], dx[4];
+      bool tap[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int k = 4 * kq + i;
+        tap[i] = k < 9;
+        dy[i] = k / 3 - 1;
+        dx[i] = k % 3 - 1;
+      }
+      int oy = 0, ox = r16;
       for (int mt = 0; mt < 28; ++mt) {
-        const int m = mt * 16 + r16;
-        const int oy = m / 21, ox = m % 21;
+        const bool live = mt * 16 + r16 < 441;
         short v[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k = 4 * kq + i;
-          const int iy = oy + k / 3 - 1, ix = ox + k % 3 - 1;
-          v[i] = (m < 441 && k < 9 && iy >= 0 && iy < 21 && ix >= 0 && ix < 21) ? (short)st[iy * 21 + ix] : (short)0;
+          const int iy = oy + dy[i], ix = ox + dx[i];
+          v[i] = (live && tap[i] && (unsigned)iy < 21u && (unsigned)ix < 21u) ? (short)st[iy * 21 + ix] : (short)0;
         }
         const float4_t d = mfma(short4_t{v[0], v[1], v[2], v[3]}, bw1, float4_t{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int mo = mt * 16 + 4 * kq + r;
-          if (mo < 441) h1[h1a(mo, r16)] = f2bf(fmaxf(d[r] + bias1, 0.f));
+          if (mo < 441) h1[h1a(mo, r16)] = relu_bf(d[r], bias1);
+        }
+        ox += 16;
+        if (ox >= 21) {
+          ox -= 21;
+          ++oy;
         }
       }
       wave_sync();
@@ -174,8 +185,8 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
         for (int r = 0; r < 4; ++r) {
           const int mo = mt * 16 + 4 * kq + r;
           if (mo < 121) {
-            h2[h2a(mo, r16)] = f2bf(fmaxf(acc0[r] + bias2a, 0.f));
-            h2[h2a(mo, 16 + r16)] = f2bf(fmaxf(acc1[r] + bias2b, 0.f));
+            h2[h2a(mo, r16)] = relu_bf(acc0[r], bias2a);
+            h2[h2a(mo, 16 + r16)] = relu_bf(acc1[r], bias2b);
           }
         }
       }
@@ -204,8 +215,8 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
         for (int r = 0; r < 4; ++r) {
           const int mo = mt * 16 + 4 * kq + r;
           if (mo < 36) {
-            h3[mo * 32 + r16] = f2bf(fmaxf(acc0[r] + bias3a, 0.f));
-            h3[mo * 32 + 16 + r16] = f2bf(fmaxf(acc1[r] + bias3b, 0.f));
+            h3[mo * 32 + r16] = relu_bf(acc0[r], bias3a);
+            h3[mo * 32 + 16 + r16] = relu_bf(acc1[r], bias3b);
           }
         }
       }
