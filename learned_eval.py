@@ -188,3 +188,63 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
     if log:
         log(f"learned eval: {res}")
     return res
+
+
+def stage_times(bench: Bench, scorer, budget_frac: float = 0.02, reps: int = 4):
+    """Per-stage device times (ms, median over reps after one warm-up) of the
+    learned path on the current images, and of the exhaustive stack."""
+    import torch
+    import paper_2503_08854_amd as dt
+    from paper_2503_08854_amd import proposer
+    s = bench.s
+    budget = max(1, int(round(budget_frac * s.n_cells)))
+    out = dt.batch_outputs([bench.grid])[0]
+    rows = []
+    for it in range(reps + 1):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        e[0].record()
+        st, ft = proposer.cell_inputs(bench.patch, bench.reps, s.da, s.dm)
+        e[1].record()
+        z = proposer.score_cells(scorer, st, ft)
+        e[2].record()
+        cells = proposer.select_cells(bench.ctx, z, budget)
+        e[3].record()
+        dt.stack_cells(bench.patch, bench.grid, cells, s.cell_size, out=out)
+        e[4].record()
+        dt.stack(bench.patch, bench.grid, out)
+        e[5].record()
+        torch.cuda.synchronize()
+        if it:
+            rows.append([e[i].elapsed_time(e[i + 1]) for i in range(5)])
+    m = np.median(np.array(rows), axis=0)
+    return dict(stamps_ms=m[0], scorer_ms=m[1], topk_ms=m[2], stack_cells_ms=m[3], full_stack_ms=m[4],
+                budget_cells=budget)
+
+
+def main():
+    """Stage timing of the learned path on the learned workload (a short
+    training run first; realization 0's injections in fresh noise)."""
+    import argparse
+    import paper_2503_08854_amd as dt
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--setup", default="learned")
+    ap.add_argument("--train-realizations", type=int, default=4)
+    ap.add_argument("--budget", type=float, default=0.02)
+    args = ap.parse_args()
+    s = load_setup(args.setup)
+    ctx = dt.Context(0)
+    b = Bench(s, ctx)
+    X, F, Y = training_set(b, args.train_realizations, seed=1)
+    sc, _ = train_scorer(ctx, X, F, Y, epochs=1)
+    injs = s.geom["realizations"][0]
+    hits = np.array([[h[0], h[1], h[2], inj["flux"]] for inj in injs for h in inj["hits"]])
+    b.realize(10_000, hits)
+    print(stage_times(b, sc, args.budget), flush=True)
+    sc.close()
+    b.patch.close()
+    b.coarse.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -34,31 +34,42 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Bitonic sort of the tile, descending.  Thread t holds keys
-// [PER t, PER t + PER) in r[]; a compare-exchange at distance j runs in
-// registers when j < PER, between lanes of one wavefront (shuffles) when
-// PER <= j < 64 PER, and through LDS with a barrier only when j >= 64 PER
-// (6 of the 91 stages for 8192 keys).  On return s holds the sorted tile.
+// Bitonic sort of the first S keys of s (S a power of two, 64 <= S <=
+// TOPK_T), descending.  Thread t < S / PER holds keys [PER t, PER t + PER)
+// in r[]; a compare-exchange at distance j runs in registers when j < PER,
+// between lanes of one wavefront (shuffles) when PER <= j < 64 PER, and
+// through LDS with a barrier only when j >= 64 PER (6 of the 91 stages for
+// 8192 keys).  Every thread of the block calls it; on return s[0, S) holds
+// the sorted keys.
 template <int PER>
-__device__ __forceinline__ void bitonic_desc(uint64_t (&r)[PER], uint64_t* s) {
+__device__ __forceinline__ void bitonic_desc(uint64_t* s, int S) {
   const int t = threadIdx.x;
-  for (int k = 2; k <= TOPK_T; k <<= 1) {
+  const bool act = t < S / PER;
+  uint64_t r[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) r[q] = act ? s[PER * t + q] : 0;
+  __syncthreads();
+  for (int k = 2; k <= S; k <<= 1) {
     for (int j = k >> 1; j >= PER; j >>= 1) {
       if (j >= 64 * PER) {
+        if (act) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
-        __syncthreads();
-        uint64_t o[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) o[q] = s[(PER * t + q) ^ j];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int e = PER * t + q;
-          const bool keep_max = ((e & j) == 0) == ((e & k) == 0);
-          r[q] = ((o[q] > r[q]) == keep_max) ? o[q] : r[q];  // keys are distinct (or both empty)
+          for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
         }
         __syncthreads();
-      } else {
+        if (act) {
+          uint64_t o[PER];
+#pragma unroll
+          for (int q = 0; q < PER; ++q) o[q] = s[(PER * t + q) ^ j];
+#pragma unroll
+          for (int q = 0; q < PER; ++q) {
+            const int e = PER * t + q;
+            const bool keep_max = ((e & j) == 0) == ((e & k) == 0);
+            r[q] = ((o[q] > r[q]) == keep_max) ? o[q] : r[q];  // keys are distinct (or both empty)
+          }
+        }
+        __syncthreads();
+      } else if (act) {
         // all shuffles of the stage first, so that they are in flight together
         const int m = j / PER;
         uint64_t o[PER];
@@ -71,25 +82,29 @@ __device__ __forceinline__ void bitonic_desc(uint64_t (&r)[PER], uint64_t* s) {
         for (int q = 0; q < PER; ++q) r[q] = ((o[q] > r[q]) == keep_max) ? o[q] : r[q];
       }
     }
+    if (act) {
 #pragma unroll
-    for (int jj = PER / 2; jj > 0; jj >>= 1) {
-      if (jj <= (k >> 1)) {
+      for (int jj = PER / 2; jj > 0; jj >>= 1) {
+        if (jj <= (k >> 1)) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          if (q & jj) continue;
-          const int e = PER * t + q;
-          const uint64_t a = r[q], b = r[q | jj];
-          const bool desc = (e & k) == 0;
-          if (desc ? (a < b) : (a > b)) {
-            r[q] = b;
-            r[q | jj] = a;
+          for (int q = 0; q < PER; ++q) {
+            if (q & jj) continue;
+            const int e = PER * t + q;
+            const uint64_t a = r[q], b = r[q | jj];
+            const bool desc = (e & k) == 0;
+            if (desc ? (a < b) : (a > b)) {
+              r[q] = b;
+              r[q | jj] = a;
+            }
           }
         }
       }
     }
   }
+  if (act) {
 #pragma unroll
-  for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
+    for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
+  }
   __syncthreads();
 }
 
@@ -145,8 +160,26 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __rest
     for (int j = total + threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = 0;
     return;
   }
-  bitonic_desc<PER>(mine, s);
-  for (int j = threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = s[j];
+  // sort only the non-empty keys (compacted to the front, zero-padded to a
+  // power of two): the later rounds and sparse tiles hold few of them
+  {
+    int pos = scan[threadIdx.x] - cnt;
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+      if (mine[q] != 0) s[pos++] = mine[q];
+  }
+  int S = 64;
+  while (S < total) S <<= 1;
+  for (int j = total + threadIdx.x; j < S; j += TOPK_THREADS) s[j] = 0;
+  __syncthreads();
+  switch (S / TOPK_THREADS) {
+    case 16: bitonic_desc<16>(s, S); break;
+    case 8: bitonic_desc<8>(s, S); break;
+    case 4: bitonic_desc<4>(s, S); break;
+    case 2: bitonic_desc<2>(s, S); break;
+    default: bitonic_desc<1>(s, S); break;
+  }
+  for (int j = threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = j < total ? s[j] : 0;
 }
 
 __global__ void k_topk_emit(const uint64_t* __restrict__ keys, int k, int64_t* __restrict__ idx,
