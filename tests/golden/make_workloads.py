@@ -144,7 +144,9 @@ MOSAIC10 = [(MOSAIC10[k], ((k // 5) - 0.5) * 0.9) for k in range(10)]
 
 
 def survey(seed=2, n_exp=200, side=2048, n_orb=10_000_000, n_inj=20, cloud=1000, name="survey",
-           span=60.0, nan_frac=0.005, offsets=MOSAIC10, width=None):
+           span=60.0, nan_frac=0.005, offsets=MOSAIC10, width=None, ref=(2.7, 0.1, 5.0, 0.8),
+           a_rng=(2.0, 3.5), e_rng=(0.0, 0.3), inc_rng=(0.0, 15.0), s_rng=(0.5, 2.0), dtype="f32",
+           sigma_rng=(0.8, 1.25)):
     """Survey-scale mosaic: FP32 images plus variance, sigma U(0.8, 1.25),
     NaN-masked pixels, 0.2"/px, 10 field offsets; injections at per-image
     S/N U(0.5, 2) conditioned on s sqrt(n_hit) >= 3, each with a cloud of
@@ -154,12 +156,12 @@ def survey(seed=2, n_exp=200, side=2048, n_orb=10_000_000, n_inj=20, cloud=1000,
     H = side
     rng = synth.make_rng(seed, 1)
     t, t0 = make_epochs(rng, n_exp, span)
-    el_ref = reference_orbit(seed, t0, lam, 2.7, 0.1, 5.0, 0.8)
-    exps = make_exposures(rng, t, W, H, 0.2, el_ref, t0, lam, offsets, (0.8, 1.25), 3.0)
+    el_ref = reference_orbit(seed, t0, lam, *ref)
+    exps = make_exposures(rng, t, W, H, 0.2, el_ref, t0, lam, offsets, sigma_rng, 3.0)
     gf = grid_field(exps, t0, lam, W, H, 0.2)
-    injs = draw_injections(seed, gf, t0, exps, n_inj, (0.5, 2.0), (2.0, 3.5), (0.0, 0.3), (0.0, 15.0), 3.0)
-    return dict(name=name, seed=seed, t0=t0, dtype="f32", nan_frac=nan_frac, exposures=exps, grid_field=gf,
-                grid=dict(n=n_orb, a=[2.0, 3.5], e=[0.0, 0.3], inc_deg=[0.0, 15.0], cloud=cloud,
+    injs = draw_injections(seed, gf, t0, exps, n_inj, s_rng, a_rng, e_rng, inc_rng, 3.0)
+    return dict(name=name, seed=seed, t0=t0, dtype=dtype, nan_frac=nan_frac, exposures=exps, grid_field=gf,
+                grid=dict(n=n_orb, a=list(a_rng), e=list(e_rng), inc_deg=list(inc_rng), cloud=cloud,
                           cloud_da=1.5e-4), injections=injs)
 
 
@@ -169,6 +171,16 @@ def survey_small(seed=3):
     offs = [(-0.45, -0.45), (0.45, -0.45), (-0.45, 0.45), (0.45, 0.45)]
     return survey(seed=seed, n_exp=24, side=440, width=600, n_orb=20000, n_inj=3, cloud=50,
                   name="survey_small", span=8.0, offsets=offs)
+
+
+def distant_small(seed=6):
+    """Scaled-down distant-object case: 40 FP16 512x512 images over a year,
+    reference orbit at 45 AU, candidates a 30-60 AU, e 0-0.3, i 0-40 deg,
+    3 injections at per-image S/N U(0.2, 1) (rejection: s sqrt(n_hit) >= 3)."""
+    return survey(seed=seed, n_exp=40, side=512, n_orb=20000, n_inj=3, cloud=50, name="distant_small",
+                  span=365.0, nan_frac=0.0, offsets=[(0.0, 0.0)], ref=(45.0, 0.1, 10.0, 1.0),
+                  a_rng=(30.0, 60.0), e_rng=(0.0, 0.3), inc_rng=(0.0, 40.0), s_rng=(0.2, 1.0), dtype="f16",
+                  sigma_rng=(0.9, 1.1))
 
 
 def reference_orbit_general(rng, obs, a_rng, e_rng, inc_rng, near_earth=False):
@@ -274,7 +286,8 @@ def learned_small(seed=3):
 
 
 WORKLOADS = {"tiny": tiny, "survey": survey, "survey_small": survey_small, "batched": batched,
-             "batched_small": batched_small, "learned": learned, "learned_small": learned_small}
+             "batched_small": batched_small, "learned": learned, "learned_small": learned_small,
+             "distant_small": distant_small}
 
 
 def main(names):

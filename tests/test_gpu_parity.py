@@ -470,3 +470,24 @@ def test_gather_replay_equals_stack(small):
     W = np.array([x["width"] for x in w.exps])[order]
     want = base[None, :] + dbg["iy"][:, order].astype(np.int64) * W[None, :] + dbg["ix"][:, order]
     np.testing.assert_array_equal(o.T[valid[:, order]], want[valid[:, order]])
+
+
+def test_stack_distant_objects_fp16():
+    """Distant-object regime (a 30-60 AU over a year, light time 0.1-0.45 day,
+    FP16 images): every sample and S/N against the oracle on the same FP16
+    values."""
+    w = synth.build_workload(synth.load_geometry("distant_small"))
+    assert w.D[0].dtype == np.float16
+    ids = np.arange(w.elements.shape[0])
+    g = gpu_run(w, ids=ids, k=50)
+    o = oracle.samples(w.elements, w.t0, w.exps, w.D, w.V)
+    nb, nc = compare_samples(g["dbg"], o, w.exps)
+    assert nc > 10000
+    np.testing.assert_allclose(g["dbg"]["tau"][(o["flags"] & 1) != 0], o["tau"][(o["flags"] & 1) != 0],
+                               rtol=0, atol=1e-12)
+    snr, flux, nv = oracle.stack(w.elements, w.t0, w.exps, w.D, w.V)
+    np.testing.assert_array_equal(g["nv"], nv)
+    ok = snr_close(g["snr"], snr)
+    assert ok.all(), f"{(~ok).sum()} orbits outside tolerance"
+    want = oracle.topk(g["snr"].astype(np.float64), 50)
+    np.testing.assert_array_equal(g["topk_idx"][:g["topk_cnt"]], want)
