@@ -220,16 +220,23 @@ __device__ __forceinline__ bool kepler_warm(double M, double he, double e, KepSt
   d = fma(he * k.sE * k.g, d * d, d);
   if (anchor || !(fabs(d) <= ROT_SHORT)) return false;
   rot_short(k, d);
-  for (int it = 0; it < 8; ++it) {
-    const double g = rcp1(fma(-e, k.cE, 1.0));
-    const double dd = -fma(-e, k.sE, k.E - M) * g;
-    k.g = g;
-    if (fabs(dd) < 1e-8) {
-      rot_tiny(k, dd);
-      break;
+  double g = rcp1(fma(-e, k.cE, 1.0));
+  double dd = -fma(-e, k.sE, k.E - M) * g;
+  k.g = g;
+  if (!(fabs(dd) < 1e-8)) {  // rare: the start was poor, take more Newton steps
+    for (int it = 1; it < 8; ++it) {
+      rot_long(k, dd);
+      g = rcp1(fma(-e, k.cE, 1.0));
+      dd = -fma(-e, k.sE, k.E - M) * g;
+      k.g = g;
+      if (fabs(dd) < 1e-8) break;
     }
-    rot_long(k, dd);
+    if (!(fabs(dd) < 1e-8)) {
+      rot_long(k, dd);
+      dd = 0.0;
+    }
   }
+  rot_tiny(k, dd);
   k.M = M;
   return true;
 }
@@ -286,14 +293,19 @@ __device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt,
   double tg = FIRST ? 0.0 : fma(lt.rate, gap, lt.tau);
   const double b0 = o.c00 - x.ox, b1 = o.c01 - x.oy, b2 = o.c02 - x.oz;
   LtSolve s;
-  for (int pass = 0;; ++pass) {
-    const double M = fma(o.n, dt - tg, o.m0);
-    const bool first_try = pass == 0;
-    if (!(!FIRST && first_try && kepler_warm(M, o.he, o.e, k, anchor)))
-      kepler_general(M, o.e, k, first_try && anchor, FIRST && first_try);
-    lt_state(o, k, b0, b1, b2, tg, s);
-    if (fabs(s.D) <= LT_LINEAR_MAX || pass == 3) break;
-    tg += s.D;  // poor prediction: solve the orbit again at the corrected epoch
+  // common path straight-line: warm Kepler step, state, one light-time step
+  double M = fma(o.n, dt - tg, o.m0);
+  if (FIRST || !kepler_warm(M, o.he, o.e, k, anchor)) kepler_general(M, o.e, k, !FIRST && anchor, FIRST);
+  lt_state(o, k, b0, b1, b2, tg, s);
+  if (!(fabs(s.D) <= LT_LINEAR_MAX)) {
+    // poor prediction: solve the orbit again at the corrected epoch (at most 3 times)
+    for (int pass = 1; pass <= 3; ++pass) {
+      tg += s.D;
+      M = fma(o.n, dt - tg, o.m0);
+      kepler_general(M, o.e, k, false, false);
+      lt_state(o, k, b0, b1, b2, tg, s);
+      if (fabs(s.D) <= LT_LINEAR_MAX) break;
+    }
   }
   const double D = s.D;
   const double q0 = fma(-D, s.v0, s.rho0), q1 = fma(-D, s.v1, s.rho1), q2 = fma(-D, s.v2, s.rho2);
