@@ -220,7 +220,8 @@ __global__ __launch_bounds__(PREP_TX) void k_prepass(const ExpMeta* __restrict__
         pa = fmaf(g1[j], win[j].x, pa);
         pb = fmaf(g2[j], win[j].y, pb);
       }
-      planes[m.plane_off + (int64_t)gy * W + gx] = make_float2(pa * n1, pb * n2);
+      const uint64_t bits = (uint64_t)__float_as_uint(pa * n1) | ((uint64_t)__float_as_uint(pb * n2) << 32);
+      __builtin_nontemporal_store(bits, reinterpret_cast<uint64_t*>(planes + m.plane_off + (int64_t)gy * W + gx));
     }
   }
 }

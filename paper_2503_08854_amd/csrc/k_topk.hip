@@ -35,16 +35,18 @@ __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
 }
 
 // Bitonic sort of the first S keys of s (S a power of two, 64 <= S <=
-// TOPK_T), descending.  Thread t < S / PER holds keys [PER t, PER t + PER)
+// TOPK_T), descending.  Thread t < NT = S / PER holds keys [PER t, PER t + PER)
 // in r[]; a compare-exchange at distance j runs in registers when j < PER,
 // between lanes of one wavefront (shuffles) when PER <= j < 64 PER, and
 // through LDS with a barrier only when j >= 64 PER (6 of the 91 stages for
-// 8192 keys).  Every thread of the block calls it; on return s[0, S) holds
-// the sorted keys.
+// 8192 keys).  In LDS stages key e = PER t + q sits at q NT + t, so the
+// lanes of a wavefront touch consecutive words.  Every thread of the block
+// calls it; on return s[0, S) holds the sorted keys in natural order.
 template <int PER>
 __device__ __forceinline__ void bitonic_desc(uint64_t* s, int S) {
   const int t = threadIdx.x;
-  const bool act = t < S / PER;
+  const int NT = S / PER;
+  const bool act = t < NT;
   uint64_t r[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) r[q] = act ? s[PER * t + q] : 0;
@@ -54,19 +56,18 @@ __device__ __forceinline__ void bitonic_desc(uint64_t* s, int S) {
       if (j >= 64 * PER) {
         if (act) {
 #pragma unroll
-          for (int q = 0; q < PER; ++q) s[PER * t + q] = r[q];
+          for (int q = 0; q < PER; ++q) s[q * NT + t] = r[q];
         }
         __syncthreads();
         if (act) {
+          const int tp = t ^ (j / PER);
           uint64_t o[PER];
 #pragma unroll
-          for (int q = 0; q < PER; ++q) o[q] = s[(PER * t + q) ^ j];
+          for (int q = 0; q < PER; ++q) o[q] = s[q * NT + tp];
+          const int e0 = PER * t;
+          const bool keep_max = ((e0 & j) == 0) == ((e0 & k) == 0);
 #pragma unroll
-          for (int q = 0; q < PER; ++q) {
-            const int e = PER * t + q;
-            const bool keep_max = ((e & j) == 0) == ((e & k) == 0);
-            r[q] = ((o[q] > r[q]) == keep_max) ? o[q] : r[q];  // keys are distinct (or both empty)
-          }
+          for (int q = 0; q < PER; ++q) r[q] = ((o[q] > r[q]) == keep_max) ? o[q] : r[q];  // keys distinct or both empty
         }
         __syncthreads();
       } else if (act) {
