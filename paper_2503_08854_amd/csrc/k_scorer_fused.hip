@@ -2,20 +2,17 @@
 //
 // The same network and rounding points as the layer-by-layer path (every
 // activation rounded to BF16 after bias and ReLU, FP32 accumulation on
-// v_mfma_f32_16x16x16_bf16, FP32 biases), but with every intermediate kept in
-// LDS: a workgroup of four waves owns a group of 16 cells; each wave runs the
-// three convolutions of four cells as small GEMMs whose A operands are read
-// straight out of the channels-last activation in LDS (a 3x3 tap with 16
-// input channels is one 16-deep K step, four channels per lane = one 8-byte
-// read), and the fully connected layers then run with the 16 cells as the M
-// dimension of the MFMA tiles.  Per cell only the 441 + 16 BF16 inputs are
-// read and one FP32 logit is written.
-//
-// Weights arrive transposed ([N][K], one block per layer) so that every B
-// operand (four consecutive K of one output column) is one 8-byte load.  The
-// four-channel groups of a pixel are stored XOR-swizzled by pixel so that the
-// stride-2 convolutions, whose lanes read every other pixel, spread over the
-// LDS banks.
+// v_mfma_f32_16x16x16_bf16 in the same K order, FP32 biases), with every
+// intermediate kept in LDS.  A workgroup of four waves takes 16 cells at a
+// time and makes them the M dimension of every MFMA tile: a convolution
+// output pixel is one 16 (cells) x 16 (channels) tile whose A operand reads
+// the input pixel's 16-channel group of every cell (one 8-byte LDS read per
+// lane), so all pixel and tap arithmetic is uniform across the wave.  The
+// convolutions stream row by row through three-row ring buffers; the fully
+// connected layers then run on the group's 16 rows.  Per cell only the
+// 441 + 16 BF16 inputs are read and one FP32 logit is written.  Weights
+// arrive transposed ([N][K], one block per layer) so that every B operand
+// (four consecutive K of one output column) is one 8-byte load.
 #include "dt_common.hpp"
 
 namespace dtk {
@@ -36,20 +33,10 @@ __device__ __forceinline__ short4_t ld4(const uint16_t* p) {  // 8-byte aligned 
 __device__ __forceinline__ float4_t mfma(short4_t a, short4_t b, float4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
-// LDS writes of a wave visible to all its lanes
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-// swizzled channels-last addresses (elements): 16 and 32 channels per pixel
-__device__ __forceinline__ int h1a(int p, int c) { return p * 16 + (((c >> 2) ^ ((p >> 1) & 3)) << 2) + (c & 3); }
-__device__ __forceinline__ int h2a(int p, int c) { return p * 32 + (((c >> 2) ^ ((p >> 1) & 7)) << 2) + (c & 3); }
 
 constexpr int G = 16;                        // cells per workgroup
 constexpr int W1K = 16, W2K = 148, W3K = 292;  // padded K strides of the conv weights in LDS
-constexpr int H3S = 1156, FTS = 20, CTS = 132, H6S = 68;
-constexpr int SPW = 7;                       // stamp values per lane (441 = 64 * 7 - 7)
+constexpr int FTS = 20, CTS = 132, H6S = 68;
 }  // namespace
 
 // wt[toff[i] + n * K_i + k] = wb[w_off[i] + k * N_i + n]
@@ -66,174 +53,172 @@ __global__ void k_scorer_transpose(const uint16_t* __restrict__ wb, uint16_t* __
 }
 
 __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
-  __shared__ __align__(16) uint16_t w1s[16 * W1K];       // [n][k], k < 9 used
-  __shared__ __align__(16) uint16_t w2s[32 * W2K];       // [n][k]
-  __shared__ __align__(16) uint16_t w3s[32 * W3K];       // [n][k]
-  __shared__ __align__(16) uint16_t h1s[4][441 * 16];    // per wave, channels-last, swizzled
-  __shared__ __align__(16) uint16_t h2s[4][121 * 32];    // per wave; holds the stamp during conv1
-  __shared__ __align__(16) uint16_t h3g[G * H3S];        // the group's flattened conv3 outputs
+  // A workgroup owns 16 cells at a time; the cells are the M (row) dimension
+  // of every MFMA tile, so all pixel / tap index arithmetic is uniform.
+  // Activations are [pixel][cell][channel]; the convolutions stream by rows
+  // with three-row ring buffers (a stride-2 3x3 layer needs three input rows
+  // per output row), and only conv3's output is kept whole for FC4.
+  __shared__ __align__(16) uint16_t w1s[16 * W1K];           // [n][k], k < 9 used
+  __shared__ __align__(16) uint16_t w2s[32 * W2K];           // [n][k]
+  __shared__ __align__(16) uint16_t w3s[32 * W3K];           // [n][k]
+  __shared__ __align__(16) uint16_t stg[441 * G];            // stamps [pixel][cell]
+  __shared__ __align__(16) uint16_t h1r[3 * 21 * G * 16];    // conv1 rows (ring of 3) [row][x][cell][16]
+  __shared__ __align__(16) uint16_t h2r[3 * 11 * G * 32];    // conv2 rows (ring of 3) [row][x][cell][32]
+  __shared__ __align__(16) uint16_t h3s[36 * G * 32];        // conv3 output [pixel][cell][32]
   __shared__ __align__(16) uint16_t ftg[G * FTS];
   __shared__ __align__(16) uint16_t cat[G * CTS];
   __shared__ __align__(16) uint16_t h6[G * H6S];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const uint16_t* wt = A.wt;
-  for (int i = tid; i < 16 * W1K; i += 256) {
-    const int n = i / W1K, k = i % W1K;
-    w1s[i] = k < 9 ? wt[A.t_off[0] + n * 9 + k] : (uint16_t)0;
-  }
-  for (int i = tid; i < 32 * W2K; i += 256) {
-    const int n = i / W2K, k = i % W2K;
-    w2s[i] = k < 144 ? wt[A.t_off[1] + n * 144 + k] : (uint16_t)0;
-  }
-  for (int i = tid; i < 32 * W3K; i += 256) {
-    const int n = i / W3K, k = i % W3K;
-    w3s[i] = k < 288 ? wt[A.t_off[2] + n * 288 + k] : (uint16_t)0;
+  // conv weights into LDS, 8 bytes per load, all loads of a thread issued together
+  {
+    const uint2* g2 = reinterpret_cast<const uint2*>(wt + A.t_off[1]);  // 32 rows x 36 quads
+    const uint2* g3 = reinterpret_cast<const uint2*>(wt + A.t_off[2]);  // 32 rows x 72 quads
+    uint2 v2[5], v3[9];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int i = tid + 256 * q;
+      v2[q] = i < 32 * 36 ? g2[i] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v3[q] = g3[tid + 256 * q];
+    uint16_t w1v = 0;
+    if (tid < 16 * W1K) {
+      const int n = tid / W1K, k = tid % W1K;
+      w1v = k < 9 ? wt[A.t_off[0] + n * 9 + k] : (uint16_t)0;
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int i = tid + 256 * q;
+      if (i < 32 * 36) *reinterpret_cast<uint2*>(&w2s[(i / 36) * W2K + 4 * (i % 36)]) = v2[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int i = tid + 256 * q;
+      *reinterpret_cast<uint2*>(&w3s[(i / 72) * W3K + 4 * (i % 72)]) = v3[q];
+    }
+    if (tid < 16 * W1K) w1s[tid] = w1v;
   }
   const float* b1 = A.w + A.b_off[0];
   const float* b2 = A.w + A.b_off[1];
   const float* b3 = A.w + A.b_off[2];
   const float bias1 = b1[r16], bias2a = b2[r16], bias2b = b2[16 + r16], bias3a = b3[r16], bias3b = b3[16 + r16];
-  const int n_groups = (A.B + G - 1) / G;
-  uint16_t* h1 = h1s[wave];
-  uint16_t* h2 = h2s[wave];
-  uint16_t* st = h2s[wave];  // the stamp lives where h2 will be written
-  // stamp of the next cell this wave handles, prefetched into registers
-  uint16_t nxt[SPW];
-  auto fetch = [&](int cell) {
+  // this lane's conv1 taps k = 4 kq + i (taps 9..15 are padding)
+  int tdy[4], tdx[4];
+  bool tap[4];
 #pragma unroll
-    for (int q = 0; q < SPW; ++q) {
-      const int i = lane + 64 * q;
-      nxt[q] = (cell < A.B && i < 441) ? A.stamps[(int64_t)cell * 441 + i] : (uint16_t)0;
-    }
-  };
-  fetch(blockIdx.x * G + wave * (G / 4));
+  for (int i = 0; i < 4; ++i) {
+    const int k = 4 * kq + i;
+    tap[i] = k < 9;
+    tdy[i] = k / 3 - 1;
+    tdx[i] = k % 3 - 1;
+  }
+  const int n_groups = (A.B + G - 1) / G;
   for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
-    __syncthreads();  // previous group's FC reads of h3g / cat / h6 are done; weights are loaded
+    __syncthreads();  // the previous group's readers of stg / h3s / cat / h6 are done; weights loaded
     const int cell0 = grp * G;
+    {
+      // the group's stamps: 28 loads per thread issued together, then stored [pixel][cell]
+      constexpr int NQ = (441 * G + 255) / 256;
+      uint16_t v[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = tid + 256 * q;
+        const int c = i / 441;
+        v[q] = (i < 441 * G && cell0 + c < A.B) ? A.stamps[(int64_t)cell0 * 441 + i] : (uint16_t)0;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = tid + 256 * q;
+        if (i < 441 * G) stg[(i % 441) * G + i / 441] = v[q];
+      }
+    }
     for (int i = tid; i < G * 16; i += 256) {
       const int r = i / 16, c = i % 16;
       ftg[r * FTS + c] = cell0 + r < A.B ? A.feats[(int64_t)(cell0 + r) * 16 + c] : (uint16_t)0;
     }
-    for (int cc = 0; cc < G / 4; ++cc) {
-      const int slot = wave * (G / 4) + cc;
-      const int cell = cell0 + slot;
-      uint16_t* h3 = h3g + slot * H3S;
-#pragma unroll
-      for (int q = 0; q < SPW; ++q)
-        if (lane + 64 * q < 441) st[lane + 64 * q] = nxt[q];
-      // prefetch the following cell (next slot of this group, or this wave's first slot of its next group)
-      fetch(cc + 1 < G / 4 ? cell + 1 : (grp + gridDim.x) * G + wave * (G / 4));
-      if (cell >= A.B) {  // a missing cell of the last group: zero inputs to the FC layers
-        for (int i = lane; i < 1152; i += 64) h3[i] = 0;
-        continue;
-      }
-      wave_sync();
-      // conv1: [441 x 9] x [9 x 16], one K step (taps 9..15 zero); this lane's
-      // taps k = 4 kq + i are fixed, its output pixel advances by 16 per tile
-      const short4_t bw1 = ld4(&w1s[r16 * W1K + 4 * kq]);
-      int dy[4], dx[4];
-      bool tap[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int k = 4 * kq + i;
-        tap[i] = k < 9;
-        dy[i] = k / 3 - 1;
-        dx[i] = k % 3 - 1;
-      }
-      int oy = 0, ox = r16;
-      for (int mt = 0; mt < 28; ++mt) {
-        const bool live = mt * 16 + r16 < 441;
-        short v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int iy = oy + dy[i], ix = ox + dx[i];
-          v[i] = (live && tap[i] && (unsigned)iy < 21u && (unsigned)ix < 21u) ? (short)st[iy * 21 + ix] : (short)0;
-        }
-        const float4_t d = mfma(short4_t{v[0], v[1], v[2], v[3]}, bw1, float4_t{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int mo = mt * 16 + 4 * kq + r;
-          if (mo < 441) h1[h1a(mo, r16)] = relu_bf(d[r], bias1);
-        }
-        ox += 16;
-        if (ox >= 21) {
-          ox -= 21;
-          ++oy;
-        }
-      }
-      wave_sync();
-      // conv2: stride 2 -> 11 x 11, [121 x 144] x [144 x 32]; K step s = tap s, 16 channels
-      for (int mt = 0; mt < 8; ++mt) {
-        const int m = mt * 16 + r16;
-        const int oy = m / 11, ox = m % 11;
-        float4_t acc0 = float4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-        short4_t a[9];
-#pragma unroll
-        for (int s = 0; s < 9; ++s) {
-          const int iy = 2 * oy + s / 3 - 1, ix = 2 * ox + s % 3 - 1;
-          const int p = iy * 21 + ix;
-          a[s] = (m < 121 && iy >= 0 && iy < 21 && ix >= 0 && ix < 21) ? ld4(&h1[h1a(p, 4 * kq)])
-                                                                       : short4_t{0, 0, 0, 0};
-        }
-#pragma unroll
-        for (int s = 0; s < 9; ++s) {
-          acc0 = mfma(a[s], ld4(&w2s[r16 * W2K + s * 16 + 4 * kq]), acc0);
-          acc1 = mfma(a[s], ld4(&w2s[(16 + r16) * W2K + s * 16 + 4 * kq]), acc1);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int mo = mt * 16 + 4 * kq + r;
-          if (mo < 121) {
-            h2[h2a(mo, r16)] = relu_bf(acc0[r], bias2a);
-            h2[h2a(mo, 16 + r16)] = relu_bf(acc1[r], bias2b);
-          }
-        }
-      }
-      wave_sync();
-      // conv3: stride 2 -> 6 x 6, [36 x 288] x [288 x 32]; K steps: tap s, channel half h
-      for (int mt = 0; mt < 3; ++mt) {
-        const int m = mt * 16 + r16;
-        const int oy = m / 6, ox = m % 6;
-        float4_t acc0 = float4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-#pragma unroll
-        for (int s = 0; s < 9; ++s) {
-          const int iy = 2 * oy + s / 3 - 1, ix = 2 * ox + s % 3 - 1;
-          const bool in = m < 36 && iy >= 0 && iy < 11 && ix >= 0 && ix < 11;
-          const int p = iy * 11 + ix;
-          short4_t a[2];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) a[h] = in ? ld4(&h2[h2a(p, 16 * h + 4 * kq)]) : short4_t{0, 0, 0, 0};
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int k = s * 32 + 16 * h + 4 * kq;
-            acc0 = mfma(a[h], ld4(&w3s[r16 * W3K + k]), acc0);
-            acc1 = mfma(a[h], ld4(&w3s[(16 + r16) * W3K + k]), acc1);
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int mo = mt * 16 + 4 * kq + r;
-          if (mo < 36) {
-            h3[mo * 32 + r16] = relu_bf(acc0[r], bias3a);
-            h3[mo * 32 + 16 + r16] = relu_bf(acc1[r], bias3b);
-          }
-        }
-      }
-      wave_sync();
-    }
     __syncthreads();
-    // FC4 (1152 -> 64) and FC5 (16 -> 64): wave w owns output columns 16w .. 16w + 15
+    const short4_t bw1 = ld4(&w1s[r16 * W1K + 4 * kq]);
+    int h1_done = 0;  // conv1 rows computed so far
+    for (int oy2 = 0; oy2 < 11; ++oy2) {
+      // conv1 rows up to 2 oy2 + 1: pixel (y, x) of the row is one 16 x 16 tile, wave w takes x = w, w + 4, ...
+      const int need = min(21, 2 * oy2 + 2);
+      for (int y = h1_done; y < need; ++y) {
+        for (int x = wave; x < 21; x += 4) {
+          short v[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int iy = y + tdy[i], ix = x + tdx[i];
+            v[i] = (tap[i] && (unsigned)iy < 21u && (unsigned)ix < 21u) ? (short)stg[(iy * 21 + ix) * G + r16]
+                                                                       : (short)0;
+          }
+          const float4_t d = mfma(short4_t{v[0], v[1], v[2], v[3]}, bw1, float4_t{0.f, 0.f, 0.f, 0.f});
+          uint16_t* o = h1r + ((y % 3) * 21 + x) * (G * 16);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[(4 * kq + r) * 16 + r16] = relu_bf(d[r], bias1);
+        }
+      }
+      h1_done = need;
+      __syncthreads();
+      // conv2 row oy2: 11 pixels, wave w takes ox = w, w + 4, w + 8; K step s = tap s
+      for (int ox = wave; ox < 11; ox += 4) {
+        float4_t acc0 = float4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+          const int iy = 2 * oy2 + s / 3 - 1, ix = 2 * ox + s % 3 - 1;
+          short4_t a = short4_t{0, 0, 0, 0};
+          if ((unsigned)iy < 21u && (unsigned)ix < 21u) a = ld4(&h1r[((iy % 3) * 21 + ix) * (G * 16) + r16 * 16 + 4 * kq]);
+          acc0 = mfma(a, ld4(&w2s[r16 * W2K + s * 16 + 4 * kq]), acc0);
+          acc1 = mfma(a, ld4(&w2s[(16 + r16) * W2K + s * 16 + 4 * kq]), acc1);
+        }
+        uint16_t* o = h2r + ((oy2 % 3) * 11 + ox) * (G * 32);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          o[(4 * kq + r) * 32 + r16] = relu_bf(acc0[r], bias2a);
+          o[(4 * kq + r) * 32 + 16 + r16] = relu_bf(acc1[r], bias2b);
+        }
+      }
+      __syncthreads();
+      // conv3 row oy3 once conv2 rows up to 2 oy3 + 1 exist: 6 pixels x 2 column tiles, 3 units per wave
+      if ((oy2 & 1) || oy2 == 10) {
+        const int oy3 = oy2 == 10 ? 5 : (oy2 - 1) / 2;
+        for (int u = wave; u < 12; u += 4) {
+          const int ox = u >> 1, nt = u & 1;
+          float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s = 0; s < 9; ++s) {
+            const int iy = 2 * oy3 + s / 3 - 1, ix = 2 * ox + s % 3 - 1;
+            const bool in = (unsigned)iy < 11u && (unsigned)ix < 11u;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              short4_t a = short4_t{0, 0, 0, 0};
+              if (in) a = ld4(&h2r[((iy % 3) * 11 + ix) * (G * 32) + r16 * 32 + 16 * h + 4 * kq]);
+              acc = mfma(a, ld4(&w3s[(16 * nt + r16) * W3K + s * 32 + 16 * h + 4 * kq]), acc);
+            }
+          }
+          const float bias3 = nt ? bias3b : bias3a;
+          uint16_t* o = h3s + (oy3 * 6 + ox) * (G * 32) + 16 * nt;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) o[(4 * kq + r) * 32 + r16] = relu_bf(acc[r], bias3);
+        }
+        __syncthreads();
+      }
+    }
+    // FC4 (1152 -> 64; K = pixel * 32 + channel) and FC5 (16 -> 64): wave w owns columns 16w .. 16w + 15
     {
       const int n = 16 * wave + r16;
       const uint16_t* w4 = wt + A.t_off[3] + (int64_t)n * 1152;
       float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
-      for (int s0 = 0; s0 < 72; s0 += 8) {
-        short4_t b[8];
+      for (int s0 = 0; s0 < 72; s0 += 24) {
+        short4_t b[24];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = ld4(&w4[(s0 + u) * 16 + 4 * kq]);
+        for (int u = 0; u < 24; ++u) b[u] = ld4(&w4[(s0 + u) * 16 + 4 * kq]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc = mfma(ld4(&h3g[r16 * H3S + (s0 + u) * 16 + 4 * kq]), b[u], acc);
+        for (int u = 0; u < 24; ++u) {
+          const int s = s0 + u;
+          acc = mfma(ld4(&h3s[((s >> 1) * G + r16) * 32 + (s & 1) * 16 + 4 * kq]), b[u], acc);
+        }
       }
       const float bias4 = A.w[A.b_off[3] + n];
 #pragma unroll
