@@ -24,6 +24,12 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // round to nearest even with the hardware conversion (v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ uint16_t relu_bf(float v, float b) { return f2bf(fmaxf(v + b, 0.f)); }
+typedef float float2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+// two values to BF16 in one hardware conversion (round to nearest even)
+__device__ __forceinline__ uint32_t cvt2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(float2_t{a, b}, bf16x2_t));
+}
 __device__ __forceinline__ short4_t as4(uint2 v) {
   return short4_t{(short)(v.x & 0xffffu), (short)(v.x >> 16), (short)(v.y & 0xffffu), (short)(v.y >> 16)};
 }
@@ -33,10 +39,20 @@ __device__ __forceinline__ short4_t ld4(const uint16_t* p) {  // 8-byte aligned 
 __device__ __forceinline__ float4_t mfma(short4_t a, short4_t b, float4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
+// D tile rows 4 kq + r (cells), column r16: relu(d + bias) as BF16 into o[row * stride + r16]
+__device__ __forceinline__ void store4(uint16_t* o, int kq, int r16, int stride, float4_t d, float bias) {
+  const uint32_t p01 = cvt2(fmaxf(d[0] + bias, 0.f), fmaxf(d[1] + bias, 0.f));
+  const uint32_t p23 = cvt2(fmaxf(d[2] + bias, 0.f), fmaxf(d[3] + bias, 0.f));
+  o[(4 * kq + 0) * stride + r16] = (uint16_t)p01;
+  o[(4 * kq + 1) * stride + r16] = (uint16_t)(p01 >> 16);
+  o[(4 * kq + 2) * stride + r16] = (uint16_t)p23;
+  o[(4 * kq + 3) * stride + r16] = (uint16_t)(p23 >> 16);
+}
 
 constexpr int G = 16;                        // cells per workgroup
 constexpr int W1K = 16, W2K = 148, W3K = 292;  // padded K strides of the conv weights in LDS
 constexpr int FTS = 20, CTS = 132, H6S = 68;
+constexpr int SPAD = 23 * 23;                // the stamp with a one-pixel zero border
 }  // namespace
 
 // wt[toff[i] + n * K_i + k] = wb[w_off[i] + k * N_i + n]
@@ -61,7 +77,7 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
   __shared__ __align__(16) uint16_t w1s[16 * W1K];           // [n][k], k < 9 used
   __shared__ __align__(16) uint16_t w2s[32 * W2K];           // [n][k]
   __shared__ __align__(16) uint16_t w3s[32 * W3K];           // [n][k]
-  __shared__ __align__(16) uint16_t stg[441 * G];            // stamps [pixel][cell]
+  __shared__ __align__(16) uint16_t stg[SPAD * G];           // stamps [pixel of the 23 x 23 zero-bordered stamp][cell]
   __shared__ __align__(16) uint16_t h1r[3 * 21 * G * 16];    // conv1 rows (ring of 3) [row][x][cell][16]
   __shared__ __align__(16) uint16_t h2r[3 * 11 * G * 32];    // conv2 rows (ring of 3) [row][x][cell][32]
   __shared__ __align__(16) uint16_t h3s[36 * G * 32];        // conv3 output [pixel][cell][32]
@@ -104,16 +120,18 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
   const float* b2 = A.w + A.b_off[1];
   const float* b3 = A.w + A.b_off[2];
   const float bias1 = b1[r16], bias2a = b2[r16], bias2b = b2[16 + r16], bias3a = b3[r16], bias3b = b3[16 + r16];
-  // this lane's conv1 taps k = 4 kq + i (taps 9..15 are padding)
-  int tdy[4], tdx[4];
-  bool tap[4];
+  // this lane's conv1 taps k = 4 kq + i as LDS offsets into the bordered
+  // stamp (taps 9..15 are padding: zero)
+  int toff[4];
+  bool tapv[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int k = 4 * kq + i;
-    tap[i] = k < 9;
-    tdy[i] = k / 3 - 1;
-    tdx[i] = k % 3 - 1;
+    tapv[i] = k < 9;
+    toff[i] = (k < 9 ? ((k / 3) * 23 + k % 3) * G : 0) + r16;
   }
+  // the zero border (never written below)
+  for (int i = tid; i < SPAD * G; i += 256) stg[i] = 0;
   const int n_groups = (A.B + G - 1) / G;
   for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
     __syncthreads();  // the previous group's readers of stg / h3s / cat / h6 are done; weights loaded
@@ -131,7 +149,8 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int i = tid + 256 * q;
-        if (i < 441 * G) stg[(i % 441) * G + i / 441] = v[q];
+        const int px = i % 441;
+        if (i < 441 * G) stg[((px / 21 + 1) * 23 + px % 21 + 1) * G + i / 441] = v[q];
       }
     }
     for (int i = tid; i < G * 16; i += 256) {
@@ -146,17 +165,15 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
       const int need = min(21, 2 * oy2 + 2);
       for (int y = h1_done; y < need; ++y) {
         for (int x = wave; x < 21; x += 4) {
+          // output pixel (y, x) reads bordered pixels (y + dy, x + dx), dy, dx in 0..2
+          const uint16_t* b = stg + (y * 23 + x) * G;
           short v[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int iy = y + tdy[i], ix = x + tdx[i];
-            v[i] = (tap[i] && (unsigned)iy < 21u && (unsigned)ix < 21u) ? (short)stg[(iy * 21 + ix) * G + r16]
-                                                                       : (short)0;
-          }
-          const float4_t d = mfma(short4_t{v[0], v[1], v[2], v[3]}, bw1, float4_t{0.f, 0.f, 0.f, 0.f});
+          for (int i = 0; i < 4; ++i) v[i] = tapv[i] ? (short)b[toff[i]] : (short)0;
+          const short4_t a = short4_t{v[0], v[1], v[2], v[3]};
+          const float4_t d = mfma(a, bw1, float4_t{0.f, 0.f, 0.f, 0.f});
           uint16_t* o = h1r + ((y % 3) * 21 + x) * (G * 16);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) o[(4 * kq + r) * 16 + r16] = relu_bf(d[r], bias1);
+          store4(o, kq, r16, 16, d, bias1);
         }
       }
       h1_done = need;
@@ -173,11 +190,8 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
           acc1 = mfma(a, ld4(&w2s[(16 + r16) * W2K + s * 16 + 4 * kq]), acc1);
         }
         uint16_t* o = h2r + ((oy2 % 3) * 11 + ox) * (G * 32);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          o[(4 * kq + r) * 32 + r16] = relu_bf(acc0[r], bias2a);
-          o[(4 * kq + r) * 32 + 16 + r16] = relu_bf(acc1[r], bias2b);
-        }
+        store4(o, kq, r16, 32, acc0, bias2a);
+        store4(o + 16, kq, r16, 32, acc1, bias2b);
       }
       __syncthreads();
       // conv3 row oy3 once conv2 rows up to 2 oy3 + 1 exist: 6 pixels x 2 column tiles, 3 units per wave
@@ -198,9 +212,7 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
             }
           }
           const float bias3 = nt ? bias3b : bias3a;
-          uint16_t* o = h3s + (oy3 * 6 + ox) * (G * 32) + 16 * nt;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) o[(4 * kq + r) * 32 + r16] = relu_bf(acc[r], bias3);
+          store4(h3s + (oy3 * 6 + ox) * (G * 32) + 16 * nt, kq, r16, 32, acc, bias3);
         }
         __syncthreads();
       }
