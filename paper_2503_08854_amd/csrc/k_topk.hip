@@ -113,15 +113,16 @@ __device__ __forceinline__ void bitonic_desc(uint64_t* s, int S) {
 // value and index) or keys from the previous round.  A tile with at most kk
 // non-empty keys is not sorted unless it is the last round: its keys are
 // only compacted (in index order) since a later round sorts them.
+template <int T>
 __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __restrict__ snr,
                                                              const uint64_t* __restrict__ keys_in, int64_t n_in,
                                                              float thr, int kk, int final_round,
                                                              uint64_t* __restrict__ keys_out) {
-  constexpr int PER = TOPK_T / TOPK_THREADS;  // keys owned by a thread
-  __shared__ uint64_t s[TOPK_T];
+  constexpr int PER = T / TOPK_THREADS;  // keys owned by a thread
+  __shared__ uint64_t s[T];
   __shared__ int scan[TOPK_THREADS];
-  const int64_t base = (int64_t)blockIdx.x * TOPK_T;
-  for (int j = threadIdx.x; j < TOPK_T; j += TOPK_THREADS) {
+  const int64_t base = (int64_t)blockIdx.x * T;
+  for (int j = threadIdx.x; j < T; j += TOPK_THREADS) {
     int64_t i = base + j;
     uint64_t key = 0;
     if (i < n_in) {
@@ -174,9 +175,9 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __rest
   for (int j = total + threadIdx.x; j < S; j += TOPK_THREADS) s[j] = 0;
   __syncthreads();
   switch (S / TOPK_THREADS) {
-    case 16: bitonic_desc<16>(s, S); break;
-    case 8: bitonic_desc<8>(s, S); break;
-    case 4: bitonic_desc<4>(s, S); break;
+    case 16: if constexpr (T >= 8192) bitonic_desc<16>(s, S); break;
+    case 8: if constexpr (T >= 4096) bitonic_desc<8>(s, S); break;
+    case 4: if constexpr (T >= 2048) bitonic_desc<4>(s, S); break;
     case 2: bitonic_desc<2>(s, S); break;
     default: bitonic_desc<1>(s, S); break;
   }
@@ -207,26 +208,63 @@ __global__ void k_topk_emit(const uint64_t* __restrict__ keys, int k, int64_t* _
 
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Tile of the first round: small inputs use tiles just large enough to cut
+// the keys fourfold (cheaper sorts, more workgroups); large inputs 8192.
+static int first_tile(int64_t n, int32_t k) {
+  if (n > 65536) return TOPK_T;
+  int t = 1024;
+  while (t < 4 * k && t < TOPK_T) t <<= 1;
+  return t;
+}
+static int round_tile(int64_t n_in) {
+  if (n_in > TOPK_T) return TOPK_T;
+  int t = 1024;
+  while (t < n_in) t <<= 1;
+  return t;
+}
+
 size_t topk_scratch_bytes(int64_t n, int32_t k) {
-  int64_t tiles = ceil_div(n > 0 ? n : 1, TOPK_T);
+  int64_t tiles = ceil_div(n > 0 ? n : 1, first_tile(n, k));
   int64_t kk = k < TOPK_T ? k : TOPK_T;
   return (size_t)(2 * tiles * kk + TOPK_T) * sizeof(uint64_t);
+}
+
+static void launch_round(int T, unsigned tiles, const float* snr, const uint64_t* in, int64_t n_in, float thr, int k,
+                         int final_round, uint64_t* out, hipStream_t s) {
+  switch (T) {
+    case 1024:
+      hipLaunchKernelGGL(k_topk_round<1024>, dim3(tiles), dim3(TOPK_THREADS), 0, s, snr, in, n_in, thr, k,
+                         final_round, out);
+      break;
+    case 2048:
+      hipLaunchKernelGGL(k_topk_round<2048>, dim3(tiles), dim3(TOPK_THREADS), 0, s, snr, in, n_in, thr, k,
+                         final_round, out);
+      break;
+    case 4096:
+      hipLaunchKernelGGL(k_topk_round<4096>, dim3(tiles), dim3(TOPK_THREADS), 0, s, snr, in, n_in, thr, k,
+                         final_round, out);
+      break;
+    default:
+      hipLaunchKernelGGL(k_topk_round<TOPK_T>, dim3(tiles), dim3(TOPK_THREADS), 0, s, snr, in, n_in, thr, k,
+                         final_round, out);
+      break;
+  }
 }
 
 hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,
                        int32_t* d_count, void* d_scratch, hipStream_t s) {
   if (k < 1 || k > TOPK_T / 2) return hipErrorInvalidValue;
-  int64_t tiles = ceil_div(n > 0 ? n : 1, TOPK_T);
+  const int T1 = first_tile(n, k);
+  int64_t tiles = ceil_div(n > 0 ? n : 1, T1);
   uint64_t* buf[2] = {static_cast<uint64_t*>(d_scratch), static_cast<uint64_t*>(d_scratch) + tiles * k};
   int cur = 0;
   int64_t n_in = n > 0 ? n : 0;
-  hipLaunchKernelGGL(k_topk_round, dim3((unsigned)tiles), dim3(TOPK_THREADS), 0, s, d_snr, nullptr, n_in, thr, k,
-                     tiles == 1 ? 1 : 0, buf[cur]);
+  launch_round(T1, (unsigned)tiles, d_snr, nullptr, n_in, thr, k, tiles == 1 ? 1 : 0, buf[cur], s);
   n_in = tiles * k;
   while (tiles > 1) {
-    tiles = ceil_div(n_in, TOPK_T);
-    hipLaunchKernelGGL(k_topk_round, dim3((unsigned)tiles), dim3(TOPK_THREADS), 0, s, nullptr, buf[cur], n_in,
-                       thr, k, tiles == 1 ? 1 : 0, buf[cur ^ 1]);
+    const int T = round_tile(n_in);
+    tiles = ceil_div(n_in, T);
+    launch_round(T, (unsigned)tiles, nullptr, buf[cur], n_in, thr, k, tiles == 1 ? 1 : 0, buf[cur ^ 1], s);
     cur ^= 1;
     n_in = tiles * k;
   }
