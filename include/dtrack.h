@@ -255,7 +255,7 @@ dt_status dt_stack_generated(dt_patch *p, const dt_orbit_sampler *sampler, int64
 /* Per-intersection outlier trimming of candidate orbits (Sec. 5.2.3): for
  * each of m orbits (device int64 ids into `orbits`), the valid samples'
  * (psi_e, phi_e) from the stack's device code are clipped two-sided at
- * |psi_e - F phi_e| / sqrt(phi_e) > kappa.  Round 1 takes F = the median of
+ * |psi_e - F phi_e| / sqrt(phi_e) > kappa.  Iteration 1 takes F = the median of
  * the per-sample fluxes psi_e / phi_e (mean of the two middle values for an
  * even count); each later round takes F = sum psi / sum phi of the samples
  * the previous round kept; it stops when a round keeps exactly the set it

@@ -7,7 +7,7 @@ step (tracks, planes, stamps, scoring, stacking) runs in the HIP library.
 Evaluation protocol: a cell-structured grid (representative + perturbed
 members per cell) on the survey exposures; per realization, fresh noise and
 sources injected on member orbits at the pixel positions the oracle stored.
-The exhaustive stack over every orbit is the judge: an injection counts as
+The exhaustive stack over every orbit is the reference: an injection counts as
 found by a method if its own orbit's stacked S/N is >= 5 in that method's
 output.  Recall ratio = learned-found / plain-found.
 """

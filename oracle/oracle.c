@@ -410,7 +410,7 @@ int64_t or_topk(int64_t n, const double *snr, int64_t k, double thr, int64_t *id
  * then the weighted mean F = sum psi / sum phi of the kept samples; a sample
  * is dropped when its residual chi_e = (psi_e - F phi_e) / sqrt(phi_e) has
  * |chi_e| > kappa (both sides: a one-sided clip lets a deep negative
- * artifact drag F down until the ordinary samples look high).  Round 1
+ * artifact drag F down until the ordinary samples look high).  Iteration 1
  * clips about the median; every later round about the fit of the set the
  * previous round kept, until a round keeps exactly that set or after
  * max_iter rounds.  The median of an even count is the mean of the two

@@ -3,7 +3,7 @@
 // threshold; under the constant-flux model each valid intersection e is an
 // independent flux estimate f_e = psi_e / phi_e of variance 1 / phi_e, so the
 // residuals chi_e = (psi_e - F phi_e) / sqrt(phi_e) about the expectation F
-// are standard normal.  Round 1 takes F = median(f_e), so that one dominant
+// are standard normal.  Iteration 1 takes F = median(f_e), so that one dominant
 // artifact cannot set it; every later round takes the weighted mean
 // F = sum psi / sum phi of the samples the previous round kept.  A round
 // keeps the samples with |chi_e| <= kappa; it stops when a round keeps
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(64) void k_clip_fit(const float2* __restrict__ buf,
   }
   __syncthreads();
   const int nvalid = (int)wave_sum_d((double)nv);
-  // round 1's expectation: the median of the per-sample fluxes (ranks with
+  // iteration 1 expectation: the median of the per-sample fluxes (ranks with
   // ties broken by exposure index; mean of the two middle values)
   const int lo = (nvalid - 1) / 2, hi = nvalid / 2;
   double vlo = 0.0, vhi = 0.0;

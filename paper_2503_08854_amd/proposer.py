@@ -5,7 +5,7 @@ Pipeline, every numerical step in the library's kernels:
   2. the scorer's logit per cell (fused BF16 MFMA inference kernel);
   3. the `budget` best cells by logit (dt_topk on the logits);
   4. the plain stack on the orbits of those cells only (dt_stack_cells).
-The exhaustive stack over every orbit stays the fallback and the judge.
+The exhaustive stack over every orbit stays the fallback and the reference.
 Two non-learned counterparts rank cells the same way: by the coarse stamp's
 maximum (run_coarse) and by the representatives' S/N on planes smoothed with
 a Gaussian wider than the PSF (run_coarse_to_fine).
