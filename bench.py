@@ -125,6 +125,61 @@ def gather_yardstick(patch, w, dev, m=1_000_000, reps=3):
     return res
 
 
+def bench_next_rows(ctx, patch, orb, w, snr, dev, reps=3):
+    """The follow-on rows on the survey workload: per-image iterated-MAD noise,
+    on-device orbit generation and generate-and-stack, outlier trimming of
+    the top candidates."""
+    import torch
+    import paper_2503_08854_amd as dt
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    res = {}
+    # f-2: iterated MAD over the 200 flux images (one full read per digit pass)
+    out = {}
+    t_noise = timed(lambda: out.update(r=dt.image_noise(ctx, w.D)))
+    sig, used, it = (x.cpu().numpy() for x in out["r"])
+    npix = np.array([x.numel() for x in w.D], dtype=np.float64)
+    passes = 1 + 10 * it.astype(np.float64)          # count pass + (3 + 6 digit passes + clip) per step
+    nbytes = float((passes * npix * 4).sum())
+    res["noise"] = dict(images=len(w.D), ms=t_noise, steps_mean=float(it.mean()), steps_max=int(it.max()),
+                        sigma_mean=float(sig.mean()), bytes_read=nbytes,
+                        achieved_GBs=nbytes / (t_noise * 1e-3) / 1e9, peak_GBs=HBM_PEAK_GBS)
+    # f-4: candidate orbits sampled on the device, then stacked without element arrays
+    gf = w.geom["grid_field"]
+    gr = w.geom["grid"]
+    S = dt.orbit_sampler(gf, gf["t"], gr["a"], gr["e"], gr["inc_deg"], seed=99)
+    n = orb.n
+    holder = {}
+    t_gen = timed(lambda: holder.update(el=dt.generate_orbits(ctx, S, 0, n)))
+    gen_set = dt.OrbitSet(holder["el"], gf["t"], dev)
+    o2 = dt.batch_outputs([gen_set])[0]
+    t_stack = timed(lambda: dt.stack(patch, gen_set, o2))
+    t_fused = timed(lambda: holder.update(g=dt.stack_generated(patch, S, 0, n)))
+    same = bool(torch.equal(holder["g"][2], o2[2]))
+    res["generation"] = dict(orbits=n, generate_ms=t_gen, orbits_per_s=n / (t_gen * 1e-3), stack_ms=t_stack,
+                             generate_and_stack_ms=t_fused,
+                             generate_and_stack_samples_per_s=n * patch.n_exp / (t_fused * 1e-3),
+                             element_bytes_not_moved=48.0 * n, nvalid_equal=same)
+    del holder, gen_set, o2
+    # f-1: outlier trimming of the 100 best candidates
+    ids = torch.as_tensor(np.argsort(-np.nan_to_num(snr, nan=-np.inf))[:100].copy(), device=dev)
+    t_clip = timed(lambda: dt.clip_candidates(patch, orb, ids))
+    res["outlier_trimming"] = dict(candidates=100, ms=t_clip)
+    return res
+
+
 def bench_batched(dev, steps=5):
     """The batched-patches workload: 64 uneven FP16 patches, one graph-captured
     persistent launch (stack + per-patch top-k) after autotuning."""
@@ -214,6 +269,7 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--skip-gather", action="store_true")
+    ap.add_argument("--skip-next", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the stack shards by orbit and "
@@ -302,6 +358,12 @@ def main():
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(w, snr)
         log(f"cpu baseline: {rec['cpu_baseline']['value']:.3g} samples/s on {rec['cpu_baseline']['cores']} threads")
+    if not args.skip_next:
+        rec["next_rows"] = bench_next_rows(ctx, patch, orb, w, snr, dev)
+        N = rec["next_rows"]
+        log(f"next rows: noise {N['noise']['ms']:.2f} ms ({N['noise']['achieved_GBs']:.0f} GB/s), generation "
+            f"{N['generation']['orbits_per_s']:.3g} orbits/s, generate+stack {N['generation']['generate_and_stack_ms']:.2f} "
+            f"ms vs stack {N['generation']['stack_ms']:.2f} ms, trimming {N['outlier_trimming']['ms']:.3f} ms")
     if not args.skip_gather:
         rec["gather"] = gather_yardstick(patch, w, dev)
         G = rec["gather"]
