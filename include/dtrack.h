@@ -121,7 +121,8 @@ dt_status dt_patch_create(dt_ctx *ctx, const dt_exposure *exps, int32_t n_exp,
  * clip test are FP64, so the result is exact.  Outputs (device, n_img each,
  * any may be NULL): sigma of the last step (NaN for an image with no finite
  * pixel), the size of the set it came from, the number of steps.  Enqueued
- * on the context stream; the host arrays are not read after return. */
+ * on the context stream; the host arrays are not read after return.
+ * 0 <= n_img <= 65535. */
 dt_status dt_image_noise(dt_ctx *ctx, int32_t n_img, const void *const *d_images, const int64_t *n_pixels,
                          dt_dtype dtype, double kappa, int32_t max_iter, double *d_sigma, int64_t *d_n_used,
                          int32_t *d_iters);
@@ -244,7 +245,7 @@ typedef struct {
 } dt_orbit_sampler;
 
 /* Orbits first .. first + n - 1 of the sampler into device SoA arrays
- * (an index whose 16 attempts all miss gets a = NaN). */
+ * (an index whose 16 attempts all miss gets a = NaN); 0 <= n < 2^32. */
 dt_status dt_generate_orbits(dt_ctx *ctx, const dt_orbit_sampler *sampler, int64_t first, int64_t n, double *d_a,
                              double *d_e, double *d_inc, double *d_node, double *d_peri, double *d_m0);
 /* dt_stack on orbits first .. first + n - 1 of the sampler, generated in

@@ -348,7 +348,7 @@ dt_status dt_image_noise(dt_ctx* c, int32_t n_img, const void* const* d_images, 
                          dt_dtype dtype, double kappa, int32_t max_iter, double* d_sigma, int64_t* d_n_used,
                          int32_t* d_iters) {
   if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
-  if (n_img < 0) return fail(DT_E_ARG, "n_img < 0");
+  if (n_img < 0 || n_img > 65535) return fail(DT_E_ARG, "n_img must be in [0, 65535]");
   if (n_img == 0) return DT_OK;
   if (!d_images || !n_pixels) return fail(DT_E_ARG, "NULL image or size array");
   if (dtype != DT_F32 && dtype != DT_F16) return fail(DT_E_ARG, "unknown dtype %d", (int)dtype);

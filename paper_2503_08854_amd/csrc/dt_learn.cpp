@@ -85,7 +85,7 @@ dt_status dt_generate_orbits(dt_ctx* c, const dt_orbit_sampler* S, int64_t first
   if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
   dt_status st = check_sampler(S);
   if (st != DT_OK) return st;
-  if (first < 0 || n < 0) return fail(DT_E_ARG, "first and n must be >= 0");
+  if (first < 0 || n < 0 || n >= ((int64_t)1 << 32)) return fail(DT_E_ARG, "need first >= 0 and 0 <= n < 2^32");
   if (n > 0 && (!d_a || !d_e || !d_inc || !d_node || !d_peri || !d_m0)) return fail(DT_E_ARG, "NULL output");
   DeviceGuard guard(c->device);
   hipError_t e = launch_generate(*S, first, n, d_a, d_e, d_inc, d_node, d_peri, d_m0, c->stream);

@@ -219,6 +219,23 @@ def test_argument_errors():
     assert ctx.mem_used() == used
     ctx.set_mem_limit(0)
     p = dt.Patch(ctx, [dict(x, fwhm=3.0)], [im], [im])
+    # follow-on rows: argument and domain errors are reported, nothing is launched
+    with pytest.raises(dt.DtrackError, match="DT_E_DOMAIN"):
+        dt.image_noise(ctx, [im], kappa=0.0)
+    with pytest.raises(dt.DtrackError, match="DT_E_ARG"):
+        dt.image_noise(ctx, [im], max_iter=0)
+    f = synth.load_geometry("tiny")["grid_field"]
+    with pytest.raises(dt.DtrackError, match="DT_E_DOMAIN"):
+        dt.generate_orbits(ctx, dt.orbit_sampler(f, f["t"], (2.0, 1.0), (0.0, 0.3), (0.0, 15.0), 1), 0, 10)
+    with pytest.raises(dt.DtrackError, match="DT_E_DOMAIN"):
+        dt.generate_orbits(ctx, dt.orbit_sampler(f, f["t"], (2.0, 3.0), (0.0, 1.0), (0.0, 15.0), 1), 0, 10)
+    orb = dt.OrbitSet(np.array([[2.5, 0.1, 0.1, 0.0, 0.0, 0.0]]), 0.0)
+    with pytest.raises(dt.DtrackError, match="DT_E_ARG"):
+        dt.clip_candidates(p, orb, np.array([0]), kappa=0.0)
+    with pytest.raises(dt.DtrackError, match="DT_E_DOMAIN"):
+        dt.cell_stamps(p, orb, 0.0, 1e-5)
+    with pytest.raises(dt.DtrackError, match="DT_E_STATE"):
+        p.noise()                       # the patch has variance planes
     p.close()
     assert ctx.mem_used() == used
 
