@@ -151,7 +151,9 @@ def bench_next_rows(ctx, patch, orb, w, snr, dev, reps=3):
     t_noise = timed(lambda: out.update(r=dt.image_noise(ctx, w.D)))
     sig, used, it = (x.cpu().numpy() for x in out["r"])
     npix = np.array([x.numel() for x in w.D], dtype=np.float64)
-    passes = 1 + 10 * it.astype(np.float64)          # count pass + (3 + 6 digit passes + clip) per step
+    # count pass + first median digit, then per step two median digits, three
+    # deviation digits (the third also compacts the last digits' keys) and the clip
+    passes = 2 + 6 * it.astype(np.float64)
     nbytes = float((passes * npix * 4).sum())
     res["noise"] = dict(images=len(w.D), ms=t_noise, steps_mean=float(it.mean()), steps_max=int(it.max()),
                         sigma_mean=float(sig.mean()), bytes_read=nbytes,

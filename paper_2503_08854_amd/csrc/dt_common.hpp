@@ -171,8 +171,10 @@ struct NoiseState {
   uint64_t prefix[2];     // key bits chosen so far
   int64_t rank[2];        // target ranks among keys sharing the prefix
   int64_t n, n_new, n_used;
+  int64_t n_list;         // deviation keys compacted for the last digits (> NOISE_LIST_CAP: not used)
   int32_t iter, done, changed, pad;
 };
+constexpr int64_t NOISE_LIST_CAP = 65536;  // compacted deviation keys per image
 constexpr double NOISE_KAPPA = 3.0;   // clip half-width in sigma (patches without variance planes)
 constexpr int NOISE_MAX_ITER = 10;
 size_t noise_scratch_bytes(int n_img);

@@ -13,6 +13,14 @@
 // stored: membership is the predicate |x - m_cur| <= thr_cur evaluated in
 // FP64, the same arithmetic for every pass, so selection, clipping and the
 // change test are exact and the result equals the FP64 definition.
+//
+// Passes per step: the median's second and third digits (its first is
+// histogrammed by the previous step's clip pass, which already knows the
+// next set), the deviation key's first two digits, then one pass that both
+// histograms its third digit and compacts the few keys that share the
+// chosen 22-bit prefix into a per-image list; its last three digits come
+// from that list (or from the image again if the list overflows), and one
+// clip pass: six image reads per step instead of ten.
 #include <algorithm>
 
 #include "dt_common.hpp"
@@ -91,9 +99,12 @@ __global__ void k_noise_begin(NoiseState* st, int n_img) {
 }
 
 // One digit pass.  KIND 0: key of x; KIND 1: bits of |x - m_new|.
-template <typename T, int KIND>
-__global__ __launch_bounds__(NZ_TX) void k_noise_hist(const void* const* imgs, const int64_t* npix,
-                                                     const NoiseState* st, uint32_t* hist, int lo, int nb) {
+// SRC 0: the image; SRC 1: the image, and keys sharing the prefix above
+// this digit are also appended to the image's list; SRC 2: the list (or the
+// image when the list overflowed).
+template <typename T, int KIND, int SRC>
+__global__ __launch_bounds__(NZ_TX) void k_noise_hist(const void* const* imgs, const int64_t* npix, NoiseState* st,
+                                                     uint32_t* hist, uint64_t* lists, int lo, int nb) {
   const int img = blockIdx.y;
   const NoiseState S = st[img];
   if (S.done) return;
@@ -104,16 +115,47 @@ __global__ __launch_bounds__(NZ_TX) void k_noise_hist(const void* const* imgs, c
   const int hi = lo + nb;  // <= 63 for both key kinds
   const uint64_t p0 = S.prefix[0] >> hi, p1 = S.prefix[1] >> hi;
   const uint32_t mask = (1u << nb) - 1u;
-  const void* X = imgs[img];
-  const int64_t n = npix[img];
-  for (int64_t i = (int64_t)blockIdx.x * NZ_TX + threadIdx.x; i < n; i += (int64_t)gridDim.x * NZ_TX) {
-    const float x = nz_load<T>(X, i);
-    if (!in_set(x, S)) continue;
-    const uint64_t key = KIND == 0 ? fkey(x) : (uint64_t)__double_as_longlong(fabs((double)x - S.m_new));
+  uint64_t* list = lists + (int64_t)img * NOISE_LIST_CAP;
+  auto take = [&](uint64_t key) {
     const uint32_t d = (uint32_t)(key >> lo) & mask;
     const uint64_t top = key >> hi;
     if (top == p0) atomicAdd(&h[0][d], 1u);
     if (two && top == p1) atomicAdd(&h[1][d], 1u);
+    return top == p0 || (two && top == p1);
+  };
+  if (SRC == 2 && S.n_list <= NOISE_LIST_CAP) {
+    for (int64_t i = (int64_t)blockIdx.x * NZ_TX + threadIdx.x; i < S.n_list; i += (int64_t)gridDim.x * NZ_TX)
+      (void)take(list[i]);
+  } else {
+    const void* X = imgs[img];
+    const int64_t n = npix[img];
+    for (int64_t i0 = (int64_t)blockIdx.x * NZ_TX; i0 < n; i0 += (int64_t)gridDim.x * NZ_TX) {
+      const int64_t i = i0 + threadIdx.x;
+      bool keep = false;
+      uint64_t key = 0;
+      if (i < n) {
+        const float x = nz_load<T>(X, i);
+        if (in_set(x, S)) {
+          key = KIND == 0 ? fkey(x) : (uint64_t)__double_as_longlong(fabs((double)x - S.m_new));
+          keep = take(key);
+        }
+      }
+      if (SRC == 1) {
+        // one atomic per wave for the list position of its kept keys
+        const uint64_t ball = __ballot(keep);
+        if (ball) {
+          const int lane = threadIdx.x & 63;
+          int64_t base = 0;
+          if (lane == 0)
+            base = (int64_t)atomicAdd((unsigned long long*)&st[img].n_list, (unsigned long long)__popcll(ball));
+          base = __shfl(base, 0);
+          if (keep) {
+            const int64_t pos = base + __popcll(ball & ((1ull << lane) - 1ull));
+            if (pos < NOISE_LIST_CAP) list[pos] = key;
+          }
+        }
+      }
+    }
   }
   __syncthreads();
   uint32_t* g = hist + (int64_t)img * 2 * NZ_BINS;
@@ -187,6 +229,7 @@ __global__ void k_noise_mid(NoiseState* st, int n_img) {
   NoiseState& S = st[i];
   if (S.done) return;
   S.m_new = 0.5 * (S.val[0] + S.val[1]);
+  S.n_list = 0;
   begin_select(S);
 }
 
@@ -204,12 +247,18 @@ __global__ void k_noise_sigma(NoiseState* st, int n_img, double kappa) {
   S.changed = 0;
 }
 
-// Size of the clipped set and whether any pixel changed membership.
+// Size of the clipped set and whether any pixel changed membership; also the
+// histogram of the first median digit (top 11 bits of the float key) over
+// the clipped set, which is the next step's set if the step is repeated.
 template <typename T>
-__global__ __launch_bounds__(NZ_TX) void k_noise_clip(const void* const* imgs, const int64_t* npix, NoiseState* st) {
+__global__ __launch_bounds__(NZ_TX) void k_noise_clip(const void* const* imgs, const int64_t* npix, NoiseState* st,
+                                                     uint32_t* hist) {
   const int img = blockIdx.y;
   const NoiseState S = st[img];
   if (S.done) return;
+  __shared__ uint32_t h[NZ_BINS];
+  for (int b = threadIdx.x; b < NZ_BINS; b += NZ_TX) h[b] = 0u;
+  __syncthreads();
   const void* X = imgs[img];
   const int64_t n = npix[img];
   uint64_t c = 0;
@@ -222,6 +271,7 @@ __global__ __launch_bounds__(NZ_TX) void k_noise_clip(const void* const* imgs, c
     const bool k_new = fabs(xd - S.m_new) <= S.thr_new;
     c += k_new ? 1u : 0u;
     ch |= (k_old != k_new) ? 1 : 0;
+    if (k_new) atomicAdd(&h[(uint32_t)(fkey(x) >> 21) & (NZ_BINS - 1)], 1u);
   }
   for (int o = 32; o > 0; o >>= 1) {
     c += __shfl_xor(c, o);
@@ -231,6 +281,10 @@ __global__ __launch_bounds__(NZ_TX) void k_noise_clip(const void* const* imgs, c
     if (c) atomicAdd((unsigned long long*)&st[img].n_new, (unsigned long long)c);
     if (ch) atomicOr(&st[img].changed, 1);
   }
+  __syncthreads();
+  uint32_t* g = hist + (int64_t)img * 2 * NZ_BINS;
+  for (int b = threadIdx.x; b < NZ_BINS; b += NZ_TX)
+    if (h[b]) atomicAdd(&g[b], h[b]);
 }
 
 __global__ void k_noise_update(NoiseState* st, int n_img, int max_iter) {
@@ -263,7 +317,7 @@ __global__ void k_noise_out(const NoiseState* st, int n_img, double* sigma, int6
 }
 
 size_t noise_scratch_bytes(int n_img) {
-  return (sizeof(NoiseState) + 2 * NZ_BINS * sizeof(uint32_t)) * (size_t)n_img;
+  return (sizeof(NoiseState) + 2 * NZ_BINS * sizeof(uint32_t) + NOISE_LIST_CAP * sizeof(uint64_t)) * (size_t)n_img;
 }
 
 template <typename T>
@@ -272,6 +326,8 @@ static hipError_t noise_t(const void* const* d_imgs, const int64_t* d_npix, int6
                           ExpMeta* d_meta, hipStream_t s) {
   NoiseState* st = static_cast<NoiseState*>(scratch);
   uint32_t* hist = reinterpret_cast<uint32_t*>(static_cast<char*>(scratch) + sizeof(NoiseState) * (size_t)n_img);
+  uint64_t* lists = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(hist) +
+                                                2 * NZ_BINS * sizeof(uint32_t) * (size_t)n_img);
   const int64_t nh = (int64_t)n_img * 2 * NZ_BINS;
   const unsigned g1 = (unsigned)((std::max<int64_t>(nh, n_img) + 255) / 256);
   const unsigned gi = (unsigned)((n_img + 63) / 64);
@@ -283,18 +339,31 @@ static hipError_t noise_t(const void* const* d_imgs, const int64_t* d_npix, int6
   hipLaunchKernelGGL(k_noise_begin, dim3(gi), dim3(64), 0, s, st, n_img);
   static const int lo_x[3] = {21, 10, 0}, nb_x[3] = {11, 11, 10};
   static const int lo_d[6] = {52, 41, 30, 19, 8, 0}, nb_d[6] = {11, 11, 11, 11, 11, 8};
+  // the first step's first median digit; later steps get it from the clip pass
+  hipLaunchKernelGGL((k_noise_hist<T, 0, 0>), grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist, lists, lo_x[0],
+                     nb_x[0]);
   for (int it = 0; it < max_iter; ++it) {
-    for (int p = 0; p < 3; ++p) {
-      hipLaunchKernelGGL((k_noise_hist<T, 0>), grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist, lo_x[p], nb_x[p]);
+    hipLaunchKernelGGL(k_noise_pick, dim3(n_img), dim3(NZ_TX), 0, s, st, hist, lo_x[0], 0);
+    for (int p = 1; p < 3; ++p) {
+      hipLaunchKernelGGL((k_noise_hist<T, 0, 0>), grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist, lists, lo_x[p],
+                         nb_x[p]);
       hipLaunchKernelGGL(k_noise_pick, dim3(n_img), dim3(NZ_TX), 0, s, st, hist, lo_x[p], 0);
     }
     hipLaunchKernelGGL(k_noise_mid, dim3(gi), dim3(64), 0, s, st, n_img);
     for (int p = 0; p < 6; ++p) {
-      hipLaunchKernelGGL((k_noise_hist<T, 1>), grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist, lo_d[p], nb_d[p]);
+      if (p < 2)
+        hipLaunchKernelGGL((k_noise_hist<T, 1, 0>), grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist, lists, lo_d[p],
+                           nb_d[p]);
+      else if (p == 2)
+        hipLaunchKernelGGL((k_noise_hist<T, 1, 1>), grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist, lists, lo_d[p],
+                           nb_d[p]);
+      else
+        hipLaunchKernelGGL((k_noise_hist<T, 1, 2>), grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist, lists, lo_d[p],
+                           nb_d[p]);
       hipLaunchKernelGGL(k_noise_pick, dim3(n_img), dim3(NZ_TX), 0, s, st, hist, lo_d[p], 1);
     }
     hipLaunchKernelGGL(k_noise_sigma, dim3(gi), dim3(64), 0, s, st, n_img, kappa);
-    hipLaunchKernelGGL(k_noise_clip<T>, grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st);
+    hipLaunchKernelGGL(k_noise_clip<T>, grid, dim3(NZ_TX), 0, s, d_imgs, d_npix, st, hist);
     hipLaunchKernelGGL(k_noise_update, dim3(gi), dim3(64), 0, s, st, n_img, max_iter);
   }
   hipLaunchKernelGGL(k_noise_out, dim3(gi), dim3(64), 0, s, st, n_img, d_sigma, d_used, d_iters, d_meta);
