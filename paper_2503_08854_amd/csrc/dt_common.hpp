@@ -29,6 +29,10 @@ struct alignas(16) ExpMeta {
   double a1x, a1y, a1z;     // row 1
   double px0, py0;          // CRPIX - 1
   double gap, inv_gap;      // epoch step from the previous exposure (epoch order) and its reciprocal
+  // Sky cone holding every direction that projects into the pixel rectangle
+  // widened by one pixel: unit axis u, tangent of the half-angle, and the
+  // limit of the cone test (0; +inf with u = 0 when no cone is used).
+  double ux, uy, uz, cone_tan, cone_lim;
   int64_t plane_off;        // offset of this exposure's plane (in float2 units)
   int32_t W, H;             // image size
   int32_t src;              // caller's index of this exposure
@@ -36,7 +40,7 @@ struct alignas(16) ExpMeta {
   int32_t R;                // stamp half-width ceil(3 sigma)
   float vs;                 // scalar pixel variance when the patch has no variance planes
 };
-static_assert(sizeof(ExpMeta) == 176, "ExpMeta layout");
+static_assert(sizeof(ExpMeta) == 208, "ExpMeta layout");
 
 // One tile of the matched-filter pre-pass.
 struct PrepTile {

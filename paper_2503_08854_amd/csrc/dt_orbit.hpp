@@ -26,7 +26,8 @@
 //     corrected epoch), which bounds them below 1e-15 AU.
 // The common case (small steps) runs straight-line code; the general paths
 // (cold start, long rotations, light-time re-solves) are taken per lane only
-// when a bound above is not met.
+// when a bound above is not met, and their loops stay rolled so the loop over
+// exposures stays small.
 #pragma once
 #include "dt_common.hpp"
 
@@ -67,13 +68,13 @@ __device__ __forceinline__ void sqrt_rsq(double x, double& s, double& rs) {
 
 // Per-orbit constants ("orbit preparation"): with P the unit vector to
 // perihelion and Q the one 90 deg ahead in the orbit plane (ecliptic),
-// r(E) = a (cos E - e) P + b sin E Q = cos E aP + sin E bQ + c0 and
-// v(E) = n g (-sin E aP + cos E bQ), g = 1 / (1 - e cos E).
+// r(E) = (cos E - e) aP + sin E bQ and v(E) = n g (-sin E aP + cos E bQ),
+// g = 1 / (1 - e cos E).
 struct Orbit {
   double e, n, m0, he;          // eccentricity, mean motion k a^-3/2, M0, -e/2
   double aP0, aP1, aP2;         // a P
   double bQ0, bQ1, bQ2;         // b Q, b = a sqrt(1 - e^2)
-  double c00, c01, c02;         // -a e P
+  double mq;                    // bound on (1 + 0.1) |D v| for any |D0| <= LT_LINEAR_MAX (AU)
 };
 
 struct KepState {
@@ -106,9 +107,10 @@ __device__ __forceinline__ void orbit_prep(double a, double e, double inc, doubl
   o.bQ0 = b * Q0;
   o.bQ1 = b * Q1;
   o.bQ2 = b * Q2;
-  o.c00 = -e * o.aP0;
-  o.c01 = -e * o.aP1;
-  o.c02 = -e * o.aP2;
+  // |v| <= n a sqrt((1 + e) / (1 - e)) (the perihelion speed); the applied
+  // correction D = D0 (1 - rv / c) obeys |D| <= |D0| (1 + vmax / c)
+  const double vmax = o.n * a * sqrt((1.0 + e) / (1.0 - e));
+  o.mq = 1.1002 * LT_LINEAR_MAX * vmax * (1.0 + vmax * (1.0 / C_AU_DAY));
 }
 
 // Rotate (sE, cE) by d: sin d and cos d - 1 from their Taylor series.
@@ -158,6 +160,7 @@ __device__ inline void kepler_cold(double M, double e, KepState& k) {
   double E = Mr + 0.85 * e * (Mr > 0.0 ? 1.0 : (Mr < 0.0 ? -1.0 : 0.0));
   E = fmin(fmax(E, lo), hi);
   double s, c;
+#pragma unroll 1
   for (int it = 0; it < 60; ++it) {
     sincos(E, &s, &c);
     double f = E - e * s - Mr;
@@ -199,6 +202,7 @@ __device__ inline void kepler_general(double M, double e, KepState& k, bool anch
   } else {
     rot_long(k, d);
   }
+#pragma unroll 1
   for (int it = 0; it < 8; ++it) {
     k.g = rcp1(fma(-e, k.cE, 1.0));
     double dd = -fma(-e, k.sE, k.E - M) * k.g;
@@ -220,10 +224,13 @@ __device__ __forceinline__ bool kepler_warm(double M, double he, double e, KepSt
   d = fma(he * k.sE * k.g, d * d, d);
   if (anchor || !(fabs(d) <= ROT_SHORT)) return false;
   rot_short(k, d);
-  double g = rcp1(fma(-e, k.cE, 1.0));
+  // the raw reciprocal estimate (relative error ~1e-7) suffices here: it
+  // scales a Newton step that is itself below 1e-8 rad, and the next start
+  double g = __builtin_amdgcn_rcp(fma(-e, k.cE, 1.0));
   double dd = -fma(-e, k.sE, k.E - M) * g;
   k.g = g;
   if (!(fabs(dd) < 1e-8)) {  // rare: the start was poor, take more Newton steps
+#pragma unroll 1
     for (int it = 1; it < 8; ++it) {
       rot_long(k, dd);
       g = rcp1(fma(-e, k.cE, 1.0));
@@ -254,81 +261,131 @@ struct LtState {
 
 // Heliocentric state at t - tg and the one-step light-time correction D.
 struct LtSolve {
-  double rho0, rho1, rho2, v0, v1, v2, D, dist;
+  double rho0, rho1, rho2, d2, rdist, dist0, dist, v0, v1, v2, D;
 };
 
-__device__ __forceinline__ void lt_state(const Orbit& o, const KepState& k, double b0, double b1, double b2,
-                                         double tg, LtSolve& s) {
-  // rho = r(t - tg) - r_obs, v = dr/dt
+constexpr double IC = 1.0 / C_AU_DAY;  // days per AU of light travel
+
+// Relative error bound used for the raw hardware estimates of 1/sqrt(x) and
+// sqrt(x) = x rsq(x): twice the documented 2^29 ulp (~1.2e-7).
+constexpr double RSQ_REL = 2.5e-7;
+
+// rho = r(t - tg) - r_obs given -r_obs = (b0, b1, b2), and |rho| from the raw
+// estimate (dist0, relative error below RSQ_REL).
+__device__ __forceinline__ void lt_pos(const Orbit& o, const KepState& k, double b0, double b1, double b2,
+                                       LtSolve& s) {
+  const double cme = k.cE - o.e;
+  s.rho0 = fma(cme, o.aP0, fma(k.sE, o.bQ0, b0));
+  s.rho1 = fma(cme, o.aP1, fma(k.sE, o.bQ1, b1));
+  s.rho2 = fma(cme, o.aP2, fma(k.sE, o.bQ2, b2));
+  s.d2 = fma(s.rho0, s.rho0, fma(s.rho1, s.rho1, s.rho2 * s.rho2));
+  s.rdist = __builtin_amdgcn_rsq(s.d2);
+  s.dist0 = s.d2 * s.rdist;
+}
+// dist to full precision by one Newton correction of x rsq(x); the raw rdist
+// only scales rv, where a relative error of 1e-5 changes D by less than 1e-7
+// relative.
+__device__ __forceinline__ void lt_refine(LtSolve& s) {
+  s.dist = fma(fma(-s.dist0, s.dist0, s.d2), 0.5 * s.rdist, s.dist0);
+}
+
+// v = dr/dt and the Newton step on F(D) = c (tg + D) - |rho - D v| from D = 0,
+// with 1 / (c + rv) = (1 / c) (1 - rv / c) to a relative (rv / c)^2 < 1e-7.
+__device__ __forceinline__ void lt_vel(const Orbit& o, const KepState& k, double tg, LtSolve& s) {
   const double ng = o.n * k.g;
   const double vs = -ng * k.sE, vc = ng * k.cE;
   s.v0 = fma(vc, o.bQ0, vs * o.aP0);
   s.v1 = fma(vc, o.bQ1, vs * o.aP1);
   s.v2 = fma(vc, o.bQ2, vs * o.aP2);
-  s.rho0 = fma(k.cE, o.aP0, fma(k.sE, o.bQ0, b0));
-  s.rho1 = fma(k.cE, o.aP1, fma(k.sE, o.bQ1, b1));
-  s.rho2 = fma(k.cE, o.aP2, fma(k.sE, o.bQ2, b2));
-  // dist to full precision by one Newton correction of x * rsq(x); the raw
-  // estimate rdist only scales rv, where a relative error of 1e-5 changes D
-  // by less than 1e-7 relative
-  const double d2 = fma(s.rho0, s.rho0, fma(s.rho1, s.rho1, s.rho2 * s.rho2));
-  const double rdist = __builtin_amdgcn_rsq(d2);
-  const double g0 = d2 * rdist;
-  s.dist = fma(fma(-g0, g0, d2), 0.5 * rdist, g0);
-  // Newton step on F(D) = c (tg + D) - |rho - D v| from D = 0
-  const double rv = fma(s.rho0, s.v0, fma(s.rho1, s.v1, s.rho2 * s.v2)) * rdist;
-  // 1 / (c + rv) = (1 / c) (1 - rv / c) to a relative (rv / c)^2 < 1e-7
-  constexpr double IC = 1.0 / C_AU_DAY;
+  const double rv = fma(s.rho0, s.v0, fma(s.rho1, s.v1, s.rho2 * s.v2)) * s.rdist;
   s.D = fma(s.dist, IC, -tg) * fma(-rv, IC, 1.0);
+}
+
+__device__ __forceinline__ void lt_state(const Orbit& o, const KepState& k, double b0, double b1, double b2,
+                                         double tg, LtSolve& s) {
+  lt_pos(o, k, b0, b1, b2, s);
+  lt_refine(s);
+  lt_vel(o, k, tg, s);
 }
 
 // One (orbit, exposure) sample.  FIRST: the orbit's first exposure (cold
 // Kepler start, no light-time history).  Otherwise `gap` is t_e minus the
 // previous exposure's epoch and inv_gap its reciprocal (0 when gap == 0);
 // `anchor` re-anchors sin E, cos E with a full sincos.
-template <bool FIRST>
+//
+// EXACT = false (walks that only use `inside`) first tests the uncorrected
+// position rho against the exposure's sky cone.  The exact position is
+// rho - D v with |D| <= |D0| (1 + vmax / c), D0 = |rho| / c - tg, so when
+// |D0| <= LT_LINEAR_MAX (tested on the raw distance with the slack of its
+// error bound) it lies within |D v| of rho; moving a point by d
+// changes its distance from the cone axis by at most d and its projection on
+// the axis by at most d.  A point that can land in the image therefore obeys
+// perp(rho) <= tan(theta) (u . rho) + (1 + tan theta) |D v| <= tan(theta) (u . rho) + mq.
+// Samples that fail this test keep the Kepler and light-time history (the
+// light time is taken as tg + D0) and report inside = front = false; their
+// px, py, ix, iy are not computed.  All others, and every sample of an
+// EXACT walk, take the full path below.
+template <bool FIRST, bool EXACT>
 __device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt, const ExpMeta& x, double epoch,
                                        double gap, double inv_gap, bool anchor, SampleOut& out) {
   const double dt = x.t - epoch;
   double tg = FIRST ? 0.0 : fma(lt.rate, gap, lt.tau);
-  const double b0 = o.c00 - x.ox, b1 = o.c01 - x.oy, b2 = o.c02 - x.oz;
+  const double b0 = -x.ox, b1 = -x.oy, b2 = -x.oz;
   LtSolve s;
-  // common path straight-line: warm Kepler step, state, one light-time step
+  // common path straight-line: warm Kepler step, position, light-time estimate
   double M = fma(o.n, dt - tg, o.m0);
   if (FIRST || !kepler_warm(M, o.he, o.e, k, anchor)) kepler_general(M, o.e, k, !FIRST && anchor, FIRST);
-  lt_state(o, k, b0, b1, b2, tg, s);
-  if (!(fabs(s.D) <= LT_LINEAR_MAX)) {
-    // poor prediction: solve the orbit again at the corrected epoch (at most 3 times)
-    for (int pass = 1; pass <= 3; ++pass) {
-      tg += s.D;
-      M = fma(o.n, dt - tg, o.m0);
-      kepler_general(M, o.e, k, false, false);
-      lt_state(o, k, b0, b1, b2, tg, s);
-      if (fabs(s.D) <= LT_LINEAR_MAX) break;
-    }
+  lt_pos(o, k, b0, b1, b2, s);
+  const double D0 = fma(s.dist0, IC, -tg);
+  bool full = EXACT || FIRST;
+  if (!full) {
+    // evaluated without branches (bitwise, not short-circuit, logic)
+    const double sc = fma(x.ux, s.rho0, fma(x.uy, s.rho1, x.uz * s.rho2));
+    const double R = fma(x.cone_tan, sc, o.mq);
+    full = !(fma(s.dist0, RSQ_REL * IC, fabs(D0)) <= LT_LINEAR_MAX) |
+           ((R >= 0.0) & (fma(-R, R, fma(-sc, sc, s.d2)) <= x.cone_lim));
   }
-  const double D = s.D;
-  const double q0 = fma(-D, s.v0, s.rho0), q1 = fma(-D, s.v1, s.rho1), q2 = fma(-D, s.v2, s.rho2);
-  const double tau = tg + D;
+  double tau;
+  if (full) {
+    lt_refine(s);
+    lt_vel(o, k, tg, s);
+    if (!(fabs(s.D) <= LT_LINEAR_MAX)) {
+      // poor prediction: solve the orbit again at the corrected epoch (at most 3 times)
+#pragma unroll 1
+      for (int pass = 1; pass <= 3; ++pass) {
+        tg += s.D;
+        M = fma(o.n, dt - tg, o.m0);
+        kepler_general(M, o.e, k, false, false);
+        lt_state(o, k, b0, b1, b2, tg, s);
+        if (fabs(s.D) <= LT_LINEAR_MAX) break;
+      }
+    }
+    const double D = s.D;
+    const double q0 = fma(-D, s.v0, s.rho0), q1 = fma(-D, s.v1, s.rho1), q2 = fma(-D, s.v2, s.rho2);
+    tau = tg + D;
+    // TAN projection: p = CRPIX - 1 + (A . q) / (c . q)
+    const double w = fma(x.cx, q0, fma(x.cy, q1, x.cz * q2));
+    const double iw = rcp1(w);
+    out.px = fma(fma(x.a0x, q0, fma(x.a0y, q1, x.a0z * q2)), iw, x.px0);
+    out.py = fma(fma(x.a1x, q0, fma(x.a1y, q1, x.a1z * q2)), iw, x.py0);
+    out.front = (w > 0.0) && (s.dist >= 1e-9);
+    // nearest pixel floor(p + 0.5), clamped into int range before conversion
+    const double fx = floor(out.px + 0.5), fy = floor(out.py + 0.5);
+    out.ix = (int)fmin(fmax(fx, -2147483648.0), 2147483647.0);
+    out.iy = (int)fmin(fmax(fy, -2147483648.0), 2147483647.0);
+    out.inside = out.front && (unsigned)out.ix < (unsigned)x.W && (unsigned)out.iy < (unsigned)x.H;
+  } else {
+    tau = tg + D0;
+    out.front = out.inside = false;
+  }
   lt.rate = FIRST ? 0.0 : (tau - lt.tau) * inv_gap;
   lt.tau = tau;
   out.tau = tau;
-  // TAN projection: p = CRPIX - 1 + (A . q) / (c . q)
-  const double w = fma(x.cx, q0, fma(x.cy, q1, x.cz * q2));
-  const double iw = rcp1(w);
-  out.px = fma(fma(x.a0x, q0, fma(x.a0y, q1, x.a0z * q2)), iw, x.px0);
-  out.py = fma(fma(x.a1x, q0, fma(x.a1y, q1, x.a1z * q2)), iw, x.py0);
-  out.front = (w > 0.0) && (s.dist >= 1e-9);
-  // nearest pixel floor(p + 0.5), clamped into int range before conversion
-  const double fx = floor(out.px + 0.5), fy = floor(out.py + 0.5);
-  out.ix = (int)fmin(fmax(fx, -2147483648.0), 2147483647.0);
-  out.iy = (int)fmin(fmax(fy, -2147483648.0), 2147483647.0);
-  out.inside = out.front && (unsigned)out.ix < (unsigned)x.W && (unsigned)out.iy < (unsigned)x.H;
 }
 
 // The walk over one orbit's exposures in epoch order: calls f(ex, out) for
-// every exposure after its sample.
-template <typename F>
+// every exposure after its sample (EXACT: see sample()).
+template <bool EXACT, typename F>
 __device__ __forceinline__ void walk_orbit(const Orbit& o, const ExpMeta* __restrict__ meta, int n_exp, double epoch,
                                            F&& f) {
   KepState k;
@@ -338,9 +395,9 @@ __device__ __forceinline__ void walk_orbit(const Orbit& o, const ExpMeta* __rest
     const ExpMeta& x = meta[ex];
     SampleOut so;
     if (ex == 0)
-      sample<true>(o, k, lt, x, epoch, 0.0, 0.0, false, so);
+      sample<true, EXACT>(o, k, lt, x, epoch, 0.0, 0.0, false, so);
     else
-      sample<false>(o, k, lt, x, epoch, x.gap, x.inv_gap, (ex % ANCHOR) == 0, so);
+      sample<false, EXACT>(o, k, lt, x, epoch, x.gap, x.inv_gap, (ex % ANCHOR) == 0, so);
     f(ex, so);
   }
 }

@@ -11,6 +11,10 @@
 
 namespace dtk {
 
+#ifndef STACK_DEFER
+#define STACK_DEFER 1
+#endif
+
 template <bool DEBUG>
 __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const DebugArgs* dbg, int64_t row,
                                             float& snr_out, float& flux_out, int& nv_out) {
@@ -33,8 +37,29 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
   ps.init();
   ph.init();
   int nv = 0;
-  walk_orbit(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
+  // Without the debug table a gather is accumulated STACK_DEFER exposures
+  // later (still in epoch order), so its load latency overlaps the arithmetic
+  // of the following samples.
+  float2 pend[STACK_DEFER];
+#pragma unroll
+  for (int i = 0; i < STACK_DEFER; ++i) pend[i] = make_float2(0.f, 0.f);
+  auto take = [&](float2 v) {
+    if (v.y > 0.f) {
+      ps.add(v.x);
+      ph.add(v.y);
+      nv++;
+    }
+  };
+  walk_orbit<DEBUG>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
     const ExpMeta& x = A.meta[ex];
+    if (!DEBUG) {
+      take(pend[0]);
+#pragma unroll
+      for (int i = 0; i + 1 < STACK_DEFER; ++i) pend[i] = pend[i + 1];
+      pend[STACK_DEFER - 1] =
+          so.inside ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
+      return;
+    }
     float2 v = make_float2(0.f, 0.f);
     bool valid = false;
     if (so.inside) {
@@ -61,6 +86,10 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
         dbg->off[(int64_t)ex * dbg->m + row] = valid ? (uint32_t)(x.plane_off + (int64_t)so.iy * x.W + so.ix) : ~0u;
     }
   });
+  if (!DEBUG) {
+#pragma unroll
+    for (int i = 0; i < STACK_DEFER; ++i) take(pend[i]);
+  }
   const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
   snr_out = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
   flux_out = Phi > 0.f ? Psi / Phi : 0.f;

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_clip_samples(StackArgs A, const int64_t
   }
   Orbit ob;
   orbit_prep(a, e, inc, node, peri, m0, ob);
-  walk_orbit(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
+  walk_orbit<false>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
     const ExpMeta& x = A.meta[ex];
     float2 v = make_float2(0.f, 0.f);
     if (so.inside) {

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_s
     ps.init();
     ph.init();
     int cnt = 0;
-    walk_orbit(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
+    walk_orbit<false>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
       if (!so.inside) return;
       const ExpMeta& x = A.meta[ex];
       const float2 v = A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix];

@@ -79,6 +79,40 @@ __global__ void k_exposure_prep(const dt_exposure* __restrict__ in, const int64_
   m.fwhm = x.psf_fwhm_px;
   m.R = rad[i];
   m.vs = 0.f;
+  // Sky cone of the image.  The pixel (x, y) is the direction
+  // c + xi e + eta n with (xi, eta) = CD (x - px0, y - py0) in radians; the
+  // axis is the centre pixel's direction and the half-angle is the largest
+  // angle to a corner of the rectangle widened by one pixel.  The cone's
+  // trace on the tangent plane is an ellipse (convex) when the axis is within
+  // ~78 deg of c and the half-angle below ~6 deg, so holding the four corners
+  // it holds the whole rectangle.  Otherwise no cone is used.
+  auto dir = [&](double px, double py, double d[3]) {
+    const double dx = px - m.px0, dy = py - m.py0;
+    const double xi = d2r * (x.cd_deg[0] * dx + x.cd_deg[1] * dy);
+    const double eta = d2r * (x.cd_deg[2] * dx + x.cd_deg[3] * dy);
+    for (int k = 0; k < 3; ++k) d[k] = cE[k] + xi * eE[k] + eta * nE[k];
+  };
+  double u[3];
+  dir(0.5 * (x.width - 1), 0.5 * (x.height - 1), u);
+  const double un = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  for (int k = 0; k < 3; ++k) u[k] *= un;
+  bool cone = (u[0] * cE[0] + u[1] * cE[1] + u[2] * cE[2]) > 0.2;
+  double tmax = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    double d[3];
+    dir((q & 1) ? x.width + 0.5 : -1.5, (q & 2) ? x.height + 0.5 : -1.5, d);
+    const double cs = u[0] * d[0] + u[1] * d[1] + u[2] * d[2];
+    const double c0 = u[1] * d[2] - u[2] * d[1], c1 = u[2] * d[0] - u[0] * d[2], c2 = u[0] * d[1] - u[1] * d[0];
+    const double sn = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+    if (!(cs > 0.0)) cone = false;
+    else tmax = fmax(tmax, sn / cs);
+  }
+  cone = cone && tmax <= 0.1;
+  m.ux = cone ? u[0] : 0.0;
+  m.uy = cone ? u[1] : 0.0;
+  m.uz = cone ? u[2] : 0.0;
+  m.cone_tan = cone ? tmax * 1.0001 + 1e-12 : 0.0;
+  m.cone_lim = cone ? 0.0 : __builtin_inf();
   out[i] = m;
 }
 

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
       } else {
         Orbit ob;
         orbit_prep(a, e, inc, node, peri, m0, ob);
-        walk_orbit(ob, meta + ex0, cnt, R.epoch, [&](int i, const SampleOut& so) {
+        walk_orbit<true>(ob, meta + ex0, cnt, R.epoch, [&](int i, const SampleOut& so) {
           tr[i] = so.front ? make_double2(so.px, so.py) : make_double2(nan, nan);
         });
       }

@@ -56,6 +56,21 @@ def test_batched_equals_per_patch_and_oracle(batch):
         assert ok.all(), f"patch {p}: {(~ok).sum()} orbits off"
 
 
+def test_pruned_stack_equals_exact_walk(batch):
+    """Sky-cone pruning against the exact walk on every patch, near-Earth
+    geometries (light-time shift up to pixels) included."""
+    import torch
+    import paper_2503_08854_amd as dt
+    for p, (patch, orb) in enumerate(zip(batch["patches"], batch["sets"])):
+        snr, flux, nv = dt.stack(patch, orb)
+        off = dt.record_gathers(patch, orb, np.arange(orb.n))
+        rep = dt.gather_replay(patch, off)
+        torch.cuda.synchronize()
+        nv = nv.cpu().numpy()
+        np.testing.assert_array_equal(np.maximum(nv, 0), (off.cpu().numpy() != -1).sum(axis=0), err_msg=f"patch {p}")
+        np.testing.assert_array_equal(rep.cpu().numpy(), np.where(nv >= 0, snr.cpu().numpy(), 0.0).astype(np.float32))
+
+
 def test_graph_replay_matches_eager(batch):
     import torch
     import paper_2503_08854_amd as dt
