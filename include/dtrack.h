@@ -294,7 +294,11 @@ dt_status dt_cell_stamps(dt_patch *p, const dt_orbits *reps, double da, double d
 /* The plain stack (as dt_stack) on the orbits of n_cells selected cells
  * (device int64 cell ids; negative ids are skipped); outputs are written at
  * the orbits' indices in the full-grid arrays d_snr / d_flux / d_nvalid
- * (device, grid->n each), other entries are left untouched. */
+ * (device, grid->n each), other entries are left untouched.  Valid counts
+ * equal dt_stack's; when few orbits are selected each orbit's exposures are
+ * walked in up to four contiguous ranges whose compensated sums are merged
+ * in range order, so S/N and flux agree with dt_stack's to rounding
+ * (deterministically for a given selection size). */
 dt_status dt_stack_cells(dt_patch *p, const dt_orbits *grid, const int64_t *d_cells, int64_t n_cells,
                          int32_t cell_size, float *d_snr, float *d_flux, int32_t *d_nvalid);
 

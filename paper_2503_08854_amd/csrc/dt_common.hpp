@@ -160,7 +160,8 @@ struct ScorerFusedArgs {
   int K[7], N[7];
   float* z;                // B logits
 };
-hipError_t launch_scorer_fused(const ScorerFusedArgs& a, hipStream_t s);
+// transpose: rebuild A.wt from A.wb first (needed after the weights changed).
+hipError_t launch_scorer_fused(const ScorerFusedArgs& a, bool transpose, hipStream_t s);
 
 // Replay of a recorded gather stream (measurement yardstick).
 hipError_t launch_gather_replay(const float2* planes, const uint32_t* off, int64_t m, int n_exp, float* snr,

@@ -53,6 +53,8 @@ struct dt_scorer {
   // activations (BF16) and backward buffers
   uint16_t *col1, *h1, *col2, *h2, *col3, *h3, *cat, *h6;
   uint16_t* wt = nullptr;  // transposed BF16 weights for the fused inference kernel
+  int64_t wver = 0;        // bumped whenever wb is rewritten
+  int64_t wt_ver = -1;     // the wb version wt was transposed from
   float* z;
   float *dz, *df, *dbig, *dmid;
   uint16_t *dz_b, *d_b, *d_mid_b;
@@ -215,6 +217,7 @@ dt_status dt_scorer_create(dt_ctx* c, int32_t max_batch, uint64_t seed, dt_score
   if (e == hipSuccess) e = hipMemsetAsync(s->m, 0, sizeof(float) * s->np, c->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->v, 0, sizeof(float) * s->np, c->stream);
   if (e == hipSuccess) e = launch_cast_bf16(s->w, s->np, s->wb, c->stream);
+  s->wver++;
   if (e != hipSuccess) {
     sfree(s);
     delete s;
@@ -249,6 +252,7 @@ dt_status dt_scorer_set_params(dt_scorer* s, const float* d_in) {
   if (e == hipSuccess) e = hipMemsetAsync(s->m, 0, sizeof(float) * s->np, st);
   if (e == hipSuccess) e = hipMemsetAsync(s->v, 0, sizeof(float) * s->np, st);
   if (e == hipSuccess) e = launch_cast_bf16(s->w, s->np, s->wb, st);
+  s->wver++;
   s->step = 0;
   return e == hipSuccess ? DT_OK : hip_fail(e, "scorer set params");
 }
@@ -289,8 +293,11 @@ dt_status dt_scorer_infer(dt_scorer* s, const uint16_t* d_stamps, const uint16_t
   a.t_off[NL] = t;
   a.wt = s->wt;
   a.z = d_logits;
-  hipError_t e = launch_scorer_fused(a, s->ctx->stream);
-  return e == hipSuccess ? DT_OK : hip_fail(e, "scorer inference");
+  // the transposed weights are rebuilt only after the weights changed
+  hipError_t e = launch_scorer_fused(a, s->wt_ver != s->wver, s->ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "scorer inference");
+  s->wt_ver = s->wver;
+  return DT_OK;
 }
 
 dt_status dt_scorer_grad(dt_scorer* s, const uint16_t* d_stamps, const uint16_t* d_feats, const float* d_labels,
@@ -313,6 +320,7 @@ dt_status dt_scorer_train_step(dt_scorer* s, const uint16_t* d_stamps, const uin
   hipError_t e = forward(s, d_stamps, d_feats, B, nullptr);
   if (e == hipSuccess) e = backward(s, d_feats, d_labels, B, d_loss, s->g);
   if (e == hipSuccess) e = launch_adam(s->w, s->m, s->v, s->g, s->np, lr, ++s->step, s->wb, s->ctx->stream);
+  s->wver++;
   return e == hipSuccess ? DT_OK : hip_fail(e, "scorer train step");
 }
 

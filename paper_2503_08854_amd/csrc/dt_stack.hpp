@@ -11,10 +11,52 @@
 
 namespace dtk {
 
-#ifndef STACK_DEFER
-#define STACK_DEFER 1
-#endif
+// Compensated sums of one prepared orbit over exposures [ex0, ex0 + cnt)
+// (epoch order; no debug table).  Each gather is accumulated one exposure
+// later, still in epoch order, so its load latency overlaps the next sample's
+// arithmetic (deeper deferral measured slower: the loads are conditional, so
+// the wait before a use covers all of them).
+struct StackPart {
+  Kahan ps, ph;
+  int nv;
+};
+__device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob, int ex0, int cnt, StackPart& P) {
+  P.ps.init();
+  P.ph.init();
+  P.nv = 0;
+  float2 pend = make_float2(0.f, 0.f);
+  auto take = [&](float2 v) {
+    if (v.y > 0.f) {
+      P.ps.add(v.x);
+      P.ph.add(v.y);
+      P.nv++;
+    }
+  };
+  walk_orbit<false>(ob, A.meta + ex0, cnt, A.epoch, [&](int i, const SampleOut& so) {
+    const ExpMeta& x = A.meta[ex0 + i];
+    take(pend);
+    pend = so.inside ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
+  });
+  take(pend);
+}
 
+// S/N = Psi / sqrt(Phi), flux = Psi / Phi (0 when Phi = 0).
+__device__ __forceinline__ void stack_finish(const StackPart& P, float& snr_out, float& flux_out, int& nv_out) {
+  const float Psi = P.ps.s - P.ps.c, Phi = P.ph.s - P.ph.c;
+  snr_out = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
+  flux_out = Phi > 0.f ? Psi / Phi : 0.f;
+  nv_out = P.nv;
+}
+
+__device__ __forceinline__ void stack_walk(const StackArgs& A, const Orbit& ob, float& snr_out, float& flux_out,
+                                           int& nv_out) {
+  StackPart P;
+  stack_range(A, ob, 0, A.n_exp, P);
+  stack_finish(P, snr_out, flux_out, nv_out);
+}
+
+// One orbit of the stack; DEBUG also fills the per-sample table of `dbg`
+// (row `row`), walking every sample exactly.
 template <bool DEBUG>
 __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const DebugArgs* dbg, int64_t row,
                                             float& snr_out, float& flux_out, int& nv_out) {
@@ -33,33 +75,16 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
   }
   Orbit ob;
   orbit_prep(a, e, inc, node, peri, m0, ob);
+  if (!DEBUG) {
+    stack_walk(A, ob, snr_out, flux_out, nv_out);
+    return;
+  }
   Kahan ps, ph;
   ps.init();
   ph.init();
   int nv = 0;
-  // Without the debug table a gather is accumulated STACK_DEFER exposures
-  // later (still in epoch order), so its load latency overlaps the arithmetic
-  // of the following samples.
-  float2 pend[STACK_DEFER];
-#pragma unroll
-  for (int i = 0; i < STACK_DEFER; ++i) pend[i] = make_float2(0.f, 0.f);
-  auto take = [&](float2 v) {
-    if (v.y > 0.f) {
-      ps.add(v.x);
-      ph.add(v.y);
-      nv++;
-    }
-  };
-  walk_orbit<DEBUG>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
+  walk_orbit<true>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
     const ExpMeta& x = A.meta[ex];
-    if (!DEBUG) {
-      take(pend[0]);
-#pragma unroll
-      for (int i = 0; i + 1 < STACK_DEFER; ++i) pend[i] = pend[i + 1];
-      pend[STACK_DEFER - 1] =
-          so.inside ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
-      return;
-    }
     float2 v = make_float2(0.f, 0.f);
     bool valid = false;
     if (so.inside) {
@@ -71,25 +96,19 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
         nv++;
       }
     }
-    if (DEBUG) {
-      const int64_t q = row * A.n_exp + x.src;
-      const bool f = so.front;
-      if (dbg->px) dbg->px[q] = f ? so.px : __builtin_nan("");
-      if (dbg->py) dbg->py[q] = f ? so.py : __builtin_nan("");
-      if (dbg->ix) dbg->ix[q] = f ? so.ix : (int)0x80000000;
-      if (dbg->iy) dbg->iy[q] = f ? so.iy : (int)0x80000000;
-      if (dbg->tau) dbg->tau[q] = so.tau;
-      if (dbg->flags) dbg->flags[q] = (f ? 1 : 0) | (so.inside ? 2 : 0) | (valid ? 4 : 0);
-      if (dbg->psi) dbg->psi[q] = valid ? v.x : 0.f;
-      if (dbg->phi) dbg->phi[q] = valid ? v.y : 0.f;
-      if (dbg->off)
-        dbg->off[(int64_t)ex * dbg->m + row] = valid ? (uint32_t)(x.plane_off + (int64_t)so.iy * x.W + so.ix) : ~0u;
-    }
+    const int64_t q = row * A.n_exp + x.src;
+    const bool f = so.front;
+    if (dbg->px) dbg->px[q] = f ? so.px : __builtin_nan("");
+    if (dbg->py) dbg->py[q] = f ? so.py : __builtin_nan("");
+    if (dbg->ix) dbg->ix[q] = f ? so.ix : (int)0x80000000;
+    if (dbg->iy) dbg->iy[q] = f ? so.iy : (int)0x80000000;
+    if (dbg->tau) dbg->tau[q] = so.tau;
+    if (dbg->flags) dbg->flags[q] = (f ? 1 : 0) | (so.inside ? 2 : 0) | (valid ? 4 : 0);
+    if (dbg->psi) dbg->psi[q] = valid ? v.x : 0.f;
+    if (dbg->phi) dbg->phi[q] = valid ? v.y : 0.f;
+    if (dbg->off)
+      dbg->off[(int64_t)ex * dbg->m + row] = valid ? (uint32_t)(x.plane_off + (int64_t)so.iy * x.W + so.ix) : ~0u;
   });
-  if (!DEBUG) {
-#pragma unroll
-    for (int i = 0; i < STACK_DEFER; ++i) take(pend[i]);
-  }
   const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
   snr_out = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
   flux_out = Phi > 0.f ? Psi / Phi : 0.f;

@@ -105,24 +105,7 @@ __global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_s
   if (gen_orbit(S, (uint64_t)(first + i), el) && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5])) {
     Orbit ob;
     orbit_prep(el[0], el[1], el[2], el[3], el[4], el[5], ob);
-    Kahan ps, ph;
-    ps.init();
-    ph.init();
-    int cnt = 0;
-    walk_orbit<false>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
-      if (!so.inside) return;
-      const ExpMeta& x = A.meta[ex];
-      const float2 v = A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix];
-      if (v.y > 0.f) {
-        ps.add(v.x);
-        ph.add(v.y);
-        cnt++;
-      }
-    });
-    const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
-    snr = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
-    flux = Phi > 0.f ? Psi / Phi : 0.f;
-    nv = cnt;
+    stack_walk(A, ob, snr, flux, nv);
   }
   if (A.snr) A.snr[i] = snr;
   if (A.flux) A.flux[i] = flux;

@@ -2,9 +2,11 @@
 //
 // The same network and rounding points as the layer-by-layer path (every
 // activation rounded to BF16 after bias and ReLU, FP32 accumulation on
-// v_mfma_f32_16x16x16_bf16 in the same K order, FP32 biases), with every
-// intermediate kept in LDS.  A workgroup of four waves takes 16 cells at a
-// time and makes them the M dimension of every MFMA tile: a convolution
+// v_mfma_f32_16x16x16_bf16 in the same K order except that the 1152-deep
+// layer sums two K halves, FP32 biases), with every intermediate kept in LDS.
+// A workgroup of eight waves (two per SIMD, so one wave's MFMA and LDS
+// latency overlaps the other's; the LDS holds one workgroup per CU) takes 16
+// cells at a time and makes them the M dimension of every MFMA tile: a convolution
 // output pixel is one 16 (cells) x 16 (channels) tile whose A operand reads
 // the input pixel's 16-channel group of every cell (one 8-byte LDS read per
 // lane), so all pixel and tap arithmetic is uniform across the wave.  The
@@ -50,6 +52,8 @@ __device__ __forceinline__ void store4(uint16_t* o, int kq, int r16, int stride,
 }
 
 constexpr int G = 16;                        // cells per workgroup
+constexpr int NW = 8;                        // waves per workgroup
+constexpr int NTH = 64 * NW;                 // threads per workgroup
 constexpr int W1K = 16, W2K = 148, W3K = 292;  // padded K strides of the conv weights in LDS
 constexpr int FTS = 20, CTS = 132, H6S = 68;
 constexpr int SPAD = 23 * 23;                // the stamp with a one-pixel zero border
@@ -68,7 +72,7 @@ __global__ void k_scorer_transpose(const uint16_t* __restrict__ wb, uint16_t* __
   wt[i] = wb[A.w_off[l] + (int64_t)k * N + n];
 }
 
-__global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
+__global__ __launch_bounds__(NTH) void k_scorer_fused(ScorerFusedArgs A) {
   // A workgroup owns 16 cells at a time; the cells are the M (row) dimension
   // of every MFMA tile, so all pixel / tap index arithmetic is uniform.
   // Activations are [pixel][cell][channel]; the convolutions stream by rows
@@ -91,28 +95,32 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
   {
     const uint2* g2 = reinterpret_cast<const uint2*>(wt + A.t_off[1]);  // 32 rows x 36 quads
     const uint2* g3 = reinterpret_cast<const uint2*>(wt + A.t_off[2]);  // 32 rows x 72 quads
-    uint2 v2[5], v3[9];
+    constexpr int Q2 = (32 * 36 + NTH - 1) / NTH, Q3 = (32 * 72 + NTH - 1) / NTH;
+    uint2 v2[Q2], v3[Q3];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const int i = tid + 256 * q;
+    for (int q = 0; q < Q2; ++q) {
+      const int i = tid + NTH * q;
       v2[q] = i < 32 * 36 ? g2[i] : make_uint2(0u, 0u);
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) v3[q] = g3[tid + 256 * q];
+    for (int q = 0; q < Q3; ++q) {
+      const int i = tid + NTH * q;
+      v3[q] = i < 32 * 72 ? g3[i] : make_uint2(0u, 0u);
+    }
     uint16_t w1v = 0;
     if (tid < 16 * W1K) {
       const int n = tid / W1K, k = tid % W1K;
       w1v = k < 9 ? wt[A.t_off[0] + n * 9 + k] : (uint16_t)0;
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const int i = tid + 256 * q;
+    for (int q = 0; q < Q2; ++q) {
+      const int i = tid + NTH * q;
       if (i < 32 * 36) *reinterpret_cast<uint2*>(&w2s[(i / 36) * W2K + 4 * (i % 36)]) = v2[q];
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const int i = tid + 256 * q;
-      *reinterpret_cast<uint2*>(&w3s[(i / 72) * W3K + 4 * (i % 72)]) = v3[q];
+    for (int q = 0; q < Q3; ++q) {
+      const int i = tid + NTH * q;
+      if (i < 32 * 72) *reinterpret_cast<uint2*>(&w3s[(i / 72) * W3K + 4 * (i % 72)]) = v3[q];
     }
     if (tid < 16 * W1K) w1s[tid] = w1v;
   }
@@ -120,6 +128,7 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
   const float* b2 = A.w + A.b_off[1];
   const float* b3 = A.w + A.b_off[2];
   const float bias1 = b1[r16], bias2a = b2[r16], bias2b = b2[16 + r16], bias3a = b3[r16], bias3b = b3[16 + r16];
+  float* red = reinterpret_cast<float*>(h1r);  // FC4 partial sums (h1r is free by then)
   // this lane's conv1 taps k = 4 kq + i as LDS offsets into the bordered
   // stamp (taps 9..15 are padding: zero)
   int toff[4];
@@ -131,29 +140,29 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
     toff[i] = (k < 9 ? ((k / 3) * 23 + k % 3) * G : 0) + r16;
   }
   // the zero border (never written below)
-  for (int i = tid; i < SPAD * G; i += 256) stg[i] = 0;
+  for (int i = tid; i < SPAD * G; i += NTH) stg[i] = 0;
   const int n_groups = (A.B + G - 1) / G;
   for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
     __syncthreads();  // the previous group's readers of stg / h3s / cat / h6 are done; weights loaded
     const int cell0 = grp * G;
     {
-      // the group's stamps: 28 loads per thread issued together, then stored [pixel][cell]
-      constexpr int NQ = (441 * G + 255) / 256;
+      // the group's stamps: all loads of a thread issued together, then stored [pixel][cell]
+      constexpr int NQ = (441 * G + NTH - 1) / NTH;
       uint16_t v[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int i = tid + 256 * q;
+        const int i = tid + NTH * q;
         const int c = i / 441;
         v[q] = (i < 441 * G && cell0 + c < A.B) ? A.stamps[(int64_t)cell0 * 441 + i] : (uint16_t)0;
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int i = tid + 256 * q;
+        const int i = tid + NTH * q;
         const int px = i % 441;
         if (i < 441 * G) stg[((px / 21 + 1) * 23 + px % 21 + 1) * G + i / 441] = v[q];
       }
     }
-    for (int i = tid; i < G * 16; i += 256) {
+    for (int i = tid; i < G * 16; i += NTH) {
       const int r = i / 16, c = i % 16;
       ftg[r * FTS + c] = cell0 + r < A.B ? A.feats[(int64_t)(cell0 + r) * 16 + c] : (uint16_t)0;
     }
@@ -161,10 +170,10 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
     const short4_t bw1 = ld4(&w1s[r16 * W1K + 4 * kq]);
     int h1_done = 0;  // conv1 rows computed so far
     for (int oy2 = 0; oy2 < 11; ++oy2) {
-      // conv1 rows up to 2 oy2 + 1: pixel (y, x) of the row is one 16 x 16 tile, wave w takes x = w, w + 4, ...
+      // conv1 rows up to 2 oy2 + 1: pixel (y, x) of the row is one 16 x 16 tile, wave w takes x = w, w + NW, ...
       const int need = min(21, 2 * oy2 + 2);
       for (int y = h1_done; y < need; ++y) {
-        for (int x = wave; x < 21; x += 4) {
+        for (int x = wave; x < 21; x += NW) {
           // output pixel (y, x) reads bordered pixels (y + dy, x + dx), dy, dx in 0..2
           const uint16_t* b = stg + (y * 23 + x) * G;
           short v[4];
@@ -178,26 +187,25 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
       }
       h1_done = need;
       __syncthreads();
-      // conv2 row oy2: 11 pixels, wave w takes ox = w, w + 4, w + 8; K step s = tap s
-      for (int ox = wave; ox < 11; ox += 4) {
-        float4_t acc0 = float4_t{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+      // conv2 row oy2: 11 pixels x 2 column tiles, wave w takes units w, w + NW, ...; K step s = tap s
+      for (int u = wave; u < 22; u += NW) {
+        const int ox = u >> 1, nt = u & 1;
+        float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 9; ++s) {
           const int iy = 2 * oy2 + s / 3 - 1, ix = 2 * ox + s % 3 - 1;
           short4_t a = short4_t{0, 0, 0, 0};
           if ((unsigned)iy < 21u && (unsigned)ix < 21u) a = ld4(&h1r[((iy % 3) * 21 + ix) * (G * 16) + r16 * 16 + 4 * kq]);
-          acc0 = mfma(a, ld4(&w2s[r16 * W2K + s * 16 + 4 * kq]), acc0);
-          acc1 = mfma(a, ld4(&w2s[(16 + r16) * W2K + s * 16 + 4 * kq]), acc1);
+          acc = mfma(a, ld4(&w2s[(16 * nt + r16) * W2K + s * 16 + 4 * kq]), acc);
         }
         uint16_t* o = h2r + ((oy2 % 3) * 11 + ox) * (G * 32);
-        store4(o, kq, r16, 32, acc0, bias2a);
-        store4(o + 16, kq, r16, 32, acc1, bias2b);
+        store4(o + 16 * nt, kq, r16, 32, acc, nt ? bias2b : bias2a);
       }
       __syncthreads();
-      // conv3 row oy3 once conv2 rows up to 2 oy3 + 1 exist: 6 pixels x 2 column tiles, 3 units per wave
+      // conv3 row oy3 once conv2 rows up to 2 oy3 + 1 exist: 6 pixels x 2 column tiles
       if ((oy2 & 1) || oy2 == 10) {
         const int oy3 = oy2 == 10 ? 5 : (oy2 - 1) / 2;
-        for (int u = wave; u < 12; u += 4) {
+        for (int u = wave; u < 12; u += NW) {
           const int ox = u >> 1, nt = u & 1;
           float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -217,33 +225,44 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
         __syncthreads();
       }
     }
-    // FC4 (1152 -> 64; K = pixel * 32 + channel) and FC5 (16 -> 64): wave w owns columns 16w .. 16w + 15
+    // FC4 (1152 -> 64; K = pixel * 32 + channel) and FC5 (16 -> 64): waves w and w + 4 own columns
+    // 16w .. 16w + 15 and K steps 0..35 and 36..71; the second half's partial sums go through LDS
     {
-      const int n = 16 * wave + r16;
+      const int ct = wave & 3, kh = wave >> 2;
+      const int n = 16 * ct + r16;
       const uint16_t* w4 = wt + A.t_off[3] + (int64_t)n * 1152;
       float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
-      for (int s0 = 0; s0 < 72; s0 += 24) {
-        short4_t b[24];
+      for (int s0 = 36 * kh; s0 < 36 * kh + 36; s0 += 18) {
+        short4_t b[18];
 #pragma unroll
-        for (int u = 0; u < 24; ++u) b[u] = ld4(&w4[(s0 + u) * 16 + 4 * kq]);
+        for (int u = 0; u < 18; ++u) b[u] = ld4(&w4[(s0 + u) * 16 + 4 * kq]);
 #pragma unroll
-        for (int u = 0; u < 24; ++u) {
+        for (int u = 0; u < 18; ++u) {
           const int s = s0 + u;
           acc = mfma(ld4(&h3s[((s >> 1) * G + r16) * 32 + (s & 1) * 16 + 4 * kq]), b[u], acc);
         }
       }
-      const float bias4 = A.w[A.b_off[3] + n];
+      if (kh) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) cat[(4 * kq + r) * CTS + n] = f2bf(fmaxf(acc[r] + bias4, 0.f));
-      const short4_t b5 = ld4(wt + A.t_off[4] + (int64_t)n * 16 + 4 * kq);
-      const float4_t d5 = mfma(ld4(&ftg[r16 * FTS + 4 * kq]), b5, float4_t{0.f, 0.f, 0.f, 0.f});
-      const float bias5 = A.w[A.b_off[4] + n];
+        for (int r = 0; r < 4; ++r) red[(ct * 4 + r) * 64 + lane] = acc[r];
+      }
+      __syncthreads();
+      if (kh == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) cat[(4 * kq + r) * CTS + 64 + n] = f2bf(fmaxf(d5[r] + bias5, 0.f));
+        for (int r = 0; r < 4; ++r) acc[r] += red[(ct * 4 + r) * 64 + lane];
+        const float bias4 = A.w[A.b_off[3] + n];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cat[(4 * kq + r) * CTS + n] = f2bf(fmaxf(acc[r] + bias4, 0.f));
+        const short4_t b5 = ld4(wt + A.t_off[4] + (int64_t)n * 16 + 4 * kq);
+        const float4_t d5 = mfma(ld4(&ftg[r16 * FTS + 4 * kq]), b5, float4_t{0.f, 0.f, 0.f, 0.f});
+        const float bias5 = A.w[A.b_off[4] + n];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cat[(4 * kq + r) * CTS + 64 + n] = f2bf(fmaxf(d5[r] + bias5, 0.f));
+      }
     }
     __syncthreads();
-    // FC6 (128 -> 64)
-    {
+    // FC6 (128 -> 64): waves 0..3
+    if (wave < 4) {
       const int n = 16 * wave + r16;
       const uint16_t* w6 = wt + A.t_off[5] + (int64_t)n * 128;
       short4_t b[8];
@@ -279,16 +298,17 @@ __global__ __launch_bounds__(256) void k_scorer_fused(ScorerFusedArgs A) {
   }
 }
 
-hipError_t launch_scorer_fused(const ScorerFusedArgs& a, hipStream_t s) {
+hipError_t launch_scorer_fused(const ScorerFusedArgs& a, bool transpose, hipStream_t s) {
   if (a.B <= 0) return hipSuccess;
   const int total = (int)a.t_off[7];
-  hipLaunchKernelGGL(k_scorer_transpose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.wb, a.wt, a,
-                     total);
+  if (transpose)
+    hipLaunchKernelGGL(k_scorer_transpose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a.wb, a.wt, a,
+                       total);
   int dev = 0, n_cu = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   const int groups = (a.B + G - 1) / G;
   const int grid = groups < n_cu ? groups : n_cu;
-  hipLaunchKernelGGL(k_scorer_fused, dim3((unsigned)grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scorer_fused, dim3((unsigned)grid), dim3(NTH), 0, s, a);
   return hipGetLastError();
 }
 

@@ -51,7 +51,6 @@ constexpr int STAMP_CHUNKS = 21;
 __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, double dm, uint16_t* __restrict__ st_bf,
                                                     float* __restrict__ st_f, uint16_t* __restrict__ ft_bf,
                                                     float* __restrict__ ft_f) {
-#pragma clang fp contract(off)
   extern __shared__ double2 trk[];  // [3][n_exp]
   const int64_t cell = blockIdx.x;
   if (cell >= R.n) return;
@@ -112,6 +111,26 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
     return __builtin_isfinite(pa.x) && __builtin_isfinite(pm.x) && p0.x + rx >= -0.5 && p0.x - rx < x.W - 0.5 &&
            p0.y + ry >= -0.5 && p0.y - ry < x.H - 0.5;
   };
+  // The gathers of one usable exposure are accumulated while the next
+  // exposure's are in flight.  Every lane issues all its loads (a node off
+  // the image reads the plane's first pixel and is dropped), so the wait
+  // before an accumulation covers only the older loads.
+  float2 pend[PER];
+  bool pend_ok[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    pend[q] = make_float2(0.f, 0.f);
+    pend_ok[q] = false;
+  }
+  auto accumulate = [&]() {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      if (pend_ok[q] && pend[q].y > 0.f) {
+        ps[q] += pend[q].x;
+        ph[q] += pend[q].y;
+      }
+    }
+  };
   for (int c0 = 0; c0 < n_exp; c0 += 64) {
     bool use = false;
     if (c0 + lane < n_exp) {
@@ -128,22 +147,28 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
       (void)usable(ex, p0, Ax, Ay, Bx, By);
       const ExpMeta& x = meta[ex];
       near += (p0.x >= -0.5 && p0.x < x.W - 0.5 && p0.y >= -0.5 && p0.y < x.H - 0.5) ? 1 : 0;
+      float2 cur[PER];
+      bool cur_ok[PER];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int j = lane + 64 * q;
-        if (j >= SP) continue;
-        const double px = (p0.x + u[q] * Ax) + v[q] * Bx;
-        const double py = (p0.y + u[q] * Ay) + v[q] * By;
+        // the node's track point p0 + u A + v B (two fused multiply-adds)
+        const double px = fma(v[q], Bx, fma(u[q], Ax, p0.x));
+        const double py = fma(v[q], By, fma(u[q], Ay, p0.y));
         const double fx = floor(px + 0.5), fy = floor(py + 0.5);
-        if (!(fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H)) continue;
-        const float2 w = planes[x.plane_off + (int64_t)fy * x.W + (int64_t)fx];
-        if (w.y > 0.f) {
-          ps[q] += w.x;
-          ph[q] += w.y;
-        }
+        cur_ok[q] = j < SP && fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H;
+        const int64_t off = cur_ok[q] ? (int64_t)fy * x.W + (int64_t)fx : 0;
+        cur[q] = planes[x.plane_off + off];
+      }
+      accumulate();
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        pend[q] = cur[q];
+        pend_ok[q] = cur_ok[q];
       }
     }
   }
+  accumulate();
   float smax = -1e30f, ssum = 0.f, ssq = 0.f, cov = 0.f, smax_c = -1e30f, center = 0.f;
   int amax = 0;
   for (int q = 0; q < PER; ++q) {
@@ -199,17 +224,68 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
 
 // The plain stack restricted to the orbits of selected cells: orbit
 // cells[c] * cell_size + m for m < cell_size; outputs at the orbit's index.
+// A few hundred thousand orbits give a few wavefronts per SIMD, whose
+// 200-exposure walks are latency-bound, so `split` wavefronts of a workgroup
+// share 64 orbits: wavefront j walks the j-th contiguous range of exposures
+// (starting cold; the range is uniform over the wavefront, so exposure
+// records stay scalar loads) and the first merges the ranges' compensated
+// sums in range order through LDS.
 __global__ __launch_bounds__(256) void k_stack_cells(StackArgs A, const int64_t* __restrict__ cells, int64_t n_sel,
-                                                     int cell_size) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_sel * cell_size) return;
-  const int64_t c = cells[t / cell_size];
-  if (c < 0) return;
-  const int64_t o = c * cell_size + t % cell_size;
-  if (o >= A.n) return;
+                                                     int cell_size, int split) {
+  __shared__ float part[4][4][64];  // [wavefront][ps.s, ps.c, ph.s, ph.c][lane]
+  __shared__ int part_nv[4][64];
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int j = w % split;
+  const int64_t r = (int64_t)blockIdx.x * (256 / split) + (w / split) * 64 + lane;
+  int64_t o = -1;
+  if (r < n_sel * cell_size) {
+    const int64_t c = cells[r / cell_size];
+    if (c >= 0) o = c * cell_size + r % cell_size;
+  }
+  const bool ok = o >= 0 && o < A.n;
+  double a = 0, e = 0, inc = 0, node = 0, peri = 0, m0 = 0;
+  if (ok) {
+    a = A.a[o]; e = A.e[o]; inc = A.inc[o]; node = A.node[o]; peri = A.peri[o]; m0 = A.m0[o];
+  }
+  const bool good = ok && orbit_ok(a, e, inc, node, peri, m0);
+  StackPart P;
+  P.ps.init();
+  P.ph.init();
+  P.nv = 0;
+  if (good) {
+    const int ch = (A.n_exp + split - 1) / split;
+    const int ex0 = j * ch;
+    const int cnt = min(ch, A.n_exp - ex0);
+    if (cnt > 0) {
+      Orbit ob;
+      orbit_prep(a, e, inc, node, peri, m0, ob);
+      stack_range(A, ob, ex0, cnt, P);
+    }
+  }
+  if (split > 1) {
+    part[w][0][lane] = P.ps.s;
+    part[w][1][lane] = P.ps.c;
+    part[w][2][lane] = P.ph.s;
+    part[w][3][lane] = P.ph.c;
+    part_nv[w][lane] = P.nv;
+    __syncthreads();
+    if (j == 0) {
+      for (int q = 1; q < split; ++q) {
+        P.ps.merge(part[w + q][0][lane], part[w + q][1][lane]);
+        P.ph.merge(part[w + q][2][lane], part[w + q][3][lane]);
+        P.nv += part_nv[w + q][lane];
+      }
+    }
+  }
+  if (!ok || j != 0) return;
   float snr, flux;
   int nv;
-  stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);
+  if (good) {
+    stack_finish(P, snr, flux, nv);
+  } else {
+    snr = flux = __builtin_nanf("");
+    nv = -1;
+  }
   if (A.snr) A.snr[o] = snr;
   if (A.flux) A.flux[o] = flux;
   if (A.nvalid) A.nvalid[o] = nv;
@@ -228,8 +304,13 @@ hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_
                               hipStream_t s) {
   const int64_t n = n_sel * cell_size;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stack_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d_cells, n_sel,
-                     cell_size);
+  // lanes per orbit: up to four, while that keeps the launch near a million
+  // lanes and the ranges at six exposures or more
+  int split = 1;
+  while (split < 4 && n * split * 2 <= (int64_t)1 << 20 && a.n_exp >= 12 * split) split *= 2;
+  const int64_t per_block = 256 / split;  // orbits per workgroup
+  hipLaunchKernelGGL(k_stack_cells, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256), 0, s, a, d_cells,
+                     n_sel, cell_size, split);
   return hipGetLastError();
 }
 

@@ -206,6 +206,147 @@ __global__ void k_topk_emit(const uint64_t* __restrict__ keys, int k, int64_t* _
   if (threadIdx.x == 0) *count = cnt;
 }
 
+// Inputs of at most TOPK_SMALL_MAX keys in one workgroup and one launch: the
+// keys stay in registers, an exact radix select (eight 8-bit digits from the
+// top) finds the k-th largest key K*, the keys >= K* (exactly
+// min(k, non-empty) of them, keys being distinct) are compacted into LDS,
+// sorted, and emitted.  The leading digits of nearby S/N values coincide, so
+// a thread counts runs of equal digits in registers and each wavefront adds
+// them into its own LDS histogram.
+constexpr int TOPK_SMALL_MAX = 16384;
+constexpr int SMALL_THREADS = 1024;
+constexpr int SMALL_PER = TOPK_SMALL_MAX / SMALL_THREADS;
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_topk_small(const float* __restrict__ snr, int n, float thr, int k,
+                                                              int64_t* __restrict__ idx, float* __restrict__ val,
+                                                              int32_t* __restrict__ count) {
+  __shared__ uint64_t s[TOPK_T / 2];
+  __shared__ int hist[SMALL_THREADS / 64][256];
+  __shared__ int sh_total, sh_sel, sh_want, sh_done;
+  __shared__ uint64_t sh_prefix;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  uint64_t key[SMALL_PER];
+  int cnt = 0;
+#pragma unroll
+  for (int q = 0; q < SMALL_PER; ++q) {
+    const int i = q * SMALL_THREADS + t;
+    uint64_t kq = 0;
+    if (i < n) {
+      const float f = snr[i];
+      if (f >= thr) kq = make_key(f, (uint64_t)i);  // false for NaN
+    }
+    key[q] = kq;
+    cnt += kq != 0;
+  }
+  if (t == 0) {
+    sh_total = 0;
+    sh_sel = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if (lane == 0) atomicAdd(&sh_total, cnt);
+  __syncthreads();
+  const int total = sh_total;
+  const int m = total < k ? total : k;
+  uint64_t kth = 1;  // every non-empty key is >= 2^32
+  if (total > k) {
+    uint64_t prefix = 0;
+    int want = k;  // rank from the top still to find below `prefix`
+    // a pass whose chosen digit holds exactly `want` keys ends the search:
+    // all keys >= prefix (lower digits zero) are then the k largest
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int i = t; i < (SMALL_THREADS / 64) * 256; i += SMALL_THREADS) (&hist[0][0])[i] = 0;
+      __syncthreads();
+      const uint64_t hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+      // runs of equal digits among a thread's keys are counted in registers
+      // first (in the leading passes nearly all keys share one digit)
+      int run_d = -1, run_c = 0;
+#pragma unroll
+      for (int q = 0; q < SMALL_PER; ++q) {
+        if (key[q] != 0 && (key[q] & hmask) == prefix) {
+          const int d = (int)((key[q] >> shift) & 255u);
+          if (d != run_d) {
+            if (run_c) atomicAdd(&hist[wv][run_d], run_c);
+            run_d = d;
+            run_c = 0;
+          }
+          run_c++;
+        }
+      }
+      if (run_c) atomicAdd(&hist[wv][run_d], run_c);
+      __syncthreads();
+      if (t < 256) {
+        int sum = 0;
+#pragma unroll
+        for (int w = 1; w < SMALL_THREADS / 64; ++w) sum += hist[w][t];
+        hist[0][t] += sum;
+      }
+      __syncthreads();
+      if (t < 64) {
+        // lane l holds digits 255 - 4 l - r, r = 0..3 (descending)
+        int c[4], sum = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          c[r] = hist[0][255 - 4 * t - r];
+          sum += c[r];
+        }
+        int inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int v = __shfl_up(inc, o, 64);
+          if (t >= o) inc += v;
+        }
+        const int exc = inc - sum;
+        if (exc < want && want <= inc) {
+          int acc = exc;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (acc + c[r] >= want) {
+              sh_prefix = prefix | ((uint64_t)(255 - 4 * t - r) << shift);
+              sh_want = want - acc;
+              sh_done = acc + c[r] == want;
+              break;
+            }
+            acc += c[r];
+          }
+        }
+      }
+      __syncthreads();
+      prefix = sh_prefix;
+      want = sh_want;
+      // uniform: every thread read the same flag; the next pass rewrites
+      // sh_* only after two more barriers
+      if (sh_done) break;
+    }
+    kth = prefix;
+  }
+#pragma unroll
+  for (int q = 0; q < SMALL_PER; ++q)
+    if (key[q] != 0 && key[q] >= kth) s[atomicAdd(&sh_sel, 1)] = key[q];
+  __syncthreads();
+  int S = 64;
+  while (S < m) S <<= 1;
+  for (int j = m + t; j < S; j += SMALL_THREADS) s[j] = 0;
+  __syncthreads();
+  switch (S / TOPK_THREADS) {
+    case 8: bitonic_desc<8>(s, S); break;
+    case 4: bitonic_desc<4>(s, S); break;
+    case 2: bitonic_desc<2>(s, S); break;
+    default: bitonic_desc<1>(s, S); break;
+  }
+  for (int j = t; j < k; j += SMALL_THREADS) {
+    if (j < m) {
+      idx[j] = key_idx(s[j]);
+      val[j] = key_val(s[j]);
+    } else {
+      idx[j] = -1;
+      val[j] = __builtin_nanf("");
+    }
+  }
+  if (t == 0) *count = m;
+}
+
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Tile of the first round: small inputs use tiles just large enough to cut
@@ -254,6 +395,11 @@ static void launch_round(int T, unsigned tiles, const float* snr, const uint64_t
 hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,
                        int32_t* d_count, void* d_scratch, hipStream_t s) {
   if (k < 1 || k > TOPK_T / 2) return hipErrorInvalidValue;
+  if (n <= TOPK_SMALL_MAX) {
+    hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(SMALL_THREADS), 0, s, d_snr, (int)(n > 0 ? n : 0), thr, k, d_idx,
+                       d_val, d_count);
+    return hipGetLastError();
+  }
   const int T1 = first_tile(n, k);
   int64_t tiles = ceil_div(n > 0 ? n : 1, T1);
   uint64_t* buf[2] = {static_cast<uint64_t*>(d_scratch), static_cast<uint64_t*>(d_scratch) + tiles * k};

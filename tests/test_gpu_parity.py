@@ -181,10 +181,18 @@ def test_topk_edge_cases():
     import paper_2503_08854_amd as dt
     ctx = dt.Context(0)
     rng = np.random.default_rng(1)
+    # inputs of at most 16384 keys take the one-workgroup radix-select path,
+    # larger ones the tournament; the last two cases are all ties
     for n, k, thr in [(1, 1, -np.inf), (10, 50, -np.inf), (100000, 4096, -np.inf), (100000, 100, 2.5),
-                      (8192 * 3 + 17, 1000, 0.0), (5000, 10, 100.0)]:
-        v = np.round(rng.standard_normal(n), 2).astype(np.float32)
-        v[rng.integers(0, n, max(1, n // 100))] = np.nan
+                      (8192 * 3 + 17, 1000, 0.0), (5000, 10, 100.0), (10000, 200, -np.inf),
+                      (16384, 4096, -np.inf), (16384, 3000, 0.5), (16385, 200, -np.inf), (12000, 777, None),
+                      (7, 3, None)]:
+        if thr is None:
+            v = np.zeros(n, np.float32)
+            thr = -np.inf
+        else:
+            v = np.round(rng.standard_normal(n), 2).astype(np.float32)
+            v[rng.integers(0, n, max(1, n // 100))] = np.nan
         t = torch.from_numpy(v).cuda()
         idx, val, cnt = dt.topk(ctx, t, k, thr)
         torch.cuda.synchronize()
