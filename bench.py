@@ -21,14 +21,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 operations per dense sample on the stack kernel's common path as
-# written (warm Kepler step: 2nd-order start 7, short rotation 20, one Newton
-# step with a tiny rotation 16; mean anomaly and predicted light time 6;
-# observer offset 3; position, velocity, distance and the light-time
-# correction 47; corrected position, projection with one-refinement
-# reciprocal and rounding 37): an FMA counts 2, add / mul / floor / hardware
-# reciprocal or rsqrt estimate 1.
-FLOPS_PER_SAMPLE = 136
+# FP64 operations of the stack kernel's path as written (an FMA counts 2;
+# add / mul / hardware reciprocal or rsqrt estimate 1).  Every dense sample:
+# mean anomaly with the predicted light time 5, warm Kepler step 39
+# (2nd-order start 7, short rotation 20, one Newton step with a tiny rotation
+# 12), position and raw distance 20, light-time estimate 2, sky-cone test 13,
+# light-time history 3.  A sample that lands in an image also takes the full
+# path: distance refinement 5, velocity and light-time correction 23,
+# corrected position 6, light time 1, projection with one-refinement
+# reciprocal 24, rounding 2, less the estimate's 1.
+FLOPS_PER_SAMPLE = 82
+FLOPS_PER_VALID = 60
 # HBM bytes of one full-size k_stack launch on the survey workload from the
 # committed FETCH_SIZE / WRITE_SIZE passes; reported only while the kernel's
 # sources are the ones those counters were taken on.
@@ -329,7 +332,8 @@ def main():
     snr = out[0].cpu().numpy()
     nv = out[2].cpu().numpy()
     idx, val, cnt = (x.cpu().numpy() for x in res)
-    achieved = FLOPS_PER_SAMPLE * samples / (stk * 1e-3) / 1e12
+    valid = int(nv[nv > 0].sum())
+    achieved = (FLOPS_PER_SAMPLE * samples + FLOPS_PER_VALID * valid) / (stk * 1e-3) / 1e12
     rec = {
         "metric": "orbit x exposure samples/s",
         "value": value,
@@ -346,11 +350,11 @@ def main():
         "config": {"workload": f"{args.workload}: {ne} exposures "
                                f"{w.exps[0]['width']}x{w.exps[0]['height']} {w.dtype} + variance, "
                                f"{n} orbits, top-{args.k} at S/N>=5",
-                   "orbits": n, "exposures": ne, "valid_samples": int(nv[nv > 0].sum()),
+                   "orbits": n, "exposures": ne, "valid_samples": valid,
                    "phase_ms": {"prepass": pre, "stack": stk, "topk": tk}},
         "roofline": {"bound": "alu", "kernel": "k_stack", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": stack_traffic(args.workload),
-                     "flops_per_sample": FLOPS_PER_SAMPLE},
+                     "flops_per_sample": FLOPS_PER_SAMPLE, "flops_per_valid_sample": FLOPS_PER_VALID},
         "detections": int(cnt[0]),
     }
     inj = w.inj_index
