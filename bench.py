@@ -90,12 +90,13 @@ def cpu_baseline(w, gpu_snr, seconds=12.0):
                 snr_max_err=float(err.max()))
 
 
-def gather_yardstick(patch, w, dev, m=1_000_000, reps=3):
+def gather_yardstick(patch, w, dev, m=None, reps=3):
     """The stack's own gather stream replayed without the orbit arithmetic, on
-    the first m orbits: the achievable gather rate of that access pattern."""
+    the first m orbits (default: all of them, the launch the benchmark times):
+    the achievable gather rate of that access pattern."""
     import torch
     import paper_2503_08854_amd as dt
-    m = min(m, w.elements.shape[0])
+    m = w.elements.shape[0] if m is None else min(m, w.elements.shape[0])
     sub = dt.OrbitSet(w.elements[:m], w.t0, dev)
     off = dt.record_gathers(patch, sub, torch.arange(m, device=dev))
     out = dt.batch_outputs([sub])[0]
@@ -231,7 +232,7 @@ def bench_batched(dev, steps=5):
     return res
 
 
-def bench_learned(dev, n_train=100, n_eval=50, budget=0.02, budget_wide=0.05, n_eval_wide=20):
+def bench_learned(dev, n_train=100, n_eval=50, budget=0.02, budget_wide=0.05, n_eval_wide=20, budget_tight=0.01):
     """Learned vs plain recall at S/N >= 5 and speedup on the cell-structured survey grid."""
     import torch
     import learned_eval as le
@@ -252,8 +253,11 @@ def bench_learned(dev, n_train=100, n_eval=50, budget=0.02, budget_wide=0.05, n_
     res = le.evaluate(b, sc, budget_frac=budget, n_real=n_eval)
     res.update(train_stacks=n_train * s.n_cells, train_s=t_train, loss_first=hist[0][1], loss_last=hist[-1][1])
     wide = le.evaluate(b, sc, budget_frac=budget_wide, n_real=n_eval_wide)
-    res["wider_budget"] = {k: wide[k] for k in ("budget_frac", "injections", "recall_ratio_learned",
-                                                 "recall_ratio_coarse", "recall_ratio_coarse_to_fine", "speedup")}
+    keys = ("budget_frac", "injections", "recall_ratio_learned", "recall_ratio_coarse",
+            "recall_ratio_coarse_to_fine", "speedup")
+    res["wider_budget"] = {k: wide[k] for k in keys}
+    tight = le.evaluate(b, sc, budget_frac=budget_tight, n_real=n_eval_wide)
+    res["tighter_budget"] = {k: tight[k] for k in keys}
     sc.close()
     b.patch.close()
     b.coarse.close()
@@ -387,7 +391,11 @@ def main():
         rec["learned"] = bench_learned(dev)
         L = rec["learned"]
         log(f"learned: recall ratio {L['recall_ratio_learned']:.3f} (coarse {L['recall_ratio_coarse']:.3f}), "
-            f"speedup {L['speedup']:.1f}x")
+            f"speedup {L['speedup']:.1f}x at a {L['budget_frac']:.0%} budget")
+        for key in ("tighter_budget", "wider_budget"):
+            T = L[key]
+            log(f"learned: recall ratio {T['recall_ratio_learned']:.3f}, speedup {T['speedup']:.1f}x "
+                f"at a {T['budget_frac']:.0%} budget")
         torch.cuda.empty_cache()
     print(json.dumps(rec), flush=True)
 
