@@ -17,6 +17,12 @@ struct BatchGraph {
   unsigned int* d_counter = nullptr;
   void* d_topk = nullptr;
   size_t n_descs = 0, n_items = 0, topk_bytes = 0;
+  // all patches' top-k in two launches (when every patch's tiles fit)
+  bool seg = false;
+  void* d_seg = nullptr;
+  size_t seg_bytes = 0;
+  SegTopkArgs seg_args{};
+  int seg_tiles = 0;
 };
 
 namespace {
@@ -87,6 +93,7 @@ void graph_free(dt_ctx* c, BatchGraph* g) {
   ctx_free(c, g->d_items, sizeof(WorkItem) * g->n_items);
   ctx_free(c, g->d_counter, sizeof(unsigned int));
   ctx_free(c, g->d_topk, g->topk_bytes);
+  ctx_free(c, g->d_seg, g->seg_bytes);
   delete g;
 }
 
@@ -102,7 +109,10 @@ dt_status enqueue(dt_ctx* c, BatchGraph* g, dt_patch* const* patches, const dt_o
   }
   hipError_t e = launch_batched(g->d_descs, g->d_items, (int)g->n_items, g->d_counter, cfg.wg_per_cu * cu_count(c->device), s);
   if (e != hipSuccess) return hip_fail(e, "batched stack launch");
-  if (k > 0) {
+  if (k > 0 && g->seg) {
+    e = launch_topk_segmented(g->seg_args, g->seg_tiles, n_patches, s);
+    if (e != hipSuccess) return hip_fail(e, "batched top-k launch");
+  } else if (k > 0) {
     for (int p = 0; p < n_patches; ++p) {
       e = launch_topk(d_snr[p], sets[p].n, k, thr, d_topk_idx + (int64_t)p * k, d_topk_val + (int64_t)p * k,
                       d_topk_count + p, g->d_topk, s);
@@ -112,8 +122,42 @@ dt_status enqueue(dt_ctx* c, BatchGraph* g, dt_patch* const* patches, const dt_o
   return DT_OK;
 }
 
+// The tables of the two-launch top-k over all patches, in one device buffer:
+// S/N pointers, orbit counts, first tile per patch, patch per tile, and the
+// tiles' surviving keys.  Returns false (per-patch top-k) when a patch has
+// more survivors than one workgroup selects from.
+bool seg_tables(const dt_orbits* sets, int32_t n_patches, int32_t k, float* const* d_snr,
+                std::vector<unsigned char>& host, size_t& key_off, int& n_tiles) {
+  const int64_t T = topk_seg_tile();
+  std::vector<int64_t> first(n_patches + 1, 0);
+  for (int p = 0; p < n_patches; ++p) {
+    const int64_t t = (sets[p].n + T - 1) / T;
+    if (t * k > topk_seg_max_keys()) return false;
+    first[p + 1] = first[p] + t;
+  }
+  if (first[n_patches] > (int64_t)1 << 30) return false;
+  n_tiles = (int)first[n_patches];
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t o_snr = 0, o_n = align(o_snr + 8 * (size_t)n_patches), o_first = align(o_n + 8 * (size_t)n_patches);
+  const size_t o_tp = align(o_first + 8 * (size_t)(n_patches + 1));
+  key_off = align(o_tp + 4 * (size_t)n_tiles);
+  host.assign(key_off, 0);
+  for (int p = 0; p < n_patches; ++p) {
+    const float* sp = d_snr[p];
+    std::memcpy(&host[o_snr + 8 * p], &sp, 8);
+    std::memcpy(&host[o_n + 8 * p], &sets[p].n, 8);
+    for (int64_t t = first[p]; t < first[p + 1]; ++t) {
+      const int32_t pp = p;
+      std::memcpy(&host[o_tp + 4 * t], &pp, 4);
+    }
+  }
+  std::memcpy(&host[o_first], first.data(), 8 * (size_t)(n_patches + 1));
+  return true;
+}
+
 // Build (allocate + upload) a BatchGraph's buffers for a plan.
 dt_status prepare(dt_ctx* c, const BatchPlan& pl, const dt_orbits* sets, int32_t n_patches, int32_t k,
+                  float* const* d_snr, float thr, int64_t* d_topk_idx, float* d_topk_val, int32_t* d_topk_count,
                   BatchGraph** out) {
   BatchGraph* g = new BatchGraph();
   dt_status st = ctx_alloc(c, (void**)&g->d_descs, sizeof(StackArgs) * pl.descs.size(), "batch descriptors");
@@ -121,7 +165,29 @@ dt_status prepare(dt_ctx* c, const BatchPlan& pl, const dt_orbits* sets, int32_t
   if (st == DT_OK) st = ctx_alloc(c, (void**)&g->d_items, sizeof(WorkItem) * pl.items.size(), "batch work items");
   g->n_items = pl.items.size();
   if (st == DT_OK) st = ctx_alloc(c, (void**)&g->d_counter, sizeof(unsigned int), "batch counter");
-  if (st == DT_OK && k > 0) {
+  std::vector<unsigned char> seg_host;
+  size_t key_off = 0;
+  if (st == DT_OK && k > 0 && seg_tables(sets, n_patches, k, d_snr, seg_host, key_off, g->seg_tiles)) {
+    g->seg_bytes = key_off + 8 * (size_t)g->seg_tiles * (size_t)k;
+    st = ctx_alloc(c, &g->d_seg, g->seg_bytes, "batch top-k tables");
+    if (st == DT_OK) {
+      unsigned char* b = static_cast<unsigned char*>(g->d_seg);
+      const size_t o_n = ((8 * (size_t)n_patches) + 255) & ~(size_t)255;
+      const size_t o_first = (o_n + 8 * (size_t)n_patches + 255) & ~(size_t)255;
+      const size_t o_tp = (o_first + 8 * (size_t)(n_patches + 1) + 255) & ~(size_t)255;
+      g->seg = true;
+      g->seg_args.snr = reinterpret_cast<const float* const*>(b);
+      g->seg_args.n = reinterpret_cast<const int64_t*>(b + o_n);
+      g->seg_args.tile_first = reinterpret_cast<const int64_t*>(b + o_first);
+      g->seg_args.tile_patch = reinterpret_cast<const int32_t*>(b + o_tp);
+      g->seg_args.keys = reinterpret_cast<uint64_t*>(b + key_off);
+      g->seg_args.thr = thr;
+      g->seg_args.k = k;
+      g->seg_args.idx = d_topk_idx;
+      g->seg_args.val = d_topk_val;
+      g->seg_args.cnt = d_topk_count;
+    }
+  } else if (st == DT_OK && k > 0) {
     g->topk_bytes = topk_scratch_bytes(pl.max_n, k);
     st = ctx_alloc(c, &g->d_topk, g->topk_bytes, "batch top-k scratch");
   }
@@ -134,6 +200,8 @@ dt_status prepare(dt_ctx* c, const BatchPlan& pl, const dt_orbits* sets, int32_t
   if (e == hipSuccess && !pl.items.empty())
     e = hipMemcpyAsync(g->d_items, pl.items.data(), sizeof(WorkItem) * pl.items.size(), hipMemcpyHostToDevice,
                        c->stream);
+  if (e == hipSuccess && g->seg)
+    e = hipMemcpyAsync(g->d_seg, seg_host.data(), seg_host.size(), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // host vectors are about to go away
   if (e != hipSuccess) {
     graph_free(c, g);
@@ -254,7 +322,7 @@ dt_status dt_stack_batched(dt_ctx* c, dt_patch* const* patches, const dt_orbits*
   if (flags & DT_BATCH_EAGER) {
     BatchPlan pl = make_plan(patches, sets, n_patches, d_snr, d_flux, d_nvalid, cfg.chunk);
     BatchGraph* g = nullptr;
-    st = prepare(c, pl, sets, n_patches, k, &g);
+    st = prepare(c, pl, sets, n_patches, k, d_snr, threshold, d_topk_idx, d_topk_val, d_topk_count, &g);
     if (st != DT_OK) return st;
     st = enqueue(c, g, patches, sets, n_patches, d_snr, k, threshold, d_topk_idx, d_topk_val, d_topk_count, cfg,
                  flags, c->stream);
@@ -266,7 +334,7 @@ dt_status dt_stack_batched(dt_ctx* c, dt_patch* const* patches, const dt_orbits*
     batch_graph_drop(c);
     BatchPlan pl = make_plan(patches, sets, n_patches, d_snr, d_flux, d_nvalid, cfg.chunk);
     BatchGraph* g = nullptr;
-    st = prepare(c, pl, sets, n_patches, k, &g);
+    st = prepare(c, pl, sets, n_patches, k, d_snr, threshold, d_topk_idx, d_topk_val, d_topk_count, &g);
     if (st != DT_OK) return st;
     g->key = key;
     g->patches.assign(patches, patches + n_patches);
@@ -318,7 +386,7 @@ dt_status dt_autotune_batched(dt_ctx* c, dt_patch* const* patches, const dt_orbi
   for (int ch : chunks) {
     BatchPlan pl = make_plan(patches, sets, n_patches, d_snr, d_flux, d_nvalid, ch);
     BatchGraph* g = nullptr;
-    st = prepare(c, pl, sets, n_patches, 0, &g);
+    st = prepare(c, pl, sets, n_patches, 0, nullptr, 0.f, nullptr, nullptr, nullptr, &g);
     if (st != DT_OK) break;
     for (int wg : wgs) {
       dt_batch_config cfg{ch, wg};

@@ -160,6 +160,24 @@ struct ScorerFusedArgs {
   int K[7], N[7];
   float* z;                // B logits
 };
+// Top-k of many S/N arrays at once (device tables, one entry per array or
+// per TOPK tile; see launch_topk_segmented).
+struct SegTopkArgs {
+  const float* const* snr;    // [arrays]
+  const int64_t* n;           // [arrays]
+  const int64_t* tile_first;  // [arrays + 1] first tile of each array
+  const int32_t* tile_patch;  // [tiles] array of each tile
+  uint64_t* keys;             // [tiles * k] scratch
+  float thr;
+  int32_t k;
+  int64_t* idx;               // [arrays * k]
+  float* val;                 // [arrays * k]
+  int32_t* cnt;               // [arrays]
+};
+int64_t topk_seg_tile();      // keys per tile
+int64_t topk_seg_max_keys();  // largest k * tiles of one array
+hipError_t launch_topk_segmented(const SegTopkArgs& a, int n_tiles, int n_arrays, hipStream_t s);
+
 // transpose: rebuild A.wt from A.wb first (needed after the weights changed).
 hipError_t launch_scorer_fused(const ScorerFusedArgs& a, bool transpose, hipStream_t s);
 

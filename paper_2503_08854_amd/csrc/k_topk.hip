@@ -113,15 +113,14 @@ __device__ __forceinline__ void bitonic_desc(uint64_t* s, int S) {
 // value and index) or keys from the previous round.  A tile with at most kk
 // non-empty keys is not sorted unless it is the last round: its keys are
 // only compacted (in index order) since a later round sorts them.
+// The tile of keys base .. base + T - 1 (of n_in) keeps its best kk in out.
 template <int T>
-__global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __restrict__ snr,
-                                                             const uint64_t* __restrict__ keys_in, int64_t n_in,
-                                                             float thr, int kk, int final_round,
-                                                             uint64_t* __restrict__ keys_out) {
+__device__ __forceinline__ void topk_tile(const float* __restrict__ snr, const uint64_t* __restrict__ keys_in,
+                                          int64_t base, int64_t n_in, float thr, int kk, int final_round,
+                                          uint64_t* __restrict__ out) {
   constexpr int PER = T / TOPK_THREADS;  // keys owned by a thread
   __shared__ uint64_t s[T];
   __shared__ int scan[TOPK_THREADS];
-  const int64_t base = (int64_t)blockIdx.x * T;
   for (int j = threadIdx.x; j < T; j += TOPK_THREADS) {
     int64_t i = base + j;
     uint64_t key = 0;
@@ -153,7 +152,6 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __rest
     __syncthreads();
   }
   const int total = scan[TOPK_THREADS - 1];
-  uint64_t* out = keys_out + (int64_t)blockIdx.x * kk;
   if (!final_round && total <= kk) {
     int pos = scan[threadIdx.x] - cnt;
 #pragma unroll
@@ -182,6 +180,15 @@ __global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __rest
     default: bitonic_desc<1>(s, S); break;
   }
   for (int j = threadIdx.x; j < kk; j += TOPK_THREADS) out[j] = j < total ? s[j] : 0;
+}
+
+template <int T>
+__global__ __launch_bounds__(TOPK_THREADS) void k_topk_round(const float* __restrict__ snr,
+                                                             const uint64_t* __restrict__ keys_in, int64_t n_in,
+                                                             float thr, int kk, int final_round,
+                                                             uint64_t* __restrict__ keys_out) {
+  topk_tile<T>(snr, keys_in, (int64_t)blockIdx.x * T, n_in, thr, kk, final_round,
+               keys_out + (int64_t)blockIdx.x * kk);
 }
 
 __global__ void k_topk_emit(const uint64_t* __restrict__ keys, int k, int64_t* __restrict__ idx,
@@ -217,9 +224,12 @@ constexpr int TOPK_SMALL_MAX = 16384;
 constexpr int SMALL_THREADS = 1024;
 constexpr int SMALL_PER = TOPK_SMALL_MAX / SMALL_THREADS;
 
-__global__ __launch_bounds__(SMALL_THREADS) void k_topk_small(const float* __restrict__ snr, int n, float thr, int k,
-                                                              int64_t* __restrict__ idx, float* __restrict__ val,
-                                                              int32_t* __restrict__ count) {
+// The best k (<= TOPK_T / 2) of the n <= TOPK_SMALL_MAX keys load(i) (0 =
+// empty), emitted as indices, values and their count; one workgroup of
+// SMALL_THREADS threads.
+template <typename Load>
+__device__ __forceinline__ void select_small(int n, int k, Load load, int64_t* __restrict__ idx,
+                                             float* __restrict__ val, int32_t* __restrict__ count) {
   __shared__ uint64_t s[TOPK_T / 2];
   __shared__ int hist[SMALL_THREADS / 64][256];
   __shared__ int sh_total, sh_sel, sh_want, sh_done;
@@ -230,11 +240,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_topk_small(const float* __res
 #pragma unroll
   for (int q = 0; q < SMALL_PER; ++q) {
     const int i = q * SMALL_THREADS + t;
-    uint64_t kq = 0;
-    if (i < n) {
-      const float f = snr[i];
-      if (f >= thr) kq = make_key(f, (uint64_t)i);  // false for NaN
-    }
+    const uint64_t kq = i < n ? load(i) : 0ull;
     key[q] = kq;
     cnt += kq != 0;
   }
@@ -347,6 +353,35 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_topk_small(const float* __res
   if (t == 0) *count = m;
 }
 
+__global__ __launch_bounds__(SMALL_THREADS) void k_topk_small(const float* __restrict__ snr, int n, float thr, int k,
+                                                              int64_t* __restrict__ idx, float* __restrict__ val,
+                                                              int32_t* __restrict__ count) {
+  select_small(n, k, [&](int i) -> uint64_t {
+    const float f = snr[i];
+    return f >= thr ? make_key(f, (uint64_t)i) : 0ull;  // false for NaN
+  }, idx, val, count);
+}
+
+// Top-k of many S/N arrays (the patches of a batch) in two launches: every
+// TOPK_T tile of every array keeps its best k (one workgroup per tile), then
+// one workgroup per array selects from its tiles' survivors.  Needs
+// k * tiles <= TOPK_SMALL_MAX for every array (checked by the host).
+__global__ __launch_bounds__(TOPK_THREADS) void k_topk_seg_tiles(SegTopkArgs a) {
+  const int t = blockIdx.x;
+  const int p = a.tile_patch[t];
+  const int64_t lt = t - a.tile_first[p];
+  topk_tile<TOPK_T>(a.snr[p], nullptr, lt * TOPK_T, a.n[p], a.thr, a.k, 0, a.keys + (int64_t)t * a.k);
+}
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_topk_seg_final(SegTopkArgs a) {
+  const int p = blockIdx.x;
+  const int64_t t0 = a.tile_first[p];
+  const int n = (int)((a.tile_first[p + 1] - t0) * a.k);
+  const uint64_t* keys = a.keys + t0 * a.k;
+  select_small(n, a.k, [&](int i) -> uint64_t { return keys[i]; }, a.idx + (int64_t)p * a.k,
+               a.val + (int64_t)p * a.k, a.cnt + p);
+}
+
 static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Tile of the first round: small inputs use tiles just large enough to cut
@@ -362,6 +397,16 @@ static int round_tile(int64_t n_in) {
   int t = 1024;
   while (t < n_in) t <<= 1;
   return t;
+}
+
+int64_t topk_seg_tile() { return TOPK_T; }
+int64_t topk_seg_max_keys() { return TOPK_SMALL_MAX; }
+
+hipError_t launch_topk_segmented(const SegTopkArgs& a, int n_tiles, int n_arrays, hipStream_t s) {
+  if (a.k < 1 || a.k > TOPK_T / 2 || n_arrays <= 0) return hipErrorInvalidValue;
+  if (n_tiles > 0) hipLaunchKernelGGL(k_topk_seg_tiles, dim3((unsigned)n_tiles), dim3(TOPK_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_topk_seg_final, dim3((unsigned)n_arrays), dim3(SMALL_THREADS), 0, s, a);
+  return hipGetLastError();
 }
 
 size_t topk_scratch_bytes(int64_t n, int32_t k) {
