@@ -71,6 +71,28 @@ def test_pruned_stack_equals_exact_walk(batch):
         np.testing.assert_array_equal(rep.cpu().numpy(), np.where(nv >= 0, snr.cpu().numpy(), 0.0).astype(np.float32))
 
 
+def test_batched_topk_both_paths(batch):
+    """Batched top-k against the single-array top-k: small k (all patches in
+    two launches) and k = 4096 with a 40000-orbit patch (more survivors than
+    one workgroup selects from: the batch takes per-patch tournaments)."""
+    import torch
+    import paper_2503_08854_amd as dt
+    ws, ctx, patches = batch["ws"], batch["ctx"], batch["patches"]
+    w0 = ws[0]
+    reps = -(-40000 // w0.elements.shape[0])
+    big = dt.OrbitSet(np.tile(w0.elements, (reps, 1))[:40000], w0.t0)
+    for k, sets, pats in [(3, batch["sets"], patches), (4096, [big, batch["sets"][1]], patches[:2])]:
+        outs, tk = dt.stack_batched(ctx, pats, sets, k=k, eager=True, cfg=(512, 2))
+        torch.cuda.synchronize()
+        for p, (patch, orb) in enumerate(zip(pats, sets)):
+            idx, val, cnt = dt.topk(ctx, outs[p][0], k)
+            torch.cuda.synchronize()
+            c = int(cnt.cpu()[0])
+            assert int(tk[2][p].cpu()) == c
+            np.testing.assert_array_equal(tk[0][p].cpu().numpy()[:c], idx.cpu().numpy()[:c])
+            np.testing.assert_array_equal(tk[1][p].cpu().numpy()[:c], val.cpu().numpy()[:c])
+
+
 def test_graph_replay_matches_eager(batch):
     import torch
     import paper_2503_08854_amd as dt
