@@ -521,6 +521,48 @@ def test_pruned_stack_equals_exact_walk(name):
     assert _pruned_vs_exact(w) > 100
 
 
+def _far_tangent(x, deg):
+    """The exposure re-expressed with its TAN tangent point `deg` degrees from
+    its field centre and CRPIX moved so that the centre pixel still looks at
+    the field (a strongly distorted projection of the same sky)."""
+    d2r = np.pi / 180.0
+    ra, dec = x["crval"][0] * d2r, x["crval"][1] * d2r
+    f = np.array([np.cos(dec) * np.cos(ra), np.cos(dec) * np.sin(ra), np.sin(dec)])
+    north = np.array([-np.sin(dec) * np.cos(ra), -np.sin(dec) * np.sin(ra), np.cos(dec)])
+    c = np.cos(deg * d2r) * f + np.sin(deg * d2r) * north
+    rc, dc = np.arctan2(c[1], c[0]), np.arcsin(c[2])
+    e_c = np.array([-np.sin(rc), np.cos(rc), 0.0])
+    n_c = np.array([-np.sin(dc) * np.cos(rc), -np.sin(dc) * np.sin(rc), np.cos(dc)])
+    xi, eta = (e_c @ f) / (c @ f) / d2r, (n_c @ f) / (c @ f) / d2r
+    cd = np.array(x["cd"]).reshape(2, 2)
+    off = np.linalg.solve(cd, [xi, eta])
+    y = dict(x)
+    y["crval"] = [float(rc / d2r % 360.0), float(dc / d2r)]
+    y["crpix"] = [float(x["crpix"][0] - off[0]), float(x["crpix"][1] - off[1])]
+    return y
+
+
+@pytest.mark.parametrize("case", ["wide", "far60", "far80"])
+def test_sky_cone_edge_geometries(tiny, case):
+    """Exposures whose sky cone is too wide to be used (200"/px), whose image
+    is 60 deg from the tangent point (a heavily distorted cone) or 80 deg from
+    it (no cone): the stack equals the exact walk and the oracle."""
+    w = tiny
+    if case == "wide":
+        exps = [dict(x, cd=[v * 1000.0 for v in x["cd"]]) for x in w.exps]
+    else:
+        exps = [_far_tangent(x, 60.0 if case == "far60" else 80.0) for x in w.exps]
+    el = w.elements[:4000] if case == "wide" else w.elements
+    w2 = synth.Workload(name=case, exps=exps, t0=w.t0, elements=el, D=w.D, V=w.V)
+    n_valid = _pruned_vs_exact(w2)
+    assert n_valid > 20  # the 80-deg image covers a much smaller piece of sky
+    g = gpu_run(w2)
+    snr, flux, nv = oracle.stack(w2.elements, w2.t0, exps, w.D, w.V)
+    np.testing.assert_array_equal(g["nv"], nv)
+    ok = snr_close(g["snr"], snr)
+    assert ok.all(), f"{(~ok).sum()} orbits outside tolerance"
+
+
 def test_stack_distant_objects_fp16():
     """Distant-object regime (a 30-60 AU over a year, light time 0.1-0.45 day,
     FP16 images): every sample and S/N against the oracle on the same FP16
