@@ -281,8 +281,8 @@ def main():
     ap.add_argument("--skip-next", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the stack shards by orbit and "
-              f"multi-GPU runs are not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the stack would shard by orbit, "
+              f"but no multi-GPU path is implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2503_08854_amd as dt
