@@ -1,6 +1,8 @@
 // dt_api.cpp -- the C ABI of libdtrack: contexts, patches, argument
 // validation, memory accounting and stream plumbing.  All numerical work is
 // in the kernels; this file only checks arguments, sizes buffers and enqueues.
+#include <cmath>
+
 #include "dt_internal.hpp"
 
 namespace dtk {
@@ -114,6 +116,7 @@ StackArgs stack_args(const dt_patch* p, const dt_orbits* o) {
   a.snr = nullptr;
   a.flux = nullptr;
   a.nvalid = nullptr;
+  a.vobs = p->vobs;
   return a;
 }
 
@@ -235,6 +238,16 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
     off += (int64_t)x.width * x.height;
   }
   p->plane_elems = (size_t)off;
+  // observer speed bound over epoch neighbours (the stack's prediction bound
+  // chains it over any span by the triangle inequality)
+  for (int s = 1; s < n_exp; ++s) {
+    const dt_exposure &x = sorted[s], &y = sorted[s - 1];
+    const double d0 = x.obs_xyz_au[0] - y.obs_xyz_au[0], d1 = x.obs_xyz_au[1] - y.obs_xyz_au[1];
+    const double d2 = x.obs_xyz_au[2] - y.obs_xyz_au[2];
+    const double dist = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2), dt = x.t - y.t;
+    if (dist > 0.0) p->vobs = std::max(p->vobs, dt > 0.0 ? dist / dt : HUGE_VAL);
+  }
+  if (!std::isfinite(p->vobs)) p->vobs = HUGE_VAL;
   if (p->rmax > PREP_RMAX) {
     delete p;
     return fail(DT_E_DOMAIN, "stamp half-width %d exceeds %d", p->rmax, PREP_RMAX);

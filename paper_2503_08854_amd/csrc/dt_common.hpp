@@ -79,6 +79,10 @@ struct StackArgs {
   float* snr;
   float* flux;
   int32_t* nvalid;
+  // Bound on the observer's speed (AU/day) between any two exposures of the
+  // patch: the largest |obs_i - obs_j| / (t_i - t_j) over epoch neighbours
+  // (infinite when two exposures share an epoch but not an observer).
+  double vobs = __builtin_inf();
 };
 
 struct DebugArgs {

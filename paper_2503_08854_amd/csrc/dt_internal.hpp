@@ -41,6 +41,7 @@ struct dt_patch {
   std::vector<int64_t> plane_off;  // caller index -> plane offset
   std::vector<int32_t> W, H;       // caller order
   int rmax = 0;
+  double vobs = 0.0;               // observer speed bound (AU/day), see StackArgs
   int64_t n_tiles = 0;
   std::vector<int64_t> group_off;  // pre-pass tiles grouped by stamp half-width
   std::vector<int32_t> group_R;

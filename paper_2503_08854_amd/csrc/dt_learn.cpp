@@ -105,6 +105,7 @@ dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t fir
   a.planes = p->d_planes;
   a.n = n;
   a.epoch = S->epoch;
+  a.vobs = p->vobs;
   a.snr = d_snr;
   a.flux = d_flux;
   a.nvalid = d_nvalid;

@@ -184,23 +184,30 @@ __device__ inline void kepler_cold(double M, double e, KepState& k) {
 }
 
 // General solve: cold start when `cold`, else warm from the previous solution
-// for any step the rotation series cover (larger steps restart cold); with
-// `anchor` the rotated (sin E, cos E) are replaced by a full sincos.
-__device__ inline void kepler_general(double M, double e, KepState& k, bool anchor, bool cold) {
+// for a start step up to `reach` (larger steps restart cold); the step is
+// taken by a full sincos with `anchor`, else by the rotation series (in equal
+// parts of at most ROT_MAX).
+__device__ inline void kepler_general(double M, double e, KepState& k, bool anchor, bool cold,
+                                      double reach = ROT_MAX) {
   double d = 0.0;
   if (!cold) {
     d = (M - k.M) * k.g;
     d = fma(-0.5 * e * k.sE * k.g, d * d, d);  // E''(M) = -e sin E g^3
   }
-  if (cold || !(fabs(d) <= ROT_MAX)) {
+  if (cold || !(fabs(d) <= reach)) {
     kepler_cold(M, e, k);
     return;
   }
   if (anchor) {
     k.E += d;
     sincos(k.E, &k.sE, &k.cE);
-  } else {
+  } else if (fabs(d) <= ROT_MAX) {
     rot_long(k, d);
+  } else {
+    const int parts = (int)ceil(fabs(d) * (1.0 / ROT_MAX));
+    const double dp = d / parts;
+#pragma unroll 1
+    for (int i = 0; i < parts; ++i) rot_long(k, dp);
   }
 #pragma unroll 1
   for (int it = 0; it < 8; ++it) {
@@ -308,6 +315,23 @@ __device__ __forceinline__ void lt_state(const Orbit& o, const KepState& k, doub
   lt_vel(o, k, tg, s);
 }
 
+// Corrected position q = rho - D v projected through the exposure's TAN WCS:
+// p = CRPIX - 1 + (A . q) / (c . q), then the nearest pixel and the image test.
+__device__ __forceinline__ void project(const ExpMeta& x, const LtSolve& s, SampleOut& out) {
+  const double D = s.D;
+  const double q0 = fma(-D, s.v0, s.rho0), q1 = fma(-D, s.v1, s.rho1), q2 = fma(-D, s.v2, s.rho2);
+  const double w = fma(x.cx, q0, fma(x.cy, q1, x.cz * q2));
+  const double iw = rcp1(w);
+  out.px = fma(fma(x.a0x, q0, fma(x.a0y, q1, x.a0z * q2)), iw, x.px0);
+  out.py = fma(fma(x.a1x, q0, fma(x.a1y, q1, x.a1z * q2)), iw, x.py0);
+  out.front = (w > 0.0) && (s.dist >= 1e-9);
+  // nearest pixel floor(p + 0.5), clamped into int range before conversion
+  const double fx = floor(out.px + 0.5), fy = floor(out.py + 0.5);
+  out.ix = (int)fmin(fmax(fx, -2147483648.0), 2147483647.0);
+  out.iy = (int)fmin(fmax(fy, -2147483648.0), 2147483647.0);
+  out.inside = out.front && (unsigned)out.ix < (unsigned)x.W && (unsigned)out.iy < (unsigned)x.H;
+}
+
 // One (orbit, exposure) sample.  FIRST: the orbit's first exposure (cold
 // Kepler start, no light-time history).  Otherwise `gap` is t_e minus the
 // previous exposure's epoch and inv_gap its reciprocal (0 when gap == 0);
@@ -360,20 +384,8 @@ __device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt,
         if (fabs(s.D) <= LT_LINEAR_MAX) break;
       }
     }
-    const double D = s.D;
-    const double q0 = fma(-D, s.v0, s.rho0), q1 = fma(-D, s.v1, s.rho1), q2 = fma(-D, s.v2, s.rho2);
-    tau = tg + D;
-    // TAN projection: p = CRPIX - 1 + (A . q) / (c . q)
-    const double w = fma(x.cx, q0, fma(x.cy, q1, x.cz * q2));
-    const double iw = rcp1(w);
-    out.px = fma(fma(x.a0x, q0, fma(x.a0y, q1, x.a0z * q2)), iw, x.px0);
-    out.py = fma(fma(x.a1x, q0, fma(x.a1y, q1, x.a1z * q2)), iw, x.py0);
-    out.front = (w > 0.0) && (s.dist >= 1e-9);
-    // nearest pixel floor(p + 0.5), clamped into int range before conversion
-    const double fx = floor(out.px + 0.5), fy = floor(out.py + 0.5);
-    out.ix = (int)fmin(fmax(fx, -2147483648.0), 2147483647.0);
-    out.iy = (int)fmin(fmax(fy, -2147483648.0), 2147483647.0);
-    out.inside = out.front && (unsigned)out.ix < (unsigned)x.W && (unsigned)out.iy < (unsigned)x.H;
+    tau = tg + s.D;
+    project(x, s, out);
   } else {
     tau = tg + D0;
     out.front = out.inside = false;

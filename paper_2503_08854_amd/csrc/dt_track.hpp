@@ -1,0 +1,295 @@
+// dt_track.hpp -- the plain stack by checkpoint prediction: a wavefront of
+// 64 orbits walks the exposures in epoch order together.
+//
+// Sec. 3 / Algorithm 1 test every (image, orbit) pair; almost all pairs miss
+// the image, and a miss can be shown from a cheap bound instead of a full
+// propagation.  Every CK_SPAN days of epochs (wave-uniform) each orbit is
+// solved at the current exposure's epoch t minus a light-time estimate tg:
+// the heliocentric position r, velocity v and half acceleration
+// h = -mu r / (2 |r|^3) at T = t - tg form a checkpoint, and the one-step
+// light-time correction D bounds |tau - tg|.  For a later exposure, D_t =
+// t' - t days on, the observer-relative position is predicted as
+//     p = r + D_t (v + D_t h) - obs',
+// and the exact one (at the emission epoch t' - tau') lies within
+//     m = J D_t^3 / 6 + vmax (|tau' - tau| + |tau - tg|) + slack,
+// where J = 2 mu vmax / q^3 bounds the jerk on the orbit (|d/dt (r / |r|^3)|
+// = sqrt(v^2 + 3 (r.v)^2 / r^2) / r^3 <= 2 |v| / r^3, r >= q the perihelion
+// distance, |v| <= vmax the perihelion speed), and the change of light time
+// obeys |tau' - tau| <= (vmax + vobs) D_t / (c - vmax) with vobs the patch's
+// observer speed bound.  The sky-cone test of the exposure, widened by
+// (1 + tan theta) m, then either proves the sample cannot land or queues it.
+// Queued samples are solved exactly, as the per-sample walk solves them
+// (Kepler from the checkpoint state, light time to LT_LINEAR_MAX, projection,
+// nearest pixel), by whichever lanes are free, 64 at a time, and each orbit
+// adds its gathered values in epoch order, so the sums equal those of the
+// per-sample walk.
+#pragma once
+#include "dt_stack.hpp"
+
+namespace dtk {
+
+constexpr double CK_SPAN = 16.0;      // days: checkpoints at least this often (epoch span)
+constexpr double CK_REACH = 0.3;     // rad: largest Kepler start step taken warm from a checkpoint
+constexpr double PRED_SLACK = 1e-9;  // AU: rounding of the checkpoint state and of the prediction
+constexpr int TQ_CAP = 128;          // queued samples per wavefront (< 64 held + 64 pushed)
+constexpr int TQ_LIST = 8;           // queued samples per lane between flushes
+constexpr int CK_ANCHOR = 8;         // checkpoints between full sincos re-anchors of sin E, cos E
+
+// One wavefront's state in LDS: the queue, and each lane's prepared orbit and
+// checkpoint Kepler state (read by whichever lane solves that orbit's queued
+// samples).  Only the owning wavefront touches it; LDS operations of one
+// wavefront complete in issue order, and the accesses are volatile so the
+// compiler keeps that order.
+struct TrackQueue {
+  int ent[TQ_CAP];                 // exposure << 6 | owner lane
+  float tg[TQ_CAP];                // light-time estimate (days; a Newton start only)
+  float rx[TQ_CAP], ry[TQ_CAP];    // gathered {psi, phi}; {0, 0} when not a valid sample
+  unsigned char list[TQ_LIST][64]; // queue slots of each lane, in push order
+  double orb[9][64];               // e, n, M0, aP, bQ of each lane's orbit
+  double kep[4][64];               // E, sin E, cos E, g at the lane's checkpoint (M = E - e sin E)
+  float bnd[2][64];                // j6, l1 of TrackBound, rounded up
+};
+typedef __attribute__((address_space(3))) TrackQueue LdsTrackQueue;
+
+// Coefficients of m(D), scaled by 1.1 >= 1 + tan(theta) (cones wider than
+// tan(theta) = 0.1 are not used).
+struct TrackBound {
+  double j6, l1, vmax;
+};
+
+__device__ __forceinline__ void track_bound(double a, double e, const Orbit& o, double vobs, TrackBound& b) {
+  const double vmax = o.n * a * sqrt((1.0 + e) / (1.0 - e));
+  const double iq = 1.0 / (a * (1.0 - e));
+  const double acc = MU_SUN * iq * iq;
+  b.j6 = 1.1 * (2.0 * MU_SUN * vmax * iq * iq * iq) / 6.0;
+  // the checkpoint velocity is taken at t - tg, up to LT_LINEAR_MAX from the emission epoch
+  b.l1 = 1.1 * (vmax * (vmax + vobs) / (C_AU_DAY - vmax) + acc * LT_LINEAR_MAX);
+  b.vmax = vmax;
+}
+
+// The walk of one wavefront.  All 64 lanes call it together; lanes with
+// live = false (no orbit, or one outside the domain) carry any valid
+// prepared orbit and queue nothing.  P receives each live lane's sums.
+//
+// Each exposure first runs the service step (wave-uniform): the queued
+// samples, 64 at a time, when a checkpoint is due, the queue is half full or
+// a lane's list is full, or after the last exposure; then the checkpoint
+// solve of every lane when due.  Both are one loop over jobs so the exact
+// solve exists once in the code.  Then the cone test of the prediction
+// queues the samples that may land.
+__device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, const TrackBound& bd, bool live,
+                                           TrackQueue& Qm, StackPart& P) {
+  // LDS address space explicitly: volatile accesses through a generic pointer
+  // would be kept generic (flat) by the compiler
+  volatile LdsTrackQueue& Q = *(volatile LdsTrackQueue*)(&Qm);
+  const int lane = (int)__lane_id();
+  const ExpMeta* __restrict__ meta = A.meta;
+  P.ps.init();
+  P.ph.init();
+  P.nv = 0;
+  if (A.n_exp <= 0) return;
+  Q.orb[0][lane] = o.e;
+  Q.orb[1][lane] = o.n;
+  Q.orb[2][lane] = o.m0;
+  Q.orb[3][lane] = o.aP0;
+  Q.orb[4][lane] = o.aP1;
+  Q.orb[5][lane] = o.aP2;
+  Q.orb[6][lane] = o.bQ0;
+  Q.orb[7][lane] = o.bQ1;
+  Q.orb[8][lane] = o.bQ2;
+  Q.bnd[0][lane] = __double2float_ru(bd.j6);
+  Q.bnd[1][lane] = __double2float_ru(bd.l1);
+  const double vmax = bd.vmax;
+  double j6 = 0.0, l1 = 0.0;  // reloaded after every service step
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
+  double s0 = 0.0;   // 1.1 PRED_SLACK, or 1e300 after a checkpoint whose light time did not converge
+  double tc = 0.0;   // checkpoint epoch
+  int n_ck = 0;      // checkpoints so far
+  int count = 0;     // queued samples (wave-uniform)
+  int len = 0;       // this lane's queued samples
+  bool full = false; // the queue must be served before more samples are pushed
+
+  for (int ex = 0; ex <= A.n_exp; ++ex) {
+    const bool last = ex == A.n_exp;
+    const ExpMeta& x = meta[last ? ex - 1 : ex];
+    double D = x.t - tc;
+    double p0 = fma(fma(h0, D, v0), D, r0) - x.ox;
+    double p1 = fma(fma(h1, D, v1), D, r1) - x.oy;
+    double p2 = fma(fma(h2, D, v2), D, r2) - x.oz;
+    const bool ck = !last && (ex == 0 || D > CK_SPAN);
+    const bool fl = count > 0 && (last || ck || full);
+    if (fl || ck) {
+      const int nb = fl ? (count + 63) >> 6 : 0;
+      double tg_ck = 0.0;
+      if (ck && ex > 0) {
+        const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
+        tg_ck = d2 * __builtin_amdgcn_rsq(d2) * IC;
+      }
+#pragma unroll 1
+      for (int jb = 0; jb < nb + (ck ? 1 : 0); ++jb) {
+        const bool ckj = jb == nb;  // the checkpoint job comes last
+        const int i = jb * 64 + lane;
+        const bool has = ckj || i < count;
+        const int ent = ckj ? ((ex << 6) | lane) : (has ? Q.ent[i] : lane);
+        const int L = ent & 63;
+        if (has) {
+          Orbit oo;
+          KepState kk;
+          oo.e = Q.orb[0][L];
+          oo.n = Q.orb[1][L];
+          oo.m0 = Q.orb[2][L];
+          oo.aP0 = Q.orb[3][L];
+          oo.aP1 = Q.orb[4][L];
+          oo.aP2 = Q.orb[5][L];
+          oo.bQ0 = Q.orb[6][L];
+          oo.bQ1 = Q.orb[7][L];
+          oo.bQ2 = Q.orb[8][L];
+          kk.E = Q.kep[0][L];
+          kk.sE = Q.kep[1][L];
+          kk.cE = Q.kep[2][L];
+          kk.g = Q.kep[3][L];
+          kk.M = fma(-oo.e, kk.sE, kk.E);  // the solved equation, to the Newton tolerance
+          const ExpMeta& xm = meta[ent >> 6];
+          const double dt = xm.t - A.epoch;
+          const double b0 = -xm.ox, b1 = -xm.oy, b2 = -xm.oz;
+          double tg = ckj ? tg_ck : (double)Q.tg[i];
+          // exact solve: Kepler (cold at the first exposure, else warm from the
+          // checkpoint state, re-anchored every CK_ANCHOR checkpoints), light time
+          double M = fma(oo.n, dt - tg, oo.m0);
+          kepler_general(M, oo.e, kk, ckj && n_ck % CK_ANCHOR == CK_ANCHOR - 1, ckj && ex == 0, CK_REACH);
+          LtSolve s;
+          lt_state(oo, kk, b0, b1, b2, tg, s);
+          // a checkpoint after the first needs no converged light time (see below)
+          if ((!ckj || ex == 0) && !(fabs(s.D) <= LT_LINEAR_MAX)) {
+#pragma unroll 1
+            for (int pass = 1; pass <= 3; ++pass) {
+              tg += s.D;
+              M = fma(oo.n, dt - tg, oo.m0);
+              kepler_general(M, oo.e, kk, false, false);
+              lt_state(oo, kk, b0, b1, b2, tg, s);
+              if (fabs(s.D) <= LT_LINEAR_MAX) break;
+            }
+          }
+          if (ckj) {
+            // New checkpoint: the state at T = t - tg (the prediction state is
+            // rebuilt from it below).  The exact emission epoch of this
+            // exposure is T - D up to the one-step error, so predictions taken
+            // at t_j - tg are off by at most vmax (|tau_j - tau_c| + |D|): the
+            // second part goes into the slack.
+            Q.kep[0][lane] = kk.E;
+            Q.kep[1][lane] = kk.sE;
+            Q.kep[2][lane] = kk.cE;
+            Q.kep[3][lane] = kk.g;
+            const double dtau = 1.01 * fabs(s.D) + 1e-9;
+            s0 = dtau < 1.0 ? 1.1 * (PRED_SLACK + vmax * dtau) : 1e300;
+          } else {
+            SampleOut so;
+            project(xm, s, so);
+            float2 v = make_float2(0.f, 0.f);
+            if (so.inside) v = A.planes[xm.plane_off + (int64_t)so.iy * xm.W + so.ix];
+            const bool ok = v.y > 0.f;
+            Q.rx[i] = ok ? v.x : 0.f;
+            Q.ry[i] = ok ? v.y : 0.f;
+          }
+        }
+      }
+      if (nb > 0) {
+        // each orbit adds its samples in push (= epoch) order
+#pragma unroll 1
+        for (int q = 0; q < len; ++q) {
+          const int i = Q.list[q][lane];
+          const float vx = Q.rx[i], vy = Q.ry[i];
+          if (vy > 0.f) {
+            P.ps.add(vx);
+            P.ph.add(vy);
+            P.nv++;
+          }
+        }
+        count = 0;
+        len = 0;
+      }
+      // prediction state from the checkpoint kept in LDS (recomputed after every
+      // service step, so it holds no registers while the solves run): the
+      // heliocentric position r(E) and velocity v(E) at T and the half
+      // acceleration -mu r / (2 |r|^3)
+      {
+        const double e = Q.orb[0][lane], n = Q.orb[1][lane];
+        const double aP0 = Q.orb[3][lane], aP1 = Q.orb[4][lane], aP2 = Q.orb[5][lane];
+        const double bQ0 = Q.orb[6][lane], bQ1 = Q.orb[7][lane], bQ2 = Q.orb[8][lane];
+        const double sE = Q.kep[1][lane], cE = Q.kep[2][lane], g = Q.kep[3][lane];
+        const double cme = cE - e, ng = n * g;
+        const double vs = -ng * sE, vc = ng * cE;
+        v0 = fma(vc, bQ0, vs * aP0);
+        v1 = fma(vc, bQ1, vs * aP1);
+        v2 = fma(vc, bQ2, vs * aP2);
+        r0 = fma(cme, aP0, sE * bQ0);
+        r1 = fma(cme, aP1, sE * bQ1);
+        r2 = fma(cme, aP2, sE * bQ2);
+        double rr, irr;
+        sqrt_rsq(fma(r0, r0, fma(r1, r1, r2 * r2)), rr, irr);
+        const double hk = -0.5 * MU_SUN * irr * irr * irr;
+        h0 = hk * r0;
+        h1 = hk * r1;
+        h2 = hk * r2;
+        j6 = (double)Q.bnd[0][lane];
+        l1 = (double)Q.bnd[1][lane];
+      }
+      // this exposure's record again, by an index the compiler does not
+      // match with the first one (ex >> 30 is 0), so the first values need
+      // not be kept in registers across the solves
+      const ExpMeta& y = meta[(last ? ex - 1 : ex) + (ex >> 30)];
+      if (ck) {
+        tc = y.t;
+        n_ck++;
+        D = 0.0;
+      }
+      p0 = fma(fma(h0, D, v0), D, r0) - y.ox;
+      p1 = fma(fma(h1, D, v1), D, r1) - y.oy;
+      p2 = fma(fma(h2, D, v2), D, r2) - y.oz;
+    }
+    if (last) break;
+    // cone test of the prediction (bitwise logic, no branches)
+    const double sc = fma(x.ux, p0, fma(x.uy, p1, x.uz * p2));
+    const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
+    const double m = fma(j6 * D * D, D, fma(l1, D, s0));
+    const double R = fma(x.cone_tan, sc, m);
+    const bool may = live & (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(may);
+    if (mask) {
+      if (may) {
+        const int slot = count + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        Q.ent[slot] = (ex << 6) | lane;
+        Q.tg[slot] = (float)(d2 * __builtin_amdgcn_rsq(d2) * IC);
+        Q.list[len][lane] = (unsigned char)slot;
+        len++;
+      }
+      count += __builtin_popcountll(mask);
+      full = count >= 64 || __builtin_amdgcn_ballot_w64(len >= TQ_LIST) != 0;
+    }
+  }
+}
+
+// One lane's orbit through the walk of its wavefront: `el` holds the
+// elements when `live` (any values otherwise); the outputs are those of the
+// per-sample stack (NaN, NaN, -1 for an orbit that is not live).  All 64
+// lanes of the wavefront call it together; Q is the wavefront's LDS queue.
+__device__ __forceinline__ void track_stack_lane(const StackArgs& A, const double el[6], bool live, TrackQueue& Q,
+                                                 float& snr, float& flux, int& nv) {
+  double a = el[0], e = el[1], inc = el[2], node = el[3], peri = el[4], m0 = el[5];
+  if (!live) {
+    a = 2.5;
+    e = inc = node = peri = m0 = 0.0;
+  }
+  Orbit ob;
+  orbit_prep(a, e, inc, node, peri, m0, ob);
+  TrackBound bd;
+  track_bound(a, e, ob, A.vobs, bd);
+  StackPart P;
+  track_walk(A, ob, bd, live, Q, P);
+  snr = flux = __builtin_nanf("");
+  nv = -1;
+  if (live) stack_finish(P, snr, flux, nv);
+}
+
+}  // namespace dtk

@@ -9,16 +9,17 @@
 // another until the counter passes the end.  Large and small patches share
 // the CUs, and the tail is made of the cheapest items.  The counter is zeroed
 // by a one-thread kernel so the whole sequence can be captured in a graph.
-#include "dt_stack.hpp"
+#include "dt_track.hpp"
 
 namespace dtk {
 
 __global__ void k_reset_counter(unsigned int* counter) { *counter = 0u; }
 
-__global__ __launch_bounds__(256) void k_stack_persistent(const StackArgs* __restrict__ descs,
-                                                          const WorkItem* __restrict__ items, int n_items,
-                                                          unsigned int* __restrict__ counter) {
+__global__ __launch_bounds__(256, 4) void k_stack_persistent(const StackArgs* __restrict__ descs,
+                                                             const WorkItem* __restrict__ items, int n_items,
+                                                             unsigned int* __restrict__ counter) {
   __shared__ int s_item;
+  __shared__ TrackQueue tq[4];
   while (true) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
     __syncthreads();
@@ -27,7 +28,28 @@ __global__ __launch_bounds__(256) void k_stack_persistent(const StackArgs* __res
     if (it >= n_items) break;
     const WorkItem w = items[it];
     const StackArgs A = descs[w.patch];
-    for (int64_t o = w.begin + threadIdx.x; o < w.begin + w.count; o += blockDim.x) {
+    const int64_t end = w.begin + w.count;
+    if (A.vobs < __builtin_inf()) {
+      // checkpoint prediction, one wavefront per 64 orbits (as k_stack_track)
+      for (int64_t o = w.begin + threadIdx.x; o - (int64_t)__lane_id() < end; o += blockDim.x) {
+        const bool in = o < end;
+        double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (in) {
+          el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+        }
+        float snr, flux;
+        int nv;
+        track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6],
+                         snr, flux, nv);
+        if (in) {
+          if (A.snr) A.snr[o] = snr;
+          if (A.flux) A.flux[o] = flux;
+          if (A.nvalid) A.nvalid[o] = nv;
+        }
+      }
+      continue;
+    }
+    for (int64_t o = w.begin + threadIdx.x; o < end; o += blockDim.x) {
       float snr, flux;
       int nv;
       stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);

@@ -14,7 +14,7 @@
 // branch) gives the node and the argument of perihelion, and nu gives M0.
 // Up to 16 attempts per index (counter-based draws); an index whose attempts
 // all miss gets a = NaN, which the stack reports as outside the domain.
-#include "dt_stack.hpp"
+#include "dt_track.hpp"
 
 namespace dtk {
 
@@ -112,6 +112,24 @@ __global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_s
   if (A.nvalid) A.nvalid[i] = nv;
 }
 
+// The same by checkpoint prediction (one wavefront per 64 generated orbits).
+__global__ __launch_bounds__(256, 4) void k_stack_generated_track(StackArgs A, dt_orbit_sampler S, int64_t first) {
+  __shared__ TrackQueue tq[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i - (int64_t)__lane_id() >= A.n) return;  // the whole wavefront is past the end
+  const bool in = i < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool live = in && gen_orbit(S, (uint64_t)(first + i), el) &&
+                    orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
+  float snr, flux;
+  int nv;
+  track_stack_lane(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv);
+  if (!in) return;
+  if (A.snr) A.snr[i] = snr;
+  if (A.flux) A.flux[i] = flux;
+  if (A.nvalid) A.nvalid[i] = nv;
+}
+
 hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, double* a, double* e, double* inc,
                            double* node, double* peri, double* m0, hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -122,7 +140,10 @@ hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, 
 
 hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stack_generated, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
+  if (a.vobs < __builtin_inf())
+    hipLaunchKernelGGL(k_stack_generated_track, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
+  else
+    hipLaunchKernelGGL(k_stack_generated, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
   return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@
 // Layout: one lane per orbit (orbit-major, coalesced SoA element loads),
 // exposure metadata read with wave-uniform (scalar) loads, planes as
 // interleaved float2 {psi, phi} so a valid sample costs one 8-byte gather.
-#include "dt_stack.hpp"
+#include "dt_track.hpp"
 
 namespace dtk {
 
@@ -23,6 +23,27 @@ __global__ __launch_bounds__(256) void k_stack(StackArgs A) {
   float snr, flux;
   int nv;
   stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
+// The same stack by checkpoint prediction (one wavefront = 64 orbits walking
+// together; used when the patch has a finite observer speed bound).
+__global__ __launch_bounds__(256, 4) void k_stack_track(StackArgs A) {
+  __shared__ TrackQueue tq[4];
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o - (int64_t)__lane_id() >= A.n) return;  // the whole wavefront is past the end
+  const bool in = o < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (in) {
+    el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+  }
+  float snr, flux;
+  int nv;
+  track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr,
+                   flux, nv);
+  if (!in) return;
   if (A.snr) A.snr[o] = snr;
   if (A.flux) A.flux[o] = flux;
   if (A.nvalid) A.nvalid[o] = nv;
@@ -86,7 +107,10 @@ hipError_t launch_gather_replay(const float2* planes, const uint32_t* off, int64
 
 hipError_t launch_stack(const StackArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stack, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+  if (a.vobs < __builtin_inf())
+    hipLaunchKernelGGL(k_stack_track, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_stack, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -563,6 +563,60 @@ def test_sky_cone_edge_geometries(tiny, case):
     assert ok.all(), f"{(~ok).sum()} orbits outside tolerance"
 
 
+def _tracked_long_gaps(w):
+    """Epochs of the small field spread over a year; even exposures point at
+    a main-belt orbit, odd ones at a short-period eccentric orbit (a = 1 AU,
+    e = 0.7), with 2 arcsec pixels; orbits: a cloud around each."""
+    import math
+    t0 = w.t0
+    ref_mb = w.elements[w.inj_index[0]]
+    ref_fast = np.array([1.0, 0.7, math.radians(12.0), 1.0, 2.0, 0.5])
+
+    def point(x, el):
+        rho, _, _, _ = oracle.light_time(el, t0, x["t"], np.array(x["obs"], float))
+        u = oracle.ecl_to_eq(rho / np.linalg.norm(rho))
+        ra, dec = math.degrees(math.atan2(u[1], u[0])) % 360.0, math.degrees(math.asin(u[2]))
+        return dict(x, crval=[ra, dec], crpix=[x["width"] / 2 + 0.5, x["height"] / 2 + 0.5])
+
+    exps = [dict(x, t=t0 + 12.0 * (x["t"] - t0), cd=[v * 10.0 for v in x["cd"]]) for x in w.exps]
+    exps = [point(x, ref_mb if i % 2 == 0 else ref_fast) for i, x in enumerate(exps)]
+    rng = np.random.default_rng(3)
+
+    def cloud(ref, n, da, dm):
+        c = np.repeat(ref[None], n, 0)
+        c[:, 0] += rng.uniform(-da, da, n)
+        c[:, 5] += rng.uniform(-dm, dm, n)
+        return c
+
+    return exps, np.concatenate([cloud(ref_mb, 3000, 2e-3, 2e-3), cloud(ref_fast, 3000, 2e-4, 2e-3)])
+
+
+@pytest.mark.parametrize("case", ["shared_epoch", "long_gaps"])
+def test_checkpoint_walk_edge_cases(tiny, case):
+    """The stack's checkpoint prediction (a bound on the observer's speed, a
+    checkpoint every few weeks of epochs) against the exact walk and the
+    oracle.  shared_epoch: two exposures at one epoch seen from different
+    observers leave the observer speed unbounded, and the per-sample walk
+    runs instead.  long_gaps: gaps of weeks between exposures and orbits
+    whose Kepler steps between checkpoints exceed the warm start's reach
+    (a = 1 AU, e = 0.7), landing in up to ten exposures each."""
+    w = tiny
+    if case == "shared_epoch":
+        exps = [dict(x) for x in w.exps]
+        exps[1] = dict(exps[1], t=exps[0]["t"], obs=[v + 1e-4 for v in exps[0]["obs"]])
+        el = w.elements
+    else:
+        exps, el = _tracked_long_gaps(w)
+    w2 = synth.Workload(name=case, exps=exps, t0=w.t0, elements=el, D=w.D, V=w.V)
+    n_valid = _pruned_vs_exact(w2)
+    assert n_valid > 5000
+    g = gpu_run(w2)
+    snr, flux, nv = oracle.stack(w2.elements, w2.t0, exps, w.D, w.V)
+    np.testing.assert_array_equal(g["nv"], nv)
+    ok = snr_close(g["snr"], snr)
+    assert ok.all(), f"{(~ok).sum()} orbits outside tolerance"
+
+
 def test_stack_distant_objects_fp16():
     """Distant-object regime (a 30-60 AU over a year, light time 0.1-0.45 day,
     FP16 images): every sample and S/N against the oracle on the same FP16
