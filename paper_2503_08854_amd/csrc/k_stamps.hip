@@ -14,7 +14,7 @@
 // A source on any member therefore shows as a peak near its (u, v).  One
 // wavefront per cell; each lane owns 7 of the 441 nodes.  Per-cell features
 // summarise the stamp and the cell's elements.
-#include "dt_stack.hpp"
+#include "dt_track.hpp"
 
 namespace dtk {
 
@@ -291,6 +291,35 @@ __global__ __launch_bounds__(256) void k_stack_cells(StackArgs A, const int64_t*
   if (A.nvalid) A.nvalid[o] = nv;
 }
 
+// The cell stack by checkpoint prediction: one lane per member, a wavefront
+// walks 64 members together (as the full stack's k_stack_track).  Splitting
+// the exposures over several wavefronts, as k_stack_cells does, measured
+// slower here: every range starts from a cold checkpoint.
+__global__ __launch_bounds__(256, 4) void k_stack_cells_track(StackArgs A, const int64_t* __restrict__ cells,
+                                                              int64_t n_sel, int cell_size) {
+  __shared__ TrackQueue tq[4];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r - (int64_t)__lane_id() >= n_sel * cell_size) return;  // the whole wavefront is past the end
+  int64_t o = -1;
+  if (r < n_sel * cell_size) {
+    const int64_t c = cells[r / cell_size];
+    if (c >= 0) o = c * cell_size + r % cell_size;
+  }
+  const bool ok = o >= 0 && o < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (ok) {
+    el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+  }
+  float snr, flux;
+  int nv;
+  track_stack_lane(A, el, ok && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr, flux,
+                   nv);
+  if (!ok) return;
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
 hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, uint16_t* st_bf, float* st_f,
                               uint16_t* ft_bf, float* ft_f, hipStream_t s) {
   if (reps.n <= 0) return hipSuccess;
@@ -309,6 +338,11 @@ hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_
   int split = 1;
   while (split < 4 && n * split * 2 <= (int64_t)1 << 20 && a.n_exp >= 12 * split) split *= 2;
   const int64_t per_block = 256 / split;  // orbits per workgroup
+  if (a.vobs < __builtin_inf()) {
+    hipLaunchKernelGGL(k_stack_cells_track, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d_cells, n_sel,
+                       cell_size);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_stack_cells, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256), 0, s, a, d_cells,
                      n_sel, cell_size, split);
   return hipGetLastError();
