@@ -97,9 +97,14 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   Q.orb[6][lane] = o.bQ0;
   Q.orb[7][lane] = o.bQ1;
   Q.orb[8][lane] = o.bQ2;
-  Q.bnd[0][lane] = __double2float_ru(bd.j6);
-  Q.bnd[1][lane] = __double2float_ru(bd.l1);
-  const double vmax = bd.vmax;
+  // An orbit whose bound coefficients do not fit FP32 comfortably (perihelion
+  // distance ~1e-10 AU, absurd observer speeds) is never pruned: its slack
+  // stays 1e300 and the stored coefficients are 0, so no step of zero
+  // multiplies an infinity.
+  const bool bounded = bd.j6 < 1e30 && bd.l1 < 1e30 && bd.vmax < 1e30;
+  Q.bnd[0][lane] = bounded ? __double2float_ru(bd.j6) : 0.f;
+  Q.bnd[1][lane] = bounded ? __double2float_ru(bd.l1) : 0.f;
+  const double vmax = bounded ? bd.vmax : 0.0;
   double j6 = 0.0, l1 = 0.0;  // reloaded after every service step
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
   double s0 = 0.0;   // 1.1 PRED_SLACK, or 1e300 after a checkpoint whose light time did not converge
@@ -181,7 +186,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
             Q.kep[2][lane] = kk.cE;
             Q.kep[3][lane] = kk.g;
             const double dtau = 1.01 * fabs(s.D) + 1e-9;
-            s0 = dtau < 1.0 ? 1.1 * (PRED_SLACK + vmax * dtau) : 1e300;
+            s0 = bounded && dtau < 1.0 ? 1.1 * (PRED_SLACK + vmax * dtau) : 1e300;
           } else {
             SampleOut so;
             project(xm, s, so);
