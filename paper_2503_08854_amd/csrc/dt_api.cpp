@@ -247,7 +247,9 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
     const double dist = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2), dt = x.t - y.t;
     if (dist > 0.0) p->vobs = std::max(p->vobs, dt > 0.0 ? dist / dt : HUGE_VAL);
   }
-  if (!std::isfinite(p->vobs)) p->vobs = HUGE_VAL;
+  // the checkpoint walk packs an exposure index into 25 bits; beyond that (and
+  // without a finite bound) the per-sample walk runs
+  if (!std::isfinite(p->vobs) || n_exp >= (1 << 25)) p->vobs = HUGE_VAL;
   if (p->rmax > PREP_RMAX) {
     delete p;
     return fail(DT_E_DOMAIN, "stamp half-width %d exceeds %d", p->rmax, PREP_RMAX);
