@@ -591,7 +591,7 @@ def _tracked_long_gaps(w):
     return exps, np.concatenate([cloud(ref_mb, 3000, 2e-3, 2e-3), cloud(ref_fast, 3000, 2e-4, 2e-3)])
 
 
-@pytest.mark.parametrize("case", ["shared_epoch", "long_gaps"])
+@pytest.mark.parametrize("case", ["shared_epoch", "long_gaps", "one_exposure", "repeated_exposure"])
 def test_checkpoint_walk_edge_cases(tiny, case):
     """The stack's checkpoint prediction (a bound on the observer's speed, a
     checkpoint every few weeks of epochs) against the exact walk and the
@@ -599,19 +599,29 @@ def test_checkpoint_walk_edge_cases(tiny, case):
     observers leave the observer speed unbounded, and the per-sample walk
     runs instead.  long_gaps: gaps of weeks between exposures and orbits
     whose Kepler steps between checkpoints exceed the warm start's reach
-    (a = 1 AU, e = 0.7), landing in up to ten exposures each."""
+    (a = 1 AU, e = 0.7), landing in up to ten exposures each.  one_exposure:
+    a patch of the exposure nearest the grid epoch alone.  repeated_exposure:
+    that exposure twice (same epoch and observer, so the observer speed stays
+    bounded), each copy with its own images."""
     w = tiny
+    D, V = w.D, w.V
     if case == "shared_epoch":
         exps = [dict(x) for x in w.exps]
         exps[1] = dict(exps[1], t=exps[0]["t"], obs=[v + 1e-4 for v in exps[0]["obs"]])
         el = w.elements
-    else:
+    elif case == "long_gaps":
         exps, el = _tracked_long_gaps(w)
-    w2 = synth.Workload(name=case, exps=exps, t0=w.t0, elements=el, D=w.D, V=w.V)
+    else:
+        k = int(np.argmin([abs(x["t"] - w.t0) for x in w.exps]))
+        j = (k + 1) % len(w.exps)
+        exps = [dict(w.exps[k])] if case == "one_exposure" else [dict(w.exps[k]), dict(w.exps[k])]
+        D, V = ([w.D[k]], [w.V[k]]) if case == "one_exposure" else ([w.D[k], w.D[j]], [w.V[k], w.V[j]])
+        el = w.elements
+    w2 = synth.Workload(name=case, exps=exps, t0=w.t0, elements=el, D=D, V=V)
     n_valid = _pruned_vs_exact(w2)
-    assert n_valid > 5000
+    assert n_valid > (5000 if case in ("shared_epoch", "long_gaps") else 500)
     g = gpu_run(w2)
-    snr, flux, nv = oracle.stack(w2.elements, w2.t0, exps, w.D, w.V)
+    snr, flux, nv = oracle.stack(w2.elements, w2.t0, exps, D, V)
     np.testing.assert_array_equal(g["nv"], nv)
     ok = snr_close(g["snr"], snr)
     assert ok.all(), f"{(~ok).sum()} orbits outside tolerance"
