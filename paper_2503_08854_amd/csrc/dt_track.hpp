@@ -51,8 +51,8 @@ struct TrackQueue {
 };
 typedef __attribute__((address_space(3))) TrackQueue LdsTrackQueue;
 
-// Coefficients of m(D), scaled by 1.1 >= 1 + tan(theta) (cones wider than
-// tan(theta) = 0.1 are not used).
+// Coefficients of m (times D^3 and D), scaled by 1.1 >= 1 + tan(theta) (cones
+// wider than tan(theta) = 0.1 are not used).
 struct TrackBound {
   double j6, l1, vmax;
 };
@@ -62,7 +62,8 @@ __device__ __forceinline__ void track_bound(double a, double e, const Orbit& o, 
   const double iq = 1.0 / (a * (1.0 - e));
   const double acc = MU_SUN * iq * iq;
   b.j6 = 1.1 * (2.0 * MU_SUN * vmax * iq * iq * iq) / 6.0;
-  // the checkpoint velocity is taken at t - tg, up to LT_LINEAR_MAX from the emission epoch
+  // the light-time term, plus acc x LT_LINEAR_MAX of margin (the checkpoint's
+  // r and v are both taken at T, so no epoch mismatch needs it)
   b.l1 = 1.1 * (vmax * (vmax + vobs) / (C_AU_DAY - vmax) + acc * LT_LINEAR_MAX);
   b.vmax = vmax;
 }
