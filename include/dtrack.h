@@ -165,6 +165,25 @@ dt_status dt_orbits_validate(dt_ctx *ctx, const dt_orbits *orbits, int64_t *n_ba
 dt_status dt_topk(dt_ctx *ctx, const float *d_snr, int64_t n, int32_t k, float threshold,
                   int64_t *d_idx, float *d_val, int32_t *d_count);
 
+/* Allocation-free top-k, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same selection, order, outputs and argument rules as
+ * dt_topk, but the tournament's key buffers live in a fixed device array of
+ * DT_TOPK_NOALLOC_BYTES bytes that the library holds on every GPU it runs on
+ * until the process ends (its address is resolved by dt_ctx_create); the
+ * call allocates nothing.  Inputs whose tournament needs more than that --
+ * (2 ceil(n / T) k + 8192) * 8 bytes with tiles of T = 8192 keys when
+ * n > 65536, so e.g. n = 10^7 with k <= 1700 or n = 10^9 with k <= 17 fit --
+ * fail with DT_E_ARG before anything is enqueued; n <= 16384 needs none.
+ * Every call on one GPU shares that array: calls that may overlap on a GPU
+ * (different streams or contexts on the same device) race and must be
+ * serialised by the caller.  No part of the array needs clearing between
+ * calls (every key a round reads was written by the previous round of the
+ * same call). */
+#define DT_TOPK_NOALLOC_BYTES (32u << 20)
+dt_status dt_topk_noalloc(dt_ctx *ctx, const float *d_snr, int64_t n, int32_t k, float threshold,
+                          int64_t *d_idx, float *d_val, int32_t *d_count);
+
 /* Launch shape of the batched stack: orbits per work item (multiple of 256
  * in [256, 65536]) and persistent workgroups per compute unit ([1, 16]). */
 typedef struct {

@@ -77,6 +77,7 @@ def lib():
         "dt_stack": ([_P, C.POINTER(DtOrbits), _P, _P, _P], C.c_int),
         "dt_orbits_validate": ([_P, C.POINTER(DtOrbits), C.POINTER(C.c_int64)], C.c_int),
         "dt_topk": ([_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P, _P], C.c_int),
+        "dt_topk_noalloc": ([_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P, _P], C.c_int),
         "dt_debug_samples": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P], C.c_int),
         "dt_stack_batched": ([_P, C.POINTER(_P), C.POINTER(DtOrbits), C.c_int32, C.POINTER(_P), C.POINTER(_P),
                               C.POINTER(_P), C.c_int32, C.c_float, _P, _P, _P, C.POINTER(DtBatchConfig),
@@ -319,6 +320,14 @@ def topk(ctx: Context, snr, k: int, threshold: float = float("-inf")):
     cnt = torch.empty(1, dtype=torch.int32, device=dev)
     _check(lib().dt_topk(ctx.handle, _ptr(snr), int(snr.numel()), int(k), float(threshold), _ptr(idx), _ptr(val),
                          _ptr(cnt)))
+    return idx, val, cnt
+
+
+def topk_noalloc(ctx: Context, snr, idx, val, cnt, k: int, threshold: float = float("-inf")):
+    """dt_topk_noalloc into caller-provided outputs (idx int64[k], val
+    float32[k], cnt int32[1] device tensors): nothing is allocated."""
+    _check(lib().dt_topk_noalloc(ctx.handle, _ptr(snr), int(snr.numel()), int(k), float(threshold), _ptr(idx),
+                                 _ptr(val), _ptr(cnt)))
     return idx, val, cnt
 
 

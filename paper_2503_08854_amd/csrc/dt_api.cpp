@@ -150,6 +150,8 @@ dt_status dt_ctx_create(int device, void* hip_stream, dt_ctx** out) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
   if (device < 0 || device >= n) return fail(DT_E_ARG, "device %d out of range (%d devices)", device, n);
   DeviceGuard g(device);
+  e = topk_noalloc_setup(device);
+  if (e != hipSuccess) return hip_fail(e, "allocation-free top-k scratch address");
   dt_ctx* c = new dt_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);

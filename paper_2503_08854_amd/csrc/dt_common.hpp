@@ -214,6 +214,9 @@ hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, 
                            double* node, double* peri, double* m0, hipStream_t s);
 hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s);
 
+// Resolves, with `device` current, the device address of the allocation-free
+// top-k's fixed scratch array (once per device).
+hipError_t topk_noalloc_setup(int device);
 // Top-k scratch requirement (bytes) for n inputs and k outputs.
 size_t topk_scratch_bytes(int64_t n, int32_t k);
 hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,

@@ -7,7 +7,9 @@
 // every key is distinct.  Orbits below the threshold (or NaN) get key 0.
 // A tournament of LDS bitonic sorts keeps the best k of every TOPK_T-key tile
 // until a single tile remains.
-#include "dt_common.hpp"
+#include <mutex>
+
+#include "dt_internal.hpp"
 
 namespace dtk {
 
@@ -463,4 +465,57 @@ hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int6
   return hipGetLastError();
 }
 
+// ---- allocation-free variant (dt_topk_noalloc) ----
+// The tournament's key buffers live in a fixed device array instead of
+// context scratch.  Host code never passes the array's name to a kernel: the
+// name is a host-side stand-in, so the device address of each GPU's copy is
+// resolved once per device (hipGetSymbolAddress, with that device current)
+// and kept in noalloc_ptr[].
+constexpr size_t NOALLOC_BYTES = (size_t)DT_TOPK_NOALLOC_BYTES;
+static __device__ __align__(256) uint64_t scratch[NOALLOC_BYTES / sizeof(uint64_t)];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+static std::mutex noalloc_mu;
+static void* noalloc_ptr[NOALLOC_MAX_DEV];
+
+// Called by dt_ctx_create with `device` current.
+hipError_t topk_noalloc_setup(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (noalloc_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  noalloc_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+static void* topk_noalloc_ptr(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEV) return nullptr;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  return noalloc_ptr[device];
+}
+
 }  // namespace dtk
+
+extern "C" dt_status dt_topk_noalloc(dt_ctx* c, const float* d_snr, int64_t n, int32_t k, float threshold,
+                                     int64_t* d_idx, float* d_val, int32_t* d_count) {
+  using namespace dtk;
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  if (n < 0 || (n > 0 && !d_snr)) return fail(DT_E_ARG, "bad S/N array");
+  if (n >= ((int64_t)1 << 32)) return fail(DT_E_ARG, "n must be < 2^32");
+  if (k < 1 || k > 4096) return fail(DT_E_ARG, "k must be in [1, 4096]");
+  if (!d_idx || !d_val || !d_count) return fail(DT_E_ARG, "NULL output");
+  if (std::isnan(threshold)) return fail(DT_E_ARG, "threshold is NaN");
+  const size_t need = topk_scratch_bytes(n, k);
+  if (need > NOALLOC_BYTES)
+    return fail(DT_E_ARG, "n = %lld, k = %d needs %zu bytes of top-k scratch; the allocation-free top-k holds %zu",
+                (long long)n, (int)k, need, NOALLOC_BYTES);
+  void* ptr = topk_noalloc_ptr(c->device);
+  if (!ptr) return fail(DT_E_STATE, "the scratch address of device %d was not resolved", c->device);
+  DeviceGuard g(c->device);
+  hipError_t e = launch_topk(d_snr, n, k, threshold, d_idx, d_val, d_count, ptr, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "top-k launch");
+  return DT_OK;
+}
