@@ -1,12 +1,16 @@
 """Benchmark of the plain stack on one MI355X.
 
-A step is one pass of the whole hot path over the survey workload resident
-in HBM: the matched-filter pre-pass over every exposure, the fused stack
-(propagate -> project -> gather -> accumulate) of every orbit over every
-exposure, and the top-k detection.  The metric is dense orbit x exposure
-samples per second.  Prints one JSON line.
+A step is one pass of the whole hot path over a workload resident in HBM:
+the matched-filter pre-pass over every exposure, the fused stack (propagate
+-> project -> gather -> accumulate) of every orbit over every exposure, and
+the top-k detection.  The metric is dense orbit x exposure samples per
+second.  The headline workload is the distant-object set (400 FP16 4096^2
+images plus variance over 365 days, 10^9 candidate orbits at 30-60 AU
+generated on the device inside the stack); the survey set (200 FP32 2048^2
+images, 10^7 stored orbits), the batched patches and the learned proposer
+are measured in blocks of the same line.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload survey|tiny]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload distant|survey|tiny]
 """
 from __future__ import annotations
 
@@ -33,6 +37,14 @@ sys.path.insert(0, ROOT)
 # refinement reciprocal 24, rounding 2.
 FLOPS_PER_SAMPLE = 37
 FLOPS_PER_SOLVE = 125
+# A wavefront whose samples land often leaves the prediction for the
+# per-sample walk: per sample 82 (mean anomaly with the predicted light time
+# 5, warm Kepler step 39, position and raw distance 20, light-time estimate 2,
+# sky-cone test 13, light-time history 3), plus 60 for each sample that takes
+# the full path (light-time correction 23, corrected position 6, projection
+# 24, rounding 2, light time 5).
+FLOPS_PER_TAIL_SAMPLE = 82
+FLOPS_PER_TAIL_FULL = 60
 CK_SPAN_DAYS = 16.0  # the kernel's checkpoint span (epoch days)
 # HBM bytes of one full-size stack launch on the survey workload from the
 # committed FETCH_SIZE / WRITE_SIZE passes; reported only while the kernel's
@@ -59,9 +71,11 @@ def checkpoints(exps):
 def stack_traffic(workload_name):
     import hashlib
     import json as _json
-    if workload_name != "survey" or not os.path.exists(TRAFFIC_RECORD):
+    if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = _json.load(open(TRAFFIC_RECORD))
+    if rec.get("workload", "survey") != workload_name:
+        return None
     h = hashlib.sha256()
     for f in rec["sources"]:
         h.update((hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() + "  " + f + "\n").encode())
@@ -99,46 +113,7 @@ def cpu_baseline(w, gpu_snr, seconds=12.0):
     err = np.abs(gpu_snr[ids] - snr) / np.maximum(1.0, np.abs(snr))
     return dict(value=samples / dt, unit="samples/s", cores=nth, kind="oracle",
                 sample=f"{m2} random orbits x {len(w.exps)} exposures ({samples:.3g} samples, {dt:.1f} s)",
-                snr_max_err=float(err.max()))
-
-
-def gather_yardstick(patch, w, dev, m=None, reps=3):
-    """The stack's own gather stream replayed without the orbit arithmetic, on
-    the first m orbits (default: all of them, the launch the benchmark times):
-    the achievable gather rate of that access pattern."""
-    import torch
-    import paper_2503_08854_amd as dt
-    m = w.elements.shape[0] if m is None else min(m, w.elements.shape[0])
-    sub = dt.OrbitSet(w.elements[:m], w.t0, dev)
-    off = dt.record_gathers(patch, sub, torch.arange(m, device=dev))
-    out = dt.batch_outputs([sub])[0]
-    snr_r = torch.empty(m, dtype=torch.float32, device=dev)
-    dt.stack(patch, sub, out)
-    dt.gather_replay(patch, off, snr_r)
-    torch.cuda.synchronize()
-    same = bool(torch.equal(torch.where(out[2] >= 0, out[0], torch.zeros_like(out[0])), snr_r))
-
-    def timed(fn):
-        ts = []
-        for _ in range(reps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            fn()
-            e1.record()
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        return float(np.median(ts))
-
-    t_stack = timed(lambda: dt.stack(patch, sub, out))
-    t_rep = timed(lambda: dt.gather_replay(patch, off, snr_r))
-    valid = int((off != -1).sum())
-    useful = 8.0 * valid
-    res = dict(orbits=m, valid_samples=valid, dense_samples=m * patch.n_exp, stack_ms=t_stack, replay_ms=t_rep,
-               stack_useful_GBs=useful / (t_stack * 1e-3) / 1e9, replay_useful_GBs=useful / (t_rep * 1e-3) / 1e9,
-               replay_index_stream_GB=4.0 * m * patch.n_exp / 1e9, frac_of_achievable_gather=t_rep / t_stack,
-               replay_equals_stack=same)
-    del off, sub, out, snr_r
-    return res
+                snr_max_err=float(err.max()), snr_p99_err=float(np.percentile(err, 99)))
 
 
 def bench_next_rows(ctx, patch, orb, w, snr, dev, reps=3):
@@ -198,29 +173,45 @@ def bench_next_rows(ctx, patch, orb, w, snr, dev, reps=3):
     return res
 
 
-def bench_batched(dev, steps=5):
+def bench_batched(dev, steps=5, check=True, per_patch=200):
     """The batched-patches workload: 64 uneven FP16 patches, one graph-captured
-    persistent launch (stack + per-patch top-k) after autotuning."""
+    persistent launch (stack + per-patch top-k) after autotuning.  With
+    check, the oracle recomputes per_patch random orbits of every patch and
+    its injection on the same FP16 values (while the images are still
+    resident), and the S/N error of the batched launch is reported."""
     import tempfile
     import torch
+    import oracle
     import paper_2503_08854_amd as dt
     import synth
     geom = synth.load_geometry("batched")
     ctx = dt.Context(0)
-    patches, sets = [], []
+    patches, sets, checks = [], [], []
     t = time.time()
     n_px = 0
-    for pg in geom["patches"]:
+    t_or = 0.0
+    for pi, pg in enumerate(geom["patches"]):
         w = synth.build_workload(pg, device=dev)
         p = dt.Patch(ctx, w.exps, w.D, w.V)
         torch.cuda.synchronize()
+        if check:
+            rng = np.random.default_rng(1000 + pi)
+            n_o = w.elements.shape[0]
+            ids = np.unique(np.r_[rng.choice(n_o, min(per_patch, n_o), replace=False), w.inj_index])
+            D = [d.cpu().numpy() for d in w.D]
+            V = [v.cpu().numpy() for v in w.V]
+            t1 = time.time()
+            so, _, nvo = oracle.stack(w.elements[ids], w.t0, w.exps, D, V)
+            t_or += time.time() - t1
+            checks.append((ids, so, nvo))
+            del D, V
         p.release_images()           # planes stay; the FP16 images are freed
         n_px += sum(x["width"] * x["height"] for x in w.exps)
         patches.append(p)
         sets.append(dt.OrbitSet(w.elements, w.t0, dev))
         del w
     torch.cuda.synchronize()
-    log(f"batched: {len(patches)} patches built ({time.time() - t:.1f} s)")
+    log(f"batched: {len(patches)} patches built ({time.time() - t:.1f} s, oracle {t_or:.1f} s)")
     outs = dt.batch_outputs(sets)
     with tempfile.TemporaryDirectory() as td:
         cfg, ms = dt.autotune_batched(ctx, patches, sets, outs, cache_path=os.path.join(td, "tune.txt"))
@@ -238,6 +229,18 @@ def bench_batched(dev, steps=5):
     res = dict(workload=f"batched: {len(patches)} patches, {sum(p.n_exp for p in patches)} FP16 exposures, "
                         f"{sum(o.n for o in sets)} orbits", samples=samples, ms_per_step=ms_step,
                samples_per_s=samples / (ms_step * 1e-3), cfg={"chunk": cfg[0], "wg_per_cu": cfg[1]}, pixels=n_px)
+    if check:
+        g_all, o_all, nv_diff = [], [], 0
+        for (ids, so, nvo), o in zip(checks, outs):
+            sel = torch.as_tensor(ids, device=dev)
+            g_all.append(o[0][sel].cpu().numpy())
+            o_all.append(so)
+            nv_diff += int((o[2][sel].cpu().numpy() != nvo).sum())
+        res["snr_error_vs_oracle"] = dict(snr_errors(np.concatenate(g_all), np.concatenate(o_all)),
+                                          nvalid_differences=nv_diff, images="the same FP16 values",
+                                          sample=f"{per_patch} random orbits and the injection of every patch")
+        log(f"batched: S/N error vs oracle max {res['snr_error_vs_oracle']['max']:.3g}, "
+            f"p99 {res['snr_error_vs_oracle']['p99']:.3g}, n_valid differences {nv_diff}")
     for p in patches:
         p.close()
     ctx.close()
@@ -277,36 +280,259 @@ def bench_learned(dev, n_train=100, n_eval=50, budget=0.02, budget_wide=0.05, n_
     return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="survey")
-    ap.add_argument("--k", type=int, default=100)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--probe-copy", action="store_true",
-                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
-    ap.add_argument("--skip-batched", action="store_true")
-    ap.add_argument("--skip-learned", action="store_true")
-    ap.add_argument("--skip-gather", action="store_true")
-    ap.add_argument("--skip-next", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the stack would shard by orbit, "
-              f"but no multi-GPU path is implemented", file=sys.stderr)
-        sys.exit(2)
+def timed_steps(step, steps, warmup, n_ev):
+    """warmup untimed steps, then `steps` timed ones bracketed by synchronisations;
+    every step records n_ev events (phase boundaries) on the current stream."""
+    import torch
+    for i in range(warmup):
+        step(None)
+        log(f"warmup {i + 1}/{warmup}")
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(n_ev)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    res = None
+    for i in range(steps):
+        res = step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    phases = [float(np.mean([e[j].elapsed_time(e[j + 1]) for e in evs])) for j in range(n_ev - 1)]
+    return wall, phases, res
+
+
+def counted_work(ctx, launch):
+    """Run one more launch with the kernel's work counters on; returns the
+    counts and the FP64 flops they imply."""
+    import torch
+    ctx.count_work(True)
+    launch()
+    w = ctx.work()
+    ctx.count_work(False)
+    torch.cuda.synchronize()
+    flops = (FLOPS_PER_SAMPLE * w["predicted"] + FLOPS_PER_SOLVE * (w["queued_solves"] + w["checkpoint_solves"])
+             + FLOPS_PER_TAIL_SAMPLE * w["tail_samples"] + FLOPS_PER_TAIL_FULL * w["tail_full"])
+    return w, flops
+
+
+def roofline_block(kernel, ms, n_orbits, n_exp, valid, flops, stored, traffic):
+    """Both rooflines of the dominant kernel.  HBM: algorithmic bytes = 8 B per
+    valid sample (the psi, phi gather) + 12 B of outputs per orbit + 48 B of
+    elements per stored orbit + 208 B per exposure record.  FP64: the
+    kernel's own flop count.  The block's top level is the one nearer its
+    peak."""
+    nbytes = 8.0 * valid + (12.0 + (48.0 if stored else 0.0)) * n_orbits + 208.0 * n_exp
+    hbm = dict(bound="hbm", achieved=nbytes / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+               algorithmic_bytes=nbytes, traffic=traffic)
+    hbm["frac"] = hbm["achieved"] / HBM_PEAK_GBS
+    alu = dict(bound="alu", achieved=flops / (ms * 1e-3) / 1e12, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+               algorithmic_flops=flops)
+    alu["frac"] = alu["achieved"] / FP64_PEAK_TFLOPS
+    top, other = (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
+    out = dict(top)
+    out.setdefault("traffic", traffic)
+    out.update(kernel=kernel, kernel_ms=ms, other=other)
+    return out
+
+
+def snr_errors(gpu, ora):
+    err = np.abs(np.asarray(gpu, np.float64) - ora) / np.maximum(1.0, np.abs(ora))
+    return dict(max=float(err.max()), p99=float(np.percentile(err, 99)), n=int(err.size))
+
+
+def oracle_generated(gs, ids):
+    """Elements of grid orbits `ids` from the oracle's own generator."""
+    import math
+    from oracle import generate as G
+    f = gs["field"]
+    So = dict(center=f["center"], east=f["east"], north=f["north"], obs=f["obs"], half_w=f["half_w"],
+              half_h=f["half_h"], a=tuple(gs["a"]), e=tuple(gs["e"]),
+              inc=tuple(math.radians(v) for v in gs["inc_deg"]), seed=int(gs["seed"]), epoch=gs["epoch"])
+    return np.array([G.sample_orbit(So, int(j)) for j in ids], dtype=np.float64)
+
+
+def bench_distant(args, dev):
+    """Headline: the distant-object workload, orbits generated inside the stack."""
+    import torch
+    import synth
+    import oracle
+    import paper_2503_08854_amd as dt
+    geom = synth.load_geometry("distant")
+    gs = synth.grid_sampler(geom)
+    t = time.time()
+    w = synth.build_workload(geom, device=dev)
+    torch.cuda.synchronize()
+    log(f"workload distant: {len(w.exps)} exposures 4096^2 FP16, {gs['n']} generated orbits ({time.time() - t:.1f} s)")
+    ctx = dt.Context(0)
+    patch = dt.Patch(ctx, w.exps, w.D, w.V)
+    S = dt.orbit_sampler(gs["field"], gs["epoch"], gs["a"], gs["e"], gs["inc_deg"], gs["seed"])
+    n, ne = gs["n"], patch.n_exp
+    out = (torch.empty(n, dtype=torch.float32, device=dev), torch.empty(n, dtype=torch.float32, device=dev),
+           torch.empty(n, dtype=torch.int32, device=dev))
+    torch.cuda.synchronize()
+
+    def step(ev):
+        if ev is not None:
+            ev[0].record()
+        patch.refresh()
+        if ev is not None:
+            ev[1].record()
+        dt.stack_generated(patch, S, 0, n, out)
+        if ev is not None:
+            ev[2].record()
+        r = dt.topk(ctx, out[0], args.k, 5.0)
+        if ev is not None:
+            ev[3].record()
+        return r
+
+    steps = args.steps if args.steps is not None else 5
+    warmup = args.warmup if args.warmup is not None else 1
+    wall, (pre, stk, tk), res = timed_steps(step, steps, warmup, 4)
+    log(f"timed {steps} steps: {wall:.3f} s; prepass {pre:.3f} ms, stack {stk:.3f} ms, topk {tk:.3f} ms")
+    samples = n * ne
+    nv = out[2]
+    valid = int(nv.clamp(min=0).sum(dtype=torch.int64))
+    work, flops = counted_work(ctx, lambda: dt.stack_generated(patch, S, 0, n, out))
+    idx, val, cnt = (x.cpu().numpy() for x in res)
+    inj = w.inj_index
+    inj_snr = out[0][torch.as_tensor(inj, device=dev)].cpu().numpy()
+    rec = {
+        "metric": "orbit x exposure samples/s",
+        "value": samples * steps / wall,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"distant: {ne} exposures 4096x4096 f16 + variance over 365 days, "
+                               f"{n} candidate orbits (a 30-60 AU) generated in the stack, top-{args.k} at S/N>=5",
+                   "orbits": n, "exposures": ne, "valid_samples": valid, "valid_frac": valid / samples,
+                   "phase_ms": {"prepass": pre, "stack": stk, "topk": tk}},
+        "roofline": roofline_block("k_stack_generated_track", stk, n, ne, valid, flops, False,
+                                   stack_traffic("distant")),
+        "work": work,
+        "detections": int(cnt[0]),
+        "injections": {"n": int(len(inj)), "recovered_snr5": int((inj_snr >= 5).sum())},
+    }
+    r = rec["roofline"]
+    log(f"roofline: {r['bound']} {r['frac']:.3f} ({r['achieved']:.3g} {r['unit']}); "
+        f"{r['other']['bound']} {r['other']['frac']:.3f}")
+    if not args.no_cpu:
+        D = [d.cpu().numpy() for d in w.D]
+        V = [v.cpu().numpy() for v in w.V]
+        rng = np.random.default_rng(123)
+        # the oracle on a bounded random sample: first a probe to size it to ~12 s
+        ids = np.sort(rng.choice(n, 300, replace=False))
+        el = oracle_generated(gs, ids)
+        t = time.time()
+        oracle.stack(el, w.t0, w.exps, D, V)
+        dt_probe = max(time.time() - t, 1e-3)
+        m = int(min(200000, max(300, 300 * 12.0 / dt_probe)))
+        ids = np.unique(np.r_[np.sort(rng.choice(n, m, replace=False)), inj, idx[:int(cnt[0])]])
+        el = oracle_generated(gs, ids)
+        t = time.time()
+        so, fo, nvo = oracle.stack(el, w.t0, w.exps, D, V)
+        dt_o = time.time() - t
+        sel = torch.as_tensor(ids, device=dev)
+        g_snr, g_nv = out[0][sel].cpu().numpy(), nv[sel].cpu().numpy()
+        rec["cpu_baseline"] = dict(value=ids.size * ne / dt_o, unit="samples/s", cores=oracle.max_threads(),
+                                   kind="oracle",
+                                   sample=f"{ids.size} orbits (random, the injections and the top-{args.k}) x {ne} "
+                                          f"exposures ({ids.size * ne:.3g} samples, {dt_o:.1f} s)")
+        rec["snr_error_vs_oracle"] = dict(snr_errors(g_snr, so), nvalid_differences=int((g_nv != nvo).sum()),
+                                          images="the same FP16 values")
+        log(f"cpu baseline: {rec['cpu_baseline']['value']:.3g} samples/s on {rec['cpu_baseline']['cores']} threads; "
+            f"S/N error max {rec['snr_error_vs_oracle']['max']:.3g}")
+        rec["fp16_storage_error"] = fp16_storage_error(geom, w, gs, D, V, ids[:2000], so[:2000], dev)
+        del D, V
+    if not args.skip_gather:
+        rec["gather"] = dict(distant=gather_yardstick_generated(patch, S, gs, dev))
+    patch.close()
+    ctx.close()
+    del w, out, patch
+    torch.cuda.empty_cache()
+    return rec
+
+
+def fp16_storage_error(geom, w, gs, D16, V16, ids, snr16, dev):
+    """S/N of the oracle on the FP16-stored images vs on the FP32 values they
+    were rounded from (same seeds), for a sample of orbits."""
+    import torch
+    import synth
+    import oracle
+    g32 = dict(geom)
+    g32["dtype"] = "f32"
+    w32 = synth.build_workload(g32, device=dev)
+    D32 = [d.cpu().numpy() for d in w32.D]
+    V32 = [v.cpu().numpy() for v in w32.V]
+    del w32
+    torch.cuda.empty_cache()
+    el = oracle_generated(gs, ids)
+    s32, _, _ = oracle.stack(el, w.t0, w.exps, D32, V32)
+    del D32, V32
+    e = snr_errors(snr16, s32)
+    log(f"FP16 storage: S/N error vs the FP32 values max {e['max']:.3g}, p99 {e['p99']:.3g}")
+    return e
+
+
+def gather_yardstick_generated(patch, S, gs, dev, m=10_000_000):
+    """Achievable gather rate of the generated stack's own valid gathers
+    (first m orbits): the stack of those orbits vs a replay of exactly their
+    gathers without the orbit arithmetic."""
     import torch
     import paper_2503_08854_amd as dt
+    ctx = patch.ctx
+    el = dt.generate_orbits(ctx, S, 0, m)
+    sub = dt.OrbitSet(el, gs["epoch"], dev)
+    del el
+    return _yardstick(patch, sub, lambda o: dt.stack_generated(patch, S, 0, m, o), dev)
 
-    dev = torch.device("cuda:0")
-    if args.probe_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    w = workload(args.workload, dev)
+
+def _yardstick(patch, sub, stack_fn, dev, reps=3):
+    import torch
+    import paper_2503_08854_amd as dt
+    m = sub.n
+    rec = dt.record_valid_gathers(patch, sub)
+    out = dt.batch_outputs([sub])[0]
+    snr_r = torch.empty(m, dtype=torch.float32, device=dev)
+    stack_fn(out)
+    dt.replay_valid_gathers(patch, rec, snr_r)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(torch.where(out[2] > 0, out[0], torch.zeros_like(out[0])), snr_r))
+
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    t_stack = timed(lambda: stack_fn(out))
+    t_rep = timed(lambda: dt.replay_valid_gathers(patch, rec, snr_r))
+    valid = int(rec.count)
+    useful = 8.0 * valid
+    res = dict(orbits=m, valid_samples=valid, dense_samples=m * patch.n_exp, stack_ms=t_stack, replay_ms=t_rep,
+               stack_useful_GBs=useful / (t_stack * 1e-3) / 1e9, replay_useful_GBs=useful / (t_rep * 1e-3) / 1e9,
+               replay_index_bytes=float(rec.index_bytes), frac_of_achievable_gather=t_rep / t_stack,
+               replay_equals_stack=same)
+    log(f"gather yardstick: stack {t_stack:.3f} ms vs replay {t_rep:.3f} ms on {m} orbits, {valid} valid gathers "
+        f"({t_rep / t_stack:.2f} of the achievable gather rate)")
+    del rec, out, snr_r
+    return res
+
+
+def bench_survey(args, dev, name="survey", steps=10, warmup=2, with_next=True, with_gather=True):
+    """The survey workload (stored orbits): pre-pass + stack + top-k per step."""
+    import torch
+    import paper_2503_08854_amd as dt
+    w = workload(name, dev)
     ctx = dt.Context(0)
     patch = dt.Patch(ctx, w.exps, w.D, w.V)
     orb = dt.OrbitSet(w.elements, w.t0, dev)
@@ -315,7 +541,7 @@ def main():
            torch.empty(n, dtype=torch.int32, device=dev))
     torch.cuda.synchronize()
 
-    def step(ev=None):
+    def step(ev):
         if ev is not None:
             ev[0].record()
         patch.refresh()
@@ -329,76 +555,95 @@ def main():
             ev[3].record()
         return r
 
-    for i in range(args.warmup):
-        step()
-        log(f"warmup {i + 1}/{args.warmup}")
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        res = step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    pre = np.mean([e[0].elapsed_time(e[1]) for e in evs])
-    stk = np.mean([e[1].elapsed_time(e[2]) for e in evs])
-    tk = np.mean([e[2].elapsed_time(e[3]) for e in evs])
-    log(f"timed {args.steps} steps: {wall:.3f} s; prepass {pre:.3f} ms, stack {stk:.3f} ms, topk {tk:.3f} ms")
+    wall, (pre, stk, tk), res = timed_steps(step, steps, warmup, 4)
+    log(f"{name}: {steps} steps {wall:.3f} s; prepass {pre:.3f} ms, stack {stk:.3f} ms, topk {tk:.3f} ms")
     samples = n * ne
-    value = samples * args.steps / wall
     snr = out[0].cpu().numpy()
     nv = out[2].cpu().numpy()
     idx, val, cnt = (x.cpu().numpy() for x in res)
     valid = int(nv[nv > 0].sum())
-    n_ck = checkpoints(w.exps)
-    achieved = (FLOPS_PER_SAMPLE * samples + FLOPS_PER_SOLVE * (valid + n * n_ck)) / (stk * 1e-3) / 1e12
-    rec = {
-        "metric": "orbit x exposure samples/s",
-        "value": value,
-        "unit": "samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {ne} exposures "
-                               f"{w.exps[0]['width']}x{w.exps[0]['height']} {w.dtype} + variance, "
-                               f"{n} orbits, top-{args.k} at S/N>=5",
-                   "orbits": n, "exposures": ne, "valid_samples": valid,
-                   "phase_ms": {"prepass": pre, "stack": stk, "topk": tk}},
-        "roofline": {"bound": "alu", "kernel": "k_stack_track", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": stack_traffic(args.workload),
-                     "flops_per_sample": FLOPS_PER_SAMPLE, "flops_per_solve": FLOPS_PER_SOLVE,
-                     "solves": valid + n * n_ck},
-        "detections": int(cnt[0]),
-    }
+    work, flops = counted_work(ctx, lambda: dt.stack(patch, orb, out))
+    rec = dict(workload=f"{name}: {ne} exposures {w.exps[0]['width']}x{w.exps[0]['height']} {w.dtype} + variance, "
+                        f"{n} stored orbits, top-{args.k} at S/N>=5",
+               value=samples * steps / wall, unit="samples/s", steps=steps, warmup=warmup,
+               ms_per_step=wall / steps * 1e3, orbits=n, exposures=ne, valid_samples=valid,
+               phase_ms={"prepass": pre, "stack": stk, "topk": tk},
+               roofline=roofline_block("k_stack_track", stk, n, ne, valid, flops, True, stack_traffic(name)),
+               work=work, detections=int(cnt[0]))
     inj = w.inj_index
     if len(inj):
         rec["injections"] = {"n": int(len(inj)), "recovered_snr5": int((snr[inj] >= 5).sum())}
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        rec["cpu_baseline"] = cpu_baseline(w, snr)
-        log(f"cpu baseline: {rec['cpu_baseline']['value']:.3g} samples/s on {rec['cpu_baseline']['cores']} threads")
-    if not args.skip_next:
+        cb = cpu_baseline(w, snr)
+        rec["snr_error_vs_oracle"] = dict(max=cb.pop("snr_max_err"), p99=cb.pop("snr_p99_err"))
+        rec["cpu_baseline"] = cb
+    if with_next and not args.skip_next:
         rec["next_rows"] = bench_next_rows(ctx, patch, orb, w, snr, dev)
         N = rec["next_rows"]
         log(f"next rows: noise {N['noise']['ms']:.2f} ms ({N['noise']['achieved_GBs']:.0f} GB/s), generation "
             f"{N['generation']['orbits_per_s']:.3g} orbits/s, generate+stack {N['generation']['generate_and_stack_ms']:.2f} "
             f"ms vs stack {N['generation']['stack_ms']:.2f} ms, trimming {N['outlier_trimming']['ms']:.3f} ms")
-    if not args.skip_gather:
-        rec["gather"] = gather_yardstick(patch, w, dev)
-        G = rec["gather"]
-        log(f"gather yardstick: stack {G['stack_ms']:.3f} ms vs replay {G['replay_ms']:.3f} ms on {G['orbits']} "
-            f"orbits ({G['frac_of_achievable_gather']:.2f} of the achievable gather rate)")
+    if with_gather and not args.skip_gather:
+        rec["gather"] = _yardstick(patch, orb, lambda o: dt.stack(patch, orb, o), dev)
     patch.close()
     ctx.close()
     del w, orb, out, patch
     torch.cuda.empty_cache()
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="distant", choices=["distant", "survey", "tiny"])
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline workload's block")
+    ap.add_argument("--skip-survey", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-learned", action="store_true")
+    ap.add_argument("--skip-gather", action="store_true")
+    ap.add_argument("--skip-next", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the stack would shard by orbit, "
+              f"but no multi-GPU path is implemented", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    dev = torch.device("cuda:0")
+    if args.probe_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.workload == "distant":
+        rec = bench_distant(args, dev)
+    else:
+        s = bench_survey(args, dev, args.workload, steps=args.steps or 10,
+                         warmup=args.warmup if args.warmup is not None else 2)
+        rec = {"metric": "orbit x exposure samples/s", "value": s.pop("value"), "unit": "samples/s", "n_gpus": 1,
+               "steps": s.pop("steps"), "warmup": s.pop("warmup"), "ms_per_step": s.pop("ms_per_step"),
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic", "config": {"workload": s.pop("workload"), "orbits": s.pop("orbits"),
+                                               "exposures": s.pop("exposures"),
+                                               "valid_samples": s.pop("valid_samples"),
+                                               "phase_ms": s.pop("phase_ms")}}
+        rec.update(s)
+    if args.headline_only:
+        print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "distant" and not args.skip_survey:
+        rec["survey"] = bench_survey(args, dev)
+        log(f"survey: {rec['survey']['value']:.3g} samples/s")
     if not args.skip_batched:
-        rec["batched"] = bench_batched(dev)
+        rec["batched"] = bench_batched(dev, check=not args.no_cpu)
         log(f"batched: {rec['batched']['samples_per_s']:.3g} samples/s")
         torch.cuda.empty_cache()
     if not args.skip_learned:

@@ -95,6 +95,24 @@ dt_status dt_ctx_mem_used(dt_ctx *ctx, size_t *out);
 /* Destroy the context; its patches must be destroyed first (DT_E_STATE otherwise). */
 dt_status dt_ctx_destroy(dt_ctx *ctx);
 
+/* Work counters (measurement, no paper counterpart).  While counting is on
+ * (on != 0; turning it on zeroes the counters), every stack launch of the
+ * context that runs the checkpoint walk (dt_stack, dt_stack_generated,
+ * dt_stack_batched, dt_stack_cells) adds what it did.  dt_ctx_work
+ * synchronises the context stream, writes the totals since the last read
+ * (out, host, DT_WORK_COUNTERS values) and zeroes them:
+ *   out[0] samples tested by the checkpoint prediction (live orbit x exposure)
+ *   out[1] queued samples solved exactly   out[2] checkpoint solves
+ *   out[3] samples walked by the per-sample tail after a wavefront switched
+ *   out[4] tail samples that took the full path (light time and projection)
+ *   out[5] wavefronts that switched        out[6..7] 0
+ * Launches captured into a graph count on every replay while counting was
+ * on at capture time.  Counting costs atomics per wavefront; leave it off
+ * when timing. */
+#define DT_WORK_COUNTERS 8
+dt_status dt_ctx_count_work(dt_ctx *ctx, int32_t on);
+dt_status dt_ctx_work(dt_ctx *ctx, uint64_t *out);
+
 /* Build a patch: n_exp exposures (host array `exps`) with their flux and
  * variance images (host arrays of n_exp device pointers, each a row-major
  * height x width image of `dtype`).  Enqueues the exposure-metadata kernel
@@ -233,18 +251,26 @@ dt_status dt_autotune_batched(dt_ctx *ctx, dt_patch *const *patches, const dt_or
 dt_status dt_patch_release_images(dt_patch *p);
 
 /* Measurement yardstick for the stack's gathers (no paper counterpart).
- * dt_record_gathers writes, for m orbits (device int64 ids), the plane
- * offset (uint32, float2 units) of every valid sample the stack would
- * gather, laid out [exposure in epoch order][m], ~0u where a sample is not
- * valid (device, n_exp * m entries; patches whose planes hold < 2^32 - 1
- * elements).  dt_gather_replay then loads those offsets' (psi, phi) in the
- * same order and sums them as dt_stack does (d_snr, device, m floats,
- * equal to dt_stack's S/N on those orbits), with none of the orbit
- * arithmetic: its rate is the achievable gather rate of the same access
- * stream.  Both enqueue on the context stream. */
-dt_status dt_record_gathers(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, int64_t m,
-                            uint32_t *d_off);
-dt_status dt_gather_replay(dt_patch *p, const uint32_t *d_off, int64_t m, float *d_snr);
+ * dt_record_gathers records, for orbits 0 .. n - 1 of `orbits`, the global
+ * plane offset (float2 units, int64) of every sample that lands inside an
+ * image -- the gathers dt_stack makes -- in epoch order per orbit.  Orbits
+ * are taken in groups of 64 (one wavefront's lanes); group g has width w_g =
+ * the largest count among its orbits and holds its entries slot-major:
+ * entry k of lane l at d_list[d_start[g] + 64 k + l], -1 past that orbit's
+ * count; d_start[g] = 64 (w_0 + ... + w_{g-1}), g = 0 .. ceil(n / 64).
+ * Two calls: with d_list == NULL it counts, writes d_start (device,
+ * ceil(n / 64) + 1 int64) and the host values *h_entries (= d_start's last
+ * entry, the list length) and *h_gathers (the number of recorded gathers;
+ * may be NULL), and synchronises; then, with the same d_start and a device
+ * d_list of *h_entries int64, it records (enqueued, no synchronisation).
+ * dt_gather_replay loads those offsets' (psi, phi) -- eight loads in flight
+ * per lane, no orbit arithmetic -- and sums them in order exactly as
+ * dt_stack does (d_snr, device, n floats: equal to dt_stack's S/N of every
+ * orbit with n_valid > 0, 0 otherwise).  Its rate is the achievable gather
+ * rate of the stack's own access stream. */
+dt_status dt_record_gathers(dt_patch *p, const dt_orbits *orbits, int64_t *d_start, int64_t *d_list,
+                            int64_t *h_entries, int64_t *h_gathers);
+dt_status dt_gather_replay(dt_patch *p, const int64_t *d_start, const int64_t *d_list, int64_t n, float *d_snr);
 
 /* Candidate-orbit distribution for on-device sampling (Algorithm 1,
  * GenerateOrbits): a, e, i uniform in their ranges (AU, -, radians); a line
@@ -362,15 +388,31 @@ dt_status dt_scorer_grad(dt_scorer *s, const uint16_t *d_stamps, const uint16_t 
 dt_status dt_scorer_train_step(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats,
                                const float *d_labels, int32_t B, float lr, float *d_loss);
 
-/* Per-sample table for m selected orbits (device int64 ids into `orbits`),
- * computed by the same device code and in the same order as dt_stack.
- * Outputs (device, m x n_exp each, exposures in caller order; any may be NULL):
+/* Per-sample table for m selected orbits (device int64 ids into `orbits`)
+ * from the exact per-sample walk: every sample propagated with light time,
+ * projected and gathered by the device functions the stack kernels use
+ * (Sec. 3 SearchImages + FilterGPUIntersections, Algorithm 1), with no
+ * pruning.  Outputs (device, m x n_exp each, exposures in caller order; any
+ * may be NULL):
  *   px, py  0-based pixel coordinates (FP64), ix, iy nearest pixel,
- *   flags   bit0 in front, bit1 inside image, bit2 valid (phi > 0),
- *   psi, phi the gathered plane values (0 when not valid), tau light time (days). */
+ *   flags   bit0 in front, bit1 inside image, bit2 valid (phi > 0), bit3 solved
+ *           (always set here),
+ *   psi, phi the gathered plane values (0 when not valid), tau light time (days).
+ * An id outside [0, orbits->n) or an orbit outside the domain gets the
+ * initial row: flags 0, NaN coordinates and light time, ix = iy = INT32_MIN. */
 dt_status dt_debug_samples(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, int64_t m,
                            double *d_px, double *d_py, int32_t *d_ix, int32_t *d_iy,
                            int32_t *d_flags, float *d_psi, float *d_phi, double *d_tau);
+/* The same table from the walk dt_stack itself runs on this patch (the
+ * checkpoint walk with its queue, and the per-sample tail it may switch to;
+ * or, for patches without an observer speed bound, the per-sample walk with
+ * its sky-cone test): only the samples that walk solves exactly carry
+ * flags bit3 and their px, py, ix, iy, tau, psi, phi; the samples its bounds
+ * exclude keep the initial row values.  Every sample that lands in an image
+ * is among the solved ones. */
+dt_status dt_debug_stack_samples(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, int64_t m,
+                                 double *d_px, double *d_py, int32_t *d_ix, int32_t *d_iy,
+                                 int32_t *d_flags, float *d_psi, float *d_phi, double *d_tau);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@ functions raises.
 from .binding import (  # noqa: F401
     DtrackError, Context, Patch, OrbitSet, lib, stack, topk, debug_samples, validate_orbits,
     exposure_struct, LIB_PATH, stack_batched, autotune_batched, batch_outputs, cell_stamps, stack_cells,
-    gemm_bf16, Scorer, clip_candidates, image_noise, record_gathers, gather_replay, orbit_sampler, generate_orbits,
+    gemm_bf16, Scorer, clip_candidates, image_noise, record_valid_gathers, replay_valid_gathers, GatherRecord,
+    orbit_sampler, generate_orbits,
     stack_generated, topk_noalloc,
 )

@@ -69,6 +69,8 @@ def lib():
         "dt_ctx_set_mem_limit": ([_P, C.c_size_t], C.c_int),
         "dt_ctx_mem_used": ([_P, C.POINTER(C.c_size_t)], C.c_int),
         "dt_ctx_destroy": ([_P], C.c_int),
+        "dt_ctx_count_work": ([_P, C.c_int32], C.c_int),
+        "dt_ctx_work": ([_P, C.POINTER(C.c_uint64)], C.c_int),
         "dt_patch_create": ([_P, C.POINTER(DtExposure), C.c_int32, C.POINTER(_P), C.POINTER(_P), C.c_int,
                              C.POINTER(_P)], C.c_int),
         "dt_patch_refresh": ([_P], C.c_int),
@@ -89,8 +91,11 @@ def lib():
         "dt_cell_stamps": ([_P, C.POINTER(DtOrbits), C.c_double, C.c_double, _P, _P, _P, _P], C.c_int),
         "dt_image_noise": ([_P, C.c_int32, _P, _P, C.c_int, C.c_double, C.c_int32, _P, _P, _P], C.c_int),
         "dt_patch_noise": ([_P, _P], C.c_int),
-        "dt_record_gathers": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P], C.c_int),
-        "dt_gather_replay": ([_P, _P, C.c_int64, _P], C.c_int),
+        "dt_record_gathers": ([_P, C.POINTER(DtOrbits), _P, _P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+                              C.c_int),
+        "dt_gather_replay": ([_P, _P, _P, C.c_int64, _P], C.c_int),
+        "dt_debug_stack_samples": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P],
+                                   C.c_int),
         "dt_scorer_infer": ([_P, _P, _P, C.c_int32, _P], C.c_int),
         "dt_generate_orbits": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P],
                                C.c_int),
@@ -173,6 +178,18 @@ class Context:
         v = C.c_size_t()
         _check(lib().dt_ctx_mem_used(self._h, C.byref(v)))
         return v.value
+
+    WORK_KEYS = ("predicted", "queued_solves", "checkpoint_solves", "tail_samples", "tail_full", "switched_waves")
+
+    def count_work(self, on: bool = True):
+        """Turn the stack kernels' work counters on (zeroed) or off."""
+        _check(lib().dt_ctx_count_work(self._h, 1 if on else 0))
+
+    def work(self) -> dict:
+        """Work counted since the last read (synchronises; zeroes the counters)."""
+        out = (C.c_uint64 * 8)()
+        _check(lib().dt_ctx_work(self._h, out))
+        return {k: int(out[i]) for i, k in enumerate(self.WORK_KEYS)}
 
     def close(self):
         if self._h:
@@ -331,8 +348,10 @@ def topk_noalloc(ctx: Context, snr, idx, val, cnt, k: int, threshold: float = fl
     return idx, val, cnt
 
 
-def debug_samples(patch: Patch, orbits: OrbitSet, ids):
-    """Per-sample table (m x n_exp, caller exposure order) computed by the stack's device code."""
+def debug_samples(patch: Patch, orbits: OrbitSet, ids, walk: str = "exact"):
+    """Per-sample table (m x n_exp, caller exposure order): walk="exact" is the
+    exact per-sample walk (dt_debug_samples), walk="stack" the walk dt_stack
+    runs, recording only the samples it solves (dt_debug_stack_samples)."""
     import torch
     dev = orbits.soa.device
     ids = torch.as_tensor(ids, dtype=torch.int64).to(dev)
@@ -346,9 +365,9 @@ def debug_samples(patch: Patch, orbits: OrbitSet, ids):
              phi=torch.empty((m, n), dtype=torch.float32, device=dev),
              tau=torch.empty((m, n), dtype=torch.float64, device=dev))
     s = orbits.struct()
-    _check(lib().dt_debug_samples(patch.handle, C.byref(s), _ptr(ids), m, _ptr(o["px"]), _ptr(o["py"]),
-                                  _ptr(o["ix"]), _ptr(o["iy"]), _ptr(o["flags"]), _ptr(o["psi"]), _ptr(o["phi"]),
-                                  _ptr(o["tau"])))
+    fn = {"exact": lib().dt_debug_samples, "stack": lib().dt_debug_stack_samples}[walk]
+    _check(fn(patch.handle, C.byref(s), _ptr(ids), m, _ptr(o["px"]), _ptr(o["py"]), _ptr(o["ix"]), _ptr(o["iy"]),
+              _ptr(o["flags"]), _ptr(o["psi"]), _ptr(o["phi"]), _ptr(o["tau"])))
     return o
 
 
@@ -405,23 +424,40 @@ def autotune_batched(ctx: Context, patches, orbit_sets, outs=None, cache_path=No
     return (best.chunk, best.wg_per_cu), ms.value
 
 
-def record_gathers(patch: Patch, orbits: OrbitSet, ids):
-    """Plane offsets of the stack's valid gathers for orbits `ids`: (n_exp, m) int32 view of uint32 (-1 = none)."""
-    import torch
-    ids = torch.as_tensor(ids, dtype=torch.int64).to(patch.device)
-    m = int(ids.numel())
-    off = torch.empty((patch.n_exp, m), dtype=torch.int32, device=patch.device)
-    _check(lib().dt_record_gathers(patch.handle, C.byref(orbits.struct()), _ptr(ids), m, _ptr(off)))
-    return off
+class GatherRecord:
+    """The stack's gathers of an orbit set (dt_record_gathers): group starts,
+    the slot-major offset list, and the number of recorded gathers."""
+
+    def __init__(self, start, lst, count):
+        self.start, self.list, self.count = start, lst, count
+        self.n = 0
+
+    @property
+    def index_bytes(self):
+        return 8 * int(self.list.numel())
 
 
-def gather_replay(patch: Patch, off, snr=None):
-    """Replay a recorded gather stream; returns the S/N (equal to the stack's on those orbits)."""
+def record_valid_gathers(patch: Patch, orbits: OrbitSet):
+    """Record the plane offsets of every gather the stack makes for `orbits`."""
     import torch
-    m = int(off.shape[1])
+    n = orbits.n
+    start = torch.empty((n + 63) // 64 + 1, dtype=torch.int64, device=patch.device)
+    entries, gathers = C.c_int64(), C.c_int64()
+    s = orbits.struct()
+    _check(lib().dt_record_gathers(patch.handle, C.byref(s), _ptr(start), None, C.byref(entries), C.byref(gathers)))
+    lst = torch.empty(max(entries.value, 1), dtype=torch.int64, device=patch.device)
+    _check(lib().dt_record_gathers(patch.handle, C.byref(s), _ptr(start), _ptr(lst), C.byref(entries), None))
+    rec = GatherRecord(start, lst, gathers.value)
+    rec.n = n
+    return rec
+
+
+def replay_valid_gathers(patch: Patch, rec: GatherRecord, snr=None):
+    """Replay a recorded gather stream; returns the S/N (the stack's where n_valid > 0, else 0)."""
+    import torch
     if snr is None:
-        snr = torch.empty(m, dtype=torch.float32, device=patch.device)
-    _check(lib().dt_gather_replay(patch.handle, _ptr(off), m, _ptr(snr)))
+        snr = torch.empty(rec.n, dtype=torch.float32, device=patch.device)
+    _check(lib().dt_gather_replay(patch.handle, _ptr(rec.start), _ptr(rec.list), rec.n, _ptr(snr)))
     return snr
 
 
@@ -472,11 +508,15 @@ def generate_orbits(ctx: Context, sampler, first: int, n: int):
     return soa.t()
 
 
-def stack_generated(patch: Patch, sampler, first: int, n: int):
+def stack_generated(patch: Patch, sampler, first: int, n: int, out=None):
+    """dt_stack_generated: (S/N, flux, n_valid) of orbits first .. first + n - 1
+    of the sampler; out = caller-provided (float32, float32, int32) tensors."""
     import torch
-    snr = torch.empty(n, dtype=torch.float32, device=patch.device)
-    flux = torch.empty(n, dtype=torch.float32, device=patch.device)
-    nv = torch.empty(n, dtype=torch.int32, device=patch.device)
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float32, device=patch.device),
+               torch.empty(n, dtype=torch.float32, device=patch.device),
+               torch.empty(n, dtype=torch.int32, device=patch.device))
+    snr, flux, nv = out
     _check(lib().dt_stack_generated(patch.handle, C.byref(sampler), int(first), int(n), _ptr(snr), _ptr(flux),
                                     _ptr(nv)))
     return snr, flux, nv

@@ -117,6 +117,7 @@ StackArgs stack_args(const dt_patch* p, const dt_orbits* o) {
   a.flux = nullptr;
   a.nvalid = nullptr;
   a.vobs = p->vobs;
+  a.work = p->ctx->count_work ? p->ctx->d_work : nullptr;
   return a;
 }
 
@@ -192,8 +193,42 @@ dt_status dt_ctx_destroy(dt_ctx* c) {
   ctx_free(c, c->topk_scratch, c->topk_bytes);
   ctx_free(c, c->noise_ws, c->noise_bytes);
   ctx_free(c, c->d_counter, sizeof(unsigned long long));
+  ctx_free(c, c->d_work, sizeof(unsigned long long) * WORK_SLOTS * WORK_N);
   c->alive = false;
   delete c;
+  return DT_OK;
+}
+
+dt_status dt_ctx_count_work(dt_ctx* c, int32_t on) {
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  DeviceGuard g(c->device);
+  const size_t bytes = sizeof(unsigned long long) * WORK_SLOTS * WORK_N;
+  if (on && !c->d_work) {
+    dt_status st = ctx_alloc(c, reinterpret_cast<void**>(&c->d_work), bytes, "work counters");
+    if (st != DT_OK) return st;
+  }
+  if (on) {
+    hipError_t e = hipMemsetAsync(c->d_work, 0, bytes, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "work counter reset");
+  }
+  c->count_work = on != 0;
+  return DT_OK;
+}
+
+dt_status dt_ctx_work(dt_ctx* c, uint64_t* out) {
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  if (!out) return fail(DT_E_ARG, "out is NULL");
+  for (int k = 0; k < DT_WORK_COUNTERS; ++k) out[k] = 0;
+  if (!c->d_work) return DT_OK;
+  DeviceGuard g(c->device);
+  std::vector<unsigned long long> h(WORK_SLOTS * WORK_N);
+  hipError_t e = hipMemcpyAsync(h.data(), c->d_work, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->d_work, 0, sizeof(unsigned long long) * h.size(), c->stream);
+  if (e != hipSuccess) return hip_fail(e, "work counter read");
+  for (int sl = 0; sl < WORK_SLOTS; ++sl)
+    for (int k = 0; k < DT_WORK_COUNTERS && k < WORK_N; ++k) out[k] += h[sl * WORK_N + k];
   return DT_OK;
 }
 
@@ -504,30 +539,78 @@ dt_status dt_debug_samples(dt_patch* p, const dt_orbits* o, const int64_t* d_ids
   if (m < 0 || (m > 0 && !d_ids)) return fail(DT_E_ARG, "bad id array");
   DeviceGuard g(p->ctx->device);
   StackArgs a = stack_args(p, o);
-  DebugArgs d{d_ids, m, d_px, d_py, d_tau, d_ix, d_iy, d_flags, d_psi, d_phi, nullptr};
+  DebugArgs d{d_ids, m, d_px, d_py, d_tau, d_ix, d_iy, d_flags, d_psi, d_phi};
   hipError_t e = launch_debug(a, d, p->ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "debug launch");
   return DT_OK;
 }
 
-dt_status dt_record_gathers(dt_patch* p, const dt_orbits* o, const int64_t* d_ids, int64_t m, uint32_t* d_off) {
+dt_status dt_debug_stack_samples(dt_patch* p, const dt_orbits* o, const int64_t* d_ids, int64_t m, double* d_px,
+                                 double* d_py, int32_t* d_ix, int32_t* d_iy, int32_t* d_flags, float* d_psi,
+                                 float* d_phi, double* d_tau) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
   dt_status st = check_orbits(o);
   if (st != DT_OK) return st;
-  if (m < 0 || (m > 0 && (!d_ids || !d_off))) return fail(DT_E_ARG, "bad id or output array");
-  if (p->plane_elems >= 0xFFFFFFFFull) return fail(DT_E_ARG, "planes too large for 32-bit offsets");
+  if (m < 0 || (m > 0 && !d_ids)) return fail(DT_E_ARG, "bad id array");
   DeviceGuard g(p->ctx->device);
   StackArgs a = stack_args(p, o);
-  DebugArgs d{d_ids, m, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, d_off};
-  hipError_t e = launch_debug(a, d, p->ctx->stream);
-  return e == hipSuccess ? DT_OK : hip_fail(e, "gather recording launch");
+  DebugArgs d{d_ids, m, d_px, d_py, d_tau, d_ix, d_iy, d_flags, d_psi, d_phi};
+  hipError_t e = launch_debug_stack(a, d, p->ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "stack-walk debug launch");
+  return DT_OK;
 }
 
-dt_status dt_gather_replay(dt_patch* p, const uint32_t* d_off, int64_t m, float* d_snr) {
+dt_status dt_record_gathers(dt_patch* p, const dt_orbits* o, int64_t* d_start, int64_t* d_list, int64_t* h_entries,
+                            int64_t* h_gathers) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
-  if (m < 0 || (m > 0 && (!d_off || !d_snr))) return fail(DT_E_ARG, "bad offset or output array");
+  dt_status st = check_orbits(o);
+  if (st != DT_OK) return st;
+  const int64_t n = o->n;
+  if (n > 0 && !d_start) return fail(DT_E_ARG, "d_start is NULL");
   DeviceGuard g(p->ctx->device);
-  hipError_t e = launch_gather_replay(p->d_planes, d_off, m, p->n_exp, d_snr, p->ctx->stream);
+  StackArgs a = stack_args(p, o);
+  hipStream_t s = p->ctx->stream;
+  if (d_list) {
+    hipError_t e = launch_record_gathers(a, nullptr, d_start, d_list, s);
+    return e == hipSuccess ? DT_OK : hip_fail(e, "gather recording launch");
+  }
+  if (!h_entries) return fail(DT_E_ARG, "h_entries is NULL");
+  const int64_t groups = (n + 63) / 64;
+  std::vector<int64_t> cnt(n), start(groups + 1, 0);
+  int64_t* d_cnt = nullptr;
+  if (n > 0) {
+    st = ctx_alloc(p->ctx, (void**)&d_cnt, sizeof(int64_t) * n, "gather counts");
+    if (st != DT_OK) return st;
+    hipError_t e = launch_record_gathers(a, d_cnt, nullptr, nullptr, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    ctx_free(p->ctx, d_cnt, sizeof(int64_t) * n);
+    if (e != hipSuccess) return hip_fail(e, "gather counting");
+  }
+  int64_t total = 0;
+  for (int64_t gi = 0; gi < groups; ++gi) {
+    int64_t w = 0;
+    for (int64_t i = gi * 64; i < std::min(n, gi * 64 + 64); ++i) {
+      w = std::max(w, cnt[i]);
+      total += cnt[i];
+    }
+    start[gi + 1] = start[gi] + 64 * w;
+  }
+  if (n > 0) {
+    hipError_t e = hipMemcpyAsync(d_start, start.data(), sizeof(int64_t) * (groups + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gather group starts");
+  }
+  *h_entries = start[groups];
+  if (h_gathers) *h_gathers = total;
+  return DT_OK;
+}
+
+dt_status dt_gather_replay(dt_patch* p, const int64_t* d_start, const int64_t* d_list, int64_t n, float* d_snr) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  if (n < 0 || (n > 0 && (!d_start || !d_list || !d_snr))) return fail(DT_E_ARG, "bad start, list or output array");
+  DeviceGuard g(p->ctx->device);
+  hipError_t e = launch_gather_replay(p->d_planes, d_start, d_list, n, d_snr, p->ctx->stream);
   return e == hipSuccess ? DT_OK : hip_fail(e, "gather replay launch");
 }
 

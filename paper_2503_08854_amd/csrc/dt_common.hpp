@@ -83,7 +83,17 @@ struct StackArgs {
   // patch: the largest |obs_i - obs_j| / (t_i - t_j) over epoch neighbours
   // (infinite when two exposures share an epoch but not an observer).
   double vobs = __builtin_inf();
+  // Work counters of the checkpoint walk (measurement only; NULL = off):
+  // WORK_SLOTS slots of WORK_N counters, slot = workgroup index mod WORK_SLOTS.
+  unsigned long long* work = nullptr;
 };
+
+// Work counters (one slot; see dt_ctx_count_work): samples tested by
+// prediction, queued exact solves, checkpoint solves, samples walked by the
+// per-sample tail, tail samples that took the full path, wavefronts that
+// switched to the tail.
+enum { WORK_PRED = 0, WORK_QUEUED, WORK_CKPT, WORK_TAIL, WORK_TAIL_FULL, WORK_SWITCHED, WORK_N = 8 };
+constexpr int WORK_SLOTS = 64;
 
 struct DebugArgs {
   const int64_t* ids;
@@ -91,7 +101,6 @@ struct DebugArgs {
   double *px, *py, *tau;
   int32_t *ix, *iy, *flags;
   float *psi, *phi;
-  uint32_t* off;  // [exposure in epoch order][m]: plane offset of a valid sample, else ~0u
 };
 
 // Work item of the batched persistent launch: orbits [begin, begin + count)
@@ -106,6 +115,8 @@ hipError_t launch_stack(const StackArgs& a, hipStream_t s);
 hipError_t launch_batched(const StackArgs* d_descs, const WorkItem* d_items, int n_items, unsigned int* d_counter,
                           int n_wg, hipStream_t s);
 hipError_t launch_debug(const StackArgs& a, const DebugArgs& d, hipStream_t s);
+// The same table from the walk launch_stack runs on this patch (solved samples only).
+hipError_t launch_debug_stack(const StackArgs& a, const DebugArgs& d, hipStream_t s);
 hipError_t launch_validate(const StackArgs& a, unsigned long long* d_bad, hipStream_t s);
 
 // BF16 GEMM C = op(A) op(B) (+ bias, ReLU) with FP32 accumulation; op(A) is
@@ -186,8 +197,10 @@ hipError_t launch_topk_segmented(const SegTopkArgs& a, int n_tiles, int n_arrays
 hipError_t launch_scorer_fused(const ScorerFusedArgs& a, bool transpose, hipStream_t s);
 
 // Replay of a recorded gather stream (measurement yardstick).
-hipError_t launch_gather_replay(const float2* planes, const uint32_t* off, int64_t m, int n_exp, float* snr,
-                                hipStream_t s);
+hipError_t launch_record_gathers(const StackArgs& a, int64_t* cnt, const int64_t* gstart, int64_t* list,
+                                 hipStream_t s);
+hipError_t launch_gather_replay(const float2* planes, const int64_t* gstart, const int64_t* list, int64_t n,
+                                float* snr, hipStream_t s);
 
 // Per-image iterated-MAD noise: per-image selection state.
 struct NoiseState {

@@ -29,6 +29,8 @@ struct dt_ctx {
   size_t noise_bytes = 0;
   dtk::BatchGraph* graph = nullptr;  // last captured batched launch
   hipStream_t capture_stream = nullptr;
+  unsigned long long* d_work = nullptr;  // work counters (dt_ctx_count_work), WORK_SLOTS x WORK_N
+  bool count_work = false;
   bool alive = true;
 };
 

@@ -106,6 +106,7 @@ dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t fir
   a.n = n;
   a.epoch = S->epoch;
   a.vobs = p->vobs;
+  a.work = p->ctx->count_work ? p->ctx->d_work : nullptr;
   a.snr = d_snr;
   a.flux = d_flux;
   a.nvalid = d_nvalid;

@@ -259,6 +259,7 @@ struct SampleOut {
   double px, py, tau;
   int ix, iy;
   bool front, inside;
+  bool solved;  // the full path ran (light-time correction and projection)
 };
 
 // Light-time history carried across exposures: last light time and its rate.
@@ -390,6 +391,7 @@ __device__ __forceinline__ void sample(const Orbit& o, KepState& k, LtState& lt,
     tau = tg + D0;
     out.front = out.inside = false;
   }
+  out.solved = full;
   lt.rate = FIRST ? 0.0 : (tau - lt.tau) * inv_gap;
   lt.tau = tau;
   out.tau = tau;

@@ -11,6 +11,39 @@
 
 namespace dtk {
 
+// Debug table of the walk that ran (dt_debug_samples and its stack-walk
+// variant): row `row`, column = the exposure's caller index.  flags: bit0 in
+// front of the tangent plane, bit1 inside the image, bit2 valid (phi > 0),
+// bit3 solved exactly by the walk; a sample the walk excluded by a bound
+// keeps the row's initial values (rec_init_row).
+__device__ __forceinline__ void rec_init_row(const DebugArgs& d, const ExpMeta* meta, int n_exp, int64_t row) {
+  for (int ex = 0; ex < n_exp; ++ex) {
+    const int64_t q = row * n_exp + meta[ex].src;
+    if (d.px) d.px[q] = __builtin_nan("");
+    if (d.py) d.py[q] = __builtin_nan("");
+    if (d.ix) d.ix[q] = (int)0x80000000;
+    if (d.iy) d.iy[q] = (int)0x80000000;
+    if (d.tau) d.tau[q] = __builtin_nan("");
+    if (d.flags) d.flags[q] = 0;
+    if (d.psi) d.psi[q] = 0.f;
+    if (d.phi) d.phi[q] = 0.f;
+  }
+}
+__device__ __forceinline__ void rec_sample(const DebugArgs& d, int n_exp, int64_t row, const ExpMeta& x,
+                                           const SampleOut& so, float2 v) {
+  const int64_t q = row * n_exp + x.src;
+  const bool f = so.front;
+  const bool valid = so.inside && v.y > 0.f;
+  if (d.px) d.px[q] = f ? so.px : __builtin_nan("");
+  if (d.py) d.py[q] = f ? so.py : __builtin_nan("");
+  if (d.ix) d.ix[q] = f ? so.ix : (int)0x80000000;
+  if (d.iy) d.iy[q] = f ? so.iy : (int)0x80000000;
+  if (d.tau) d.tau[q] = so.tau;
+  if (d.flags) d.flags[q] = (f ? 1 : 0) | (so.inside ? 2 : 0) | (valid ? 4 : 0) | 8;
+  if (d.psi) d.psi[q] = valid ? v.x : 0.f;
+  if (d.phi) d.phi[q] = valid ? v.y : 0.f;
+}
+
 // Compensated sums of one prepared orbit over exposures [ex0, ex0 + cnt)
 // (epoch order; no debug table).  Each gather is accumulated one exposure
 // later, still in epoch order, so its load latency overlaps the next sample's
@@ -20,7 +53,9 @@ struct StackPart {
   Kahan ps, ph;
   int nv;
 };
-__device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob, int ex0, int cnt, StackPart& P) {
+template <bool REC = false>
+__device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob, int ex0, int cnt, StackPart& P,
+                                            const DebugArgs* dbg = nullptr, int64_t row = 0) {
   P.ps.init();
   P.ph.init();
   P.nv = 0;
@@ -36,6 +71,7 @@ __device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob,
     const ExpMeta& x = A.meta[ex0 + i];
     take(pend);
     pend = so.inside ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
+    if (REC && so.solved) rec_sample(*dbg, A.n_exp, row, x, so, pend);
   });
   take(pend);
 }
@@ -64,13 +100,7 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
   if (!orbit_ok(a, e, inc, node, peri, m0)) {
     snr_out = flux_out = __builtin_nanf("");
     nv_out = -1;
-    if (DEBUG) {
-      for (int ex = 0; ex < A.n_exp; ++ex) {
-        int64_t q = row * A.n_exp + A.meta[ex].src;
-        if (dbg->flags) dbg->flags[q] = 0;
-        if (dbg->off) dbg->off[(int64_t)ex * dbg->m + row] = ~0u;
-      }
-    }
+    if (DEBUG) rec_init_row(*dbg, A.meta, A.n_exp, row);
     return;
   }
   Orbit ob;
@@ -86,28 +116,15 @@ __device__ __forceinline__ void stack_orbit(const StackArgs& A, int64_t o, const
   walk_orbit<true>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
     const ExpMeta& x = A.meta[ex];
     float2 v = make_float2(0.f, 0.f);
-    bool valid = false;
     if (so.inside) {
       v = A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix];
-      valid = v.y > 0.f;
-      if (valid) {
+      if (v.y > 0.f) {
         ps.add(v.x);
         ph.add(v.y);
         nv++;
       }
     }
-    const int64_t q = row * A.n_exp + x.src;
-    const bool f = so.front;
-    if (dbg->px) dbg->px[q] = f ? so.px : __builtin_nan("");
-    if (dbg->py) dbg->py[q] = f ? so.py : __builtin_nan("");
-    if (dbg->ix) dbg->ix[q] = f ? so.ix : (int)0x80000000;
-    if (dbg->iy) dbg->iy[q] = f ? so.iy : (int)0x80000000;
-    if (dbg->tau) dbg->tau[q] = so.tau;
-    if (dbg->flags) dbg->flags[q] = (f ? 1 : 0) | (so.inside ? 2 : 0) | (valid ? 4 : 0);
-    if (dbg->psi) dbg->psi[q] = valid ? v.x : 0.f;
-    if (dbg->phi) dbg->phi[q] = valid ? v.y : 0.f;
-    if (dbg->off)
-      dbg->off[(int64_t)ex * dbg->m + row] = valid ? (uint32_t)(x.plane_off + (int64_t)so.iy * x.W + so.ix) : ~0u;
+    rec_sample(*dbg, A.n_exp, row, x, so, v);
   });
   const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
   snr_out = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;

@@ -23,6 +23,12 @@
 // nearest pixel), by whichever lanes are free, 64 at a time, and each orbit
 // adds its gathered values in epoch order, so the sums equal those of the
 // per-sample walk.
+//
+// The prediction pays while most samples miss.  A wavefront whose orbits land
+// often (more than TRACK_SWITCH of its lane-exposures queued, e.g. distant
+// objects followed by the field for months) serves its queue and walks the
+// remaining exposures per sample instead, warm from each lane's checkpoint,
+// with the per-sample walk's own sky-cone test; the sums keep epoch order.
 #pragma once
 #include "dt_stack.hpp"
 
@@ -34,6 +40,8 @@ constexpr double PRED_SLACK = 1e-9;  // AU: rounding of the checkpoint state and
 constexpr int TQ_CAP = 128;          // queued samples per wavefront (< 64 held + 64 pushed)
 constexpr int TQ_LIST = 8;           // queued samples per lane between flushes
 constexpr int CK_ANCHOR = 8;         // checkpoints between full sincos re-anchors of sin E, cos E
+constexpr float TRACK_SWITCH = 0.05f; // queued fraction of lane-exposures above which a wavefront walks per sample
+constexpr int TRACK_SWITCH_MIN = 8;   // exposures walked before the fraction is trusted
 
 // One wavefront's state in LDS: the queue, and each lane's prepared orbit and
 // checkpoint Kepler state (read by whichever lane solves that orbit's queued
@@ -68,6 +76,67 @@ __device__ __forceinline__ void track_bound(double a, double e, const Orbit& o, 
   b.vmax = vmax;
 }
 
+// Per-sample tail of a wavefront's walk from exposure ex on (see the file
+// comment): Kepler warm from the lane's checkpoint state in Qm, the light
+// time started at tg0 (this exposure's predicted distance; rate 0 until the
+// second tail sample), the per-sample walk's sky-cone test, gathers
+// accumulated one exposure later, added to P in epoch order.  The prepared
+// orbit comes back from LDS (held in registers through the main loop it
+// would spill); its cone slack mq is formed from vmax as orbit_prep forms it
+// (vmax < 0: bound coefficients overflowed, never pruned).
+template <bool REC>
+__device__ __forceinline__ void track_tail(const StackArgs& A, TrackQueue& Qm, int ex, double tg0,
+                                                     double vmax, bool live, StackPart& P, int& n_full,
+                                                     const DebugArgs* dbg, int64_t rowbase) {
+  volatile LdsTrackQueue& Q = *(volatile LdsTrackQueue*)(&Qm);
+  const int lane = (int)__lane_id();
+  const ExpMeta* __restrict__ meta = A.meta;
+  Orbit ot;
+  ot.e = Q.orb[0][lane];
+  ot.n = Q.orb[1][lane];
+  ot.m0 = Q.orb[2][lane];
+  ot.aP0 = Q.orb[3][lane];
+  ot.aP1 = Q.orb[4][lane];
+  ot.aP2 = Q.orb[5][lane];
+  ot.bQ0 = Q.orb[6][lane];
+  ot.bQ1 = Q.orb[7][lane];
+  ot.bQ2 = Q.orb[8][lane];
+  ot.he = -0.5 * ot.e;
+  ot.mq = vmax >= 0.0 ? 1.1002 * LT_LINEAR_MAX * vmax * (1.0 + vmax * (1.0 / C_AU_DAY)) : __builtin_inf();
+  KepState k;
+  k.E = Q.kep[0][lane];
+  k.sE = Q.kep[1][lane];
+  k.cE = Q.kep[2][lane];
+  k.g = Q.kep[3][lane];
+  k.M = fma(-ot.e, k.sE, k.E);
+  LtState lt;
+  lt.tau = tg0;
+  lt.rate = 0.0;
+  float2 pend = make_float2(0.f, 0.f);
+  const int ex0 = ex;
+#pragma unroll 1
+  for (; ex < A.n_exp; ++ex) {
+    const ExpMeta& x = meta[ex];
+    SampleOut so;
+    const bool first = ex == ex0;
+    sample<false, false>(ot, k, lt, x, A.epoch, first ? 0.0 : x.gap, first ? 0.0 : x.inv_gap,
+                         !first && (ex % ANCHOR) == 0, so);
+    if (pend.y > 0.f) {
+      P.ps.add(pend.x);
+      P.ph.add(pend.y);
+      P.nv++;
+    }
+    pend = (live && so.inside) ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
+    if (REC && live && so.solved) rec_sample(*dbg, A.n_exp, rowbase + lane, x, so, pend);
+    n_full += __builtin_popcountll(__builtin_amdgcn_ballot_w64(live && so.solved));
+  }
+  if (pend.y > 0.f) {
+    P.ps.add(pend.x);
+    P.ph.add(pend.y);
+    P.nv++;
+  }
+}
+
 // The walk of one wavefront.  All 64 lanes call it together; lanes with
 // live = false (no orbit, or one outside the domain) carry any valid
 // prepared orbit and queue nothing.  P receives each live lane's sums.
@@ -77,9 +146,15 @@ __device__ __forceinline__ void track_bound(double a, double e, const Orbit& o, 
 // a lane's list is full, or after the last exposure; then the checkpoint
 // solve of every lane when due.  Both are one loop over jobs so the exact
 // solve exists once in the code.  Then the cone test of the prediction
-// queues the samples that may land.
+// queues the samples that may land.  After a service step the wavefront may
+// leave the prediction for the per-sample tail (see the file comment).
+//
+// REC (debug kernels only): every sample the walk solves exactly is written
+// to row rowbase + lane of dbg (the owner's row for queued samples).
+template <bool REC = false>
 __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, const TrackBound& bd, bool live,
-                                           TrackQueue& Qm, StackPart& P) {
+                                           TrackQueue& Qm, StackPart& P, const DebugArgs* dbg = nullptr,
+                                           int64_t rowbase = 0) {
   // LDS address space explicitly: volatile accesses through a generic pointer
   // would be kept generic (flat) by the compiler
   volatile LdsTrackQueue& Q = *(volatile LdsTrackQueue*)(&Qm);
@@ -113,9 +188,13 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   int n_ck = 0;      // checkpoints so far
   int count = 0;     // queued samples (wave-uniform)
   int len = 0;       // this lane's queued samples
+  int queued = 0;    // samples queued so far (wave-uniform)
   bool full = false; // the queue must be served before more samples are pushed
+  int ex = 0;
+  bool tail = false; // leave the prediction at exposure ex for the per-sample walk
+  double tg_tail = 0.0;
 
-  for (int ex = 0; ex <= A.n_exp; ++ex) {
+  for (; ex <= A.n_exp && !tail; ++ex) {
     const bool last = ex == A.n_exp;
     const ExpMeta& x = meta[last ? ex - 1 : ex];
     double D = x.t - tc;
@@ -196,6 +275,10 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
             const bool ok = v.y > 0.f;
             Q.rx[i] = ok ? v.x : 0.f;
             Q.ry[i] = ok ? v.y : 0.f;
+            if (REC) {
+              so.tau = tg + s.D;
+              rec_sample(*dbg, A.n_exp, rowbase + L, xm, so, v);
+            }
           }
         }
       }
@@ -211,8 +294,12 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
             P.nv++;
           }
         }
+        queued += count;
         count = 0;
         len = 0;
+        // most samples land: walk the rest per sample (the checkpoint due at
+        // this exposure, if any, has just been taken and starts the tail)
+        tail = !last && ex >= TRACK_SWITCH_MIN && (float)queued > TRACK_SWITCH * 64.f * (float)ex;
       }
       // prediction state from the checkpoint kept in LDS (recomputed after every
       // service step, so it holds no registers while the solves run): the
@@ -259,7 +346,9 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
     const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
     const double m = fma(j6 * D * D, D, fma(l1, D, s0));
     const double R = fma(x.cone_tan, sc, m);
-    const bool may = live & (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
+    // leaving for the tail: this exposure's predicted distance starts its light time
+    tg_tail = d2 * __builtin_amdgcn_rsq(d2) * IC;
+    const bool may = live & !tail & (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
     const uint64_t mask = __builtin_amdgcn_ballot_w64(may);
     if (mask) {
       if (may) {
@@ -274,14 +363,32 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       full = count >= 64 || __builtin_amdgcn_ballot_w64(len >= TQ_LIST) != 0;
     }
   }
+  int n_full = 0;
+  if (tail) track_tail<REC>(A, Qm, ex - 1, tg_tail, bounded ? vmax : -1.0, live, P, n_full, dbg, rowbase);
+  const unsigned long long nl = (unsigned long long)__builtin_popcountll(__builtin_amdgcn_ballot_w64(live));
+  if (A.work && lane == 0) {
+    // wave totals (uniform values) into this workgroup's slot
+    unsigned long long* w = A.work + WORK_N * (blockIdx.x % WORK_SLOTS);
+    const int ex_pred = tail ? ex - 1 : A.n_exp;
+    atomicAdd(w + WORK_PRED, nl * (unsigned long long)ex_pred);
+    atomicAdd(w + WORK_QUEUED, (unsigned long long)queued);
+    atomicAdd(w + WORK_CKPT, nl * (unsigned long long)n_ck);
+    if (tail) {
+      atomicAdd(w + WORK_TAIL, nl * (unsigned long long)(A.n_exp - ex_pred));
+      atomicAdd(w + WORK_TAIL_FULL, (unsigned long long)n_full);
+      atomicAdd(w + WORK_SWITCHED, 1ull);
+    }
+  }
 }
 
 // One lane's orbit through the walk of its wavefront: `el` holds the
 // elements when `live` (any values otherwise); the outputs are those of the
 // per-sample stack (NaN, NaN, -1 for an orbit that is not live).  All 64
 // lanes of the wavefront call it together; Q is the wavefront's LDS queue.
+template <bool REC = false>
 __device__ __forceinline__ void track_stack_lane(const StackArgs& A, const double el[6], bool live, TrackQueue& Q,
-                                                 float& snr, float& flux, int& nv) {
+                                                 float& snr, float& flux, int& nv, const DebugArgs* dbg = nullptr,
+                                                 int64_t rowbase = 0) {
   double a = el[0], e = el[1], inc = el[2], node = el[3], peri = el[4], m0 = el[5];
   if (!live) {
     a = 2.5;
@@ -292,7 +399,7 @@ __device__ __forceinline__ void track_stack_lane(const StackArgs& A, const doubl
   TrackBound bd;
   track_bound(a, e, ob, A.vobs, bd);
   StackPart P;
-  track_walk(A, ob, bd, live, Q, P);
+  track_walk<REC>(A, ob, bd, live, Q, P, dbg, rowbase);
   snr = flux = __builtin_nanf("");
   nv = -1;
   if (live) stack_finish(P, snr, flux, nv);

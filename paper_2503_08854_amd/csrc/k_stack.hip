@@ -54,15 +54,50 @@ __global__ __launch_bounds__(64) void k_stack_debug(StackArgs A, DebugArgs D) {
   if (r >= D.m) return;
   const int64_t o = D.ids[r];
   if (o < 0 || o >= A.n) {
-    for (int ex = 0; ex < A.n_exp; ++ex) {
-      if (D.flags) D.flags[r * A.n_exp + ex] = 0;
-      if (D.off) D.off[(int64_t)ex * D.m + r] = ~0u;
-    }
+    rec_init_row(D, A.meta, A.n_exp, r);
     return;
   }
   float snr, flux;
   int nv;
   stack_orbit<true>(A, o, &D, r, snr, flux, nv);
+}
+
+// The debug table from the walks dt_stack runs: the checkpoint walk (row r =
+// the wavefront's rows, queued samples written to their owner's row) and,
+// for patches without an observer speed bound, the per-sample walk with its
+// sky-cone test.  Only samples the walk solves exactly are written.
+__global__ __launch_bounds__(256, 4) void k_stack_track_debug(StackArgs A, DebugArgs D) {
+  __shared__ TrackQueue tq[4];
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = (int)__lane_id();
+  if (r - lane >= D.m) return;  // the whole wavefront is past the end
+  const bool in = r < D.m;
+  const int64_t o = in ? D.ids[r] : -1;
+  const bool has = o >= 0 && o < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (has) {
+    el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+  }
+  if (in) rec_init_row(D, A.meta, A.n_exp, r);
+  __syncthreads();  // the rows' initial values land before any lane's solves overwrite them
+  float snr, flux;
+  int nv;
+  track_stack_lane<true>(A, el, has && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6],
+                         snr, flux, nv, &D, r - lane);
+}
+
+__global__ __launch_bounds__(64) void k_stack_walk_debug(StackArgs A, DebugArgs D) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D.m) return;
+  const int64_t o = D.ids[r];
+  rec_init_row(D, A.meta, A.n_exp, r);
+  if (o < 0 || o >= A.n) return;
+  const double a = A.a[o], e = A.e[o], inc = A.inc[o], node = A.node[o], peri = A.peri[o], m0 = A.m0[o];
+  if (!orbit_ok(a, e, inc, node, peri, m0)) return;
+  Orbit ob;
+  orbit_prep(a, e, inc, node, peri, m0, ob);
+  StackPart P;
+  stack_range<true>(A, ob, 0, A.n_exp, P, &D, r);
 }
 
 __global__ __launch_bounds__(256) void k_validate(StackArgs A, unsigned long long* bad) {
@@ -71,37 +106,90 @@ __global__ __launch_bounds__(256) void k_validate(StackArgs A, unsigned long lon
   if (!orbit_ok(A.a[o], A.e[o], A.inc[o], A.node[o], A.peri[o], A.m0[o])) atomicAdd(bad, 1ull);
 }
 
-// The stack's gather stream without its arithmetic: lane i visits the
-// recorded plane offsets of orbit i in epoch order and sums what it loads
-// exactly as k_stack does.  A yardstick for the achievable gather rate.
+// Measurement yardstick: the stack's gathers without its arithmetic.
+// k_record_gathers walks orbit o exactly and either counts the samples that
+// land inside an image (the gathers the stack makes) into cnt[o], or writes
+// their global plane offsets, in epoch order, into the slot-major list of
+// its group of 64 orbits: entry (k, lane) at gstart[g] + 64 k + lane, -1 past
+// the lane's count up to the group's width (gstart[g + 1] - gstart[g]) / 64.
+__global__ __launch_bounds__(256) void k_record_gathers(StackArgs A, int64_t* __restrict__ cnt,
+                                                        const int64_t* __restrict__ gstart, int64_t* __restrict__ list) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= A.n) return;
+  const int lane = (int)(o & 63);
+  const int64_t g = o >> 6;
+  int64_t* L = list ? list + gstart[g] + lane : nullptr;
+  int64_t k = 0;
+  const double a = A.a[o], e = A.e[o], inc = A.inc[o], node = A.node[o], peri = A.peri[o], m0 = A.m0[o];
+  if (orbit_ok(a, e, inc, node, peri, m0)) {
+    Orbit ob;
+    orbit_prep(a, e, inc, node, peri, m0, ob);
+    walk_orbit<true>(ob, A.meta, A.n_exp, A.epoch, [&](int ex, const SampleOut& so) {
+      if (so.inside) {
+        const ExpMeta& x = A.meta[ex];
+        if (L) L[64 * k] = x.plane_off + (int64_t)so.iy * x.W + so.ix;
+        k++;
+      }
+    });
+  }
+  if (cnt) cnt[o] = k;
+  if (L) {
+    const int64_t w = (gstart[g + 1] - gstart[g]) >> 6;
+    for (; k < w; ++k) L[64 * k] = -1;
+  }
+}
+
+// Lane o loads its recorded offsets (eight gathers in flight; a padded slot
+// reads the first plane element and drops it) and sums them exactly as the
+// stack does, in epoch order: its S/N equals the stack's.
+constexpr int REPLAY_DEPTH = 8;
 __global__ __launch_bounds__(256) void k_gather_replay(const float2* __restrict__ planes,
-                                                       const uint32_t* __restrict__ off, int64_t m, int n_exp,
+                                                       const int64_t* __restrict__ gstart,
+                                                       const int64_t* __restrict__ list, int64_t n,
                                                        float* __restrict__ snr) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n) return;
+  const int lane = (int)(o & 63);
+  const int64_t g = o >> 6;
+  const int64_t base = gstart[g];
+  const int64_t w = (gstart[g + 1] - base) >> 6;
+  const int64_t* L = list + base + lane;
   Kahan ps, ph;
   ps.init();
   ph.init();
-  for (int ex = 0; ex < n_exp; ++ex) {
-    const uint32_t o = off[(int64_t)ex * m + i];
-    if (o != ~0u) {
-      const float2 v = planes[o];
-      if (v.y > 0.f) {
-        ps.add(v.x);
-        ph.add(v.y);
+#pragma unroll 1
+  for (int64_t k = 0; k < w; k += REPLAY_DEPTH) {
+    int64_t off[REPLAY_DEPTH];
+    float2 v[REPLAY_DEPTH];
+#pragma unroll
+    for (int j = 0; j < REPLAY_DEPTH; ++j) off[j] = k + j < w ? L[64 * (k + j)] : -1;
+#pragma unroll
+    for (int j = 0; j < REPLAY_DEPTH; ++j) v[j] = planes[off[j] >= 0 ? off[j] : 0];
+#pragma unroll
+    for (int j = 0; j < REPLAY_DEPTH; ++j) {
+      if (off[j] >= 0 && v[j].y > 0.f) {
+        ps.add(v[j].x);
+        ph.add(v[j].y);
       }
     }
   }
   const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
-  snr[i] = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
+  snr[o] = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
 }
 
 static inline unsigned int grid_for(int64_t n, int bs) { return (unsigned int)((n + bs - 1) / bs); }
 
-hipError_t launch_gather_replay(const float2* planes, const uint32_t* off, int64_t m, int n_exp, float* snr,
-                                hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_replay, dim3(grid_for(m, 256)), dim3(256), 0, s, planes, off, m, n_exp, snr);
+hipError_t launch_record_gathers(const StackArgs& a, int64_t* cnt, const int64_t* gstart, int64_t* list,
+                                 hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_record_gathers, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a, cnt, gstart, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_replay(const float2* planes, const int64_t* gstart, const int64_t* list, int64_t n,
+                                float* snr, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_replay, dim3(grid_for(n, 256)), dim3(256), 0, s, planes, gstart, list, n, snr);
   return hipGetLastError();
 }
 
@@ -117,6 +205,15 @@ hipError_t launch_stack(const StackArgs& a, hipStream_t s) {
 hipError_t launch_debug(const StackArgs& a, const DebugArgs& d, hipStream_t s) {
   if (d.m <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_stack_debug, dim3(grid_for(d.m, 64)), dim3(64), 0, s, a, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_stack(const StackArgs& a, const DebugArgs& d, hipStream_t s) {
+  if (d.m <= 0) return hipSuccess;
+  if (a.vobs < __builtin_inf())
+    hipLaunchKernelGGL(k_stack_track_debug, dim3(grid_for(d.m, 256)), dim3(256), 0, s, a, d);
+  else
+    hipLaunchKernelGGL(k_stack_walk_debug, dim3(grid_for(d.m, 64)), dim3(64), 0, s, a, d);
   return hipGetLastError();
 }
 

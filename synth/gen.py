@@ -25,7 +25,7 @@ __all__ = [
     "K_OBS", "GOLDEN_DIR", "make_rng", "sorted_epochs", "observer_circular", "unit",
     "tangent_basis", "orbits_through", "Workload", "load_geometry", "exposures_of",
     "candidate_orbits", "perturbed_cloud", "noise_images", "render_sources", "build_workload",
-    "radec_to_vec", "vec_to_radec", "hw_pixscale_deg", "cell_grid", "render_sources_fast",
+    "radec_to_vec", "vec_to_radec", "hw_pixscale_deg", "cell_grid", "render_sources_fast", "grid_sampler",
 ]
 
 # Mean motion (rad/day) of the synthetic observer on a circular 1 AU orbit.
@@ -255,6 +255,18 @@ def build_workload(geom: dict, n_orbits: int = None, seed: int = None, device=No
     g = geom["grid"]
     n = g["n"] if n_orbits is None else int(n_orbits)
     injs = geom.get("injections", [])
+    if g.get("generated"):
+        # the grid is a counter-based sampler (grid_sampler); injections sit
+        # on grid orbits at their stored indices
+        W = Workload(name=geom["name"], exps=exps, t0=float(geom["t0"]), elements=None, injections=injs,
+                     inj_index=np.array([int(i["index"]) for i in injs], dtype=np.int64),
+                     dtype=geom.get("dtype", "f32"), geom=geom)
+        if images:
+            D, V = noise_images(exps, seed, geom.get("nan_frac", 0.0), W.dtype, device)
+            hits = [(h[0], h[1], h[2], i["flux"]) for i in injs for h in i["hits"]]
+            render_sources_fast(D, exps, hits, device)
+            W.D, W.V = D, V
+        return W
     cloud = g.get("cloud", 0) if cloud is None else cloud
     extra = len(injs) * (1 + cloud)
     n_rand = max(n - extra, 0)
@@ -283,6 +295,15 @@ def build_workload(geom: dict, n_orbits: int = None, seed: int = None, device=No
         render_sources(D, exps, injs, device)
         W.D, W.V = D, V
     return W
+
+
+def grid_sampler(geom: dict) -> dict:
+    """Parameters of a generated grid: the field (center/east/north/obs/half
+    widths), the epoch, the (a, e, inclination in degrees) ranges and the
+    sampler seed.  Orbit k of the grid is a pure function of these and k."""
+    g = geom["grid"]
+    return dict(field=geom["grid_field"], epoch=float(geom["grid_field"]["t"]), a=tuple(g["a"]), e=tuple(g["e"]),
+                inc_deg=tuple(g["inc_deg"]), seed=int(g["sampler_seed"]), n=int(g["n"]))
 
 
 def cell_grid(gf: dict, n_cells: int, cell_size: int, seed: int, a_rng, e_rng, inc_deg_rng,

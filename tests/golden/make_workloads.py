@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 import synth  # noqa: E402
+from oracle import generate as ogen  # noqa: E402
 
 OUT = os.path.dirname(os.path.abspath(__file__))
 
@@ -183,6 +184,63 @@ def distant_small(seed=6):
                   sigma_rng=(0.9, 1.1))
 
 
+def oracle_sampler(gf, grid):
+    """The generated grid's sampler in the form oracle.generate takes."""
+    return dict(center=gf["center"], east=gf["east"], north=gf["north"], obs=gf["obs"], half_w=gf["half_w"],
+                half_h=gf["half_h"], a=tuple(grid["a"]), e=tuple(grid["e"]),
+                inc=tuple(math.radians(v) for v in grid["inc_deg"]), seed=int(grid["sampler_seed"]), epoch=gf["t"])
+
+
+def draw_generated_injections(seed, gf, grid, t0, exps, n, s_rng, fwhm, min_snr=3.0, batch=64):
+    """Injections on orbits of a device-generated grid: orbit indices drawn
+    uniformly from [0, grid n), elements from the oracle's generator (so the
+    true orbit is a member of the grid the stack searches), per-image S/N
+    s ~ U(s_rng) kept when s sqrt(n_hit) >= min_snr."""
+    rng = synth.make_rng(seed, 57)
+    So = oracle_sampler(gf, grid)
+    p2 = sum_p2(fwhm)
+    out, used = [], set()
+    for _ in range(1000):
+        idx = rng.integers(0, int(grid["n"]), batch)
+        s = rng.uniform(*s_rng, batch)
+        el = np.array([ogen.sample_orbit(So, int(j)) or (np.nan,) * 6 for j in idx])
+        ok = ~np.isnan(el[:, 0])
+        smp = oracle.samples(el[ok], t0, exps)
+        hit = (smp["flags"] & 3) == 3
+        for r, k in enumerate(np.nonzero(ok)[0]):
+            j = int(idx[k])
+            nh = int(hit[r].sum())
+            if j in used or s[k] * math.sqrt(nh) < min_snr:
+                continue
+            used.add(j)
+            hits = [[int(e), float(smp["px"][r, e]), float(smp["py"][r, e])] for e in np.nonzero(hit[r])[0]]
+            out.append(dict(index=j, el=[float(v) for v in el[k]], s=float(s[k]), flux=float(s[k] / math.sqrt(p2)),
+                            hits=hits))
+            if len(out) == n:
+                return out
+    raise RuntimeError("injection rejection sampling did not finish")
+
+
+def distant(seed=8, n_exp=400, side=4096, n_orb=1_000_000_000, n_inj=100, name="distant"):
+    """Distant objects at full size: 400 FP16 4096^2 images plus variance over
+    365 days, 0.2"/px, the field following a reference orbit at 45 AU (e 0.1,
+    i 10 deg); 10^9 candidate orbits a 30-60 AU, e 0-0.3, i 0-40 deg generated
+    on the device from a counter-based sampler (the grid is the sampler, no
+    element arrays); 100 injections on grid orbits at per-image S/N
+    U(0.2, 1), kept when s sqrt(n_hit) >= 3."""
+    lam = 1.1
+    rng = synth.make_rng(seed, 1)
+    t, t0 = make_epochs(rng, n_exp, 365.0)
+    el_ref = reference_orbit(seed, t0, lam, 45.0, 0.1, 10.0, 1.0)
+    exps = make_exposures(rng, t, side, side, 0.2, el_ref, t0, lam, [(0.0, 0.0)], (0.9, 1.1), 3.0)
+    gf = grid_field(exps, t0, lam, side, side, 0.2)
+    grid = dict(n=n_orb, a=[30.0, 60.0], e=[0.0, 0.3], inc_deg=[0.0, 40.0], cloud=0, generated=True,
+                sampler_seed=seed * 1000 + 17)
+    injs = draw_generated_injections(seed, gf, grid, t0, exps, n_inj, (0.2, 1.0), 3.0)
+    return dict(name=name, seed=seed, t0=t0, dtype="f16", nan_frac=0.0, exposures=exps, grid_field=gf, grid=grid,
+                injections=injs)
+
+
 def reference_orbit_general(rng, obs, a_rng, e_rng, inc_rng, near_earth=False):
     """A reference orbit whose geometric position at the epoch is on a line of
     sight from the observer at elongation 60-180 deg (opposition excluded for
@@ -287,7 +345,7 @@ def learned_small(seed=3):
 
 WORKLOADS = {"tiny": tiny, "survey": survey, "survey_small": survey_small, "batched": batched,
              "batched_small": batched_small, "learned": learned, "learned_small": learned_small,
-             "distant_small": distant_small}
+             "distant_small": distant_small, "distant": distant}
 
 
 def main(names):

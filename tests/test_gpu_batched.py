@@ -63,12 +63,13 @@ def test_pruned_stack_equals_exact_walk(batch):
     import paper_2503_08854_amd as dt
     for p, (patch, orb) in enumerate(zip(batch["patches"], batch["sets"])):
         snr, flux, nv = dt.stack(patch, orb)
-        off = dt.record_gathers(patch, orb, np.arange(orb.n))
-        rep = dt.gather_replay(patch, off)
+        rec = dt.record_valid_gathers(patch, orb)
+        rep = dt.replay_valid_gathers(patch, rec)
+        ex = {k: v.cpu().numpy() for k, v in dt.debug_samples(patch, orb, np.arange(orb.n)).items()}
         torch.cuda.synchronize()
         nv = nv.cpu().numpy()
-        np.testing.assert_array_equal(np.maximum(nv, 0), (off.cpu().numpy() != -1).sum(axis=0), err_msg=f"patch {p}")
-        np.testing.assert_array_equal(rep.cpu().numpy(), np.where(nv >= 0, snr.cpu().numpy(), 0.0).astype(np.float32))
+        np.testing.assert_array_equal(np.maximum(nv, 0), ((ex["flags"] & 4) != 0).sum(axis=1), err_msg=f"patch {p}")
+        np.testing.assert_array_equal(rep.cpu().numpy(), np.where(nv > 0, snr.cpu().numpy(), 0.0).astype(np.float32))
 
 
 def test_batched_topk_both_paths(batch):

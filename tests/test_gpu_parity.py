@@ -6,7 +6,8 @@ import pytest
 
 import oracle
 import synth
-from helpers import compare_samples, gpu_run, snr_close, to_torch_images
+from helpers import (compare_samples, compare_stack_walk, decode_gathers, gpu_run, plane_offsets, snr_close,
+                     to_torch_images)
 
 pytestmark = pytest.mark.gpu
 
@@ -74,6 +75,59 @@ def test_stack_tiny(tiny):
     # top-k order: the oracle's ordering of the GPU's own S/N values
     want = oracle.topk(g["snr"].astype(np.float64), 16)
     np.testing.assert_array_equal(g["topk_idx"][:g["topk_cnt"]], want)
+
+
+@pytest.mark.parametrize("name", ["tiny", "survey_small", "distant_small"])
+def test_stack_walk_samples_match_oracle(name):
+    """The per-sample table of the walk dt_stack runs (checkpoint prediction,
+    its queue and its per-sample tail): every sample that lands was solved,
+    and solved samples carry the oracle's pixel (bit-exact outside the 1e-6 px
+    band), coordinates within 1e-6 px and light time within 1e-12 day."""
+    import torch
+    import paper_2503_08854_amd as dt
+    w = synth.build_workload(synth.load_geometry(name))
+    n = w.elements.shape[0]
+    ids = np.unique(np.r_[np.arange(min(n, 4000)), w.inj_index])
+    g = gpu_run(w)
+    ctx, patch, orb, _, _ = g["_keep"]
+    st = {k: v.cpu().numpy() for k, v in dt.debug_samples(patch, orb, ids, walk="stack").items()}
+    torch.cuda.synchronize()
+    o = oracle.samples(w.elements[ids], w.t0, w.exps, w.D, w.V)
+    nb, ns, nc = compare_stack_walk(st, o, w.exps)
+    assert o["bad"] == 0 and nb <= 2 and nc > 1000
+    # pruning did its job: far fewer samples solved than walked
+    assert ns < 0.5 * st["flags"].size
+    # the table's valid samples are the stack's own: same counts as dt_stack
+    np.testing.assert_array_equal(((st["flags"] & 4) != 0).sum(axis=1), np.maximum(g["nv"][ids], 0))
+
+
+@pytest.mark.parametrize("name", ["tiny", "survey_small", "distant_small"])
+def test_work_counters(name):
+    """The checkpoint walk's work counters: every live orbit-exposure is either
+    tested by the prediction or walked by the per-sample tail; checkpoints
+    follow the 16-day rule until a wavefront switches; every valid sample was
+    solved (queued or on the tail's full path); counting changes no result."""
+    import torch
+    import paper_2503_08854_amd as dt
+    import bench
+    w = synth.build_workload(synth.load_geometry(name))
+    g = gpu_run(w)
+    ctx, patch, orb, _, _ = g["_keep"]
+    ctx.count_work(True)
+    snr, flux, nv = dt.stack(patch, orb)
+    wk = ctx.work()
+    ctx.count_work(False)
+    np.testing.assert_array_equal(nv.cpu().numpy(), g["nv"])
+    np.testing.assert_array_equal(snr.cpu().numpy(), g["snr"])
+    n, ne = orb.n, patch.n_exp
+    assert wk["predicted"] + wk["tail_samples"] == n * ne
+    assert wk["checkpoint_solves"] <= n * bench.checkpoints(w.exps)
+    if wk["switched_waves"] == 0:
+        assert wk["checkpoint_solves"] == n * bench.checkpoints(w.exps) and wk["tail_samples"] == 0
+    assert wk["queued_solves"] + wk["tail_full"] >= int(np.maximum(g["nv"], 0).sum())
+    assert wk["tail_full"] <= wk["tail_samples"]
+    assert ctx.work()["predicted"] == 0     # reading zeroes the counters
+    print(name, wk)
 
 
 def test_stack_survey_small(small):
@@ -171,7 +225,8 @@ def test_tiny_images_and_behind_the_plane():
     w = synth.Workload(name="edge", exps=exps, t0=t0, elements=el, D=D, V=V)
     g = gpu_run(w, ids=[0], k=1)
     o = oracle.samples(el, t0, exps, D, V)
-    assert list(g["dbg"]["flags"][0]) == list(o["flags"][0] & 7) == [7, 7, 0]
+    assert list(g["dbg"]["flags"][0] & 7) == list(o["flags"][0] & 7) == [7, 7, 0]
+    assert np.all((g["dbg"]["flags"][0] & 8) != 0)   # the exact walk solves every sample
     snr, flux, nv = oracle.stack(el, t0, exps, D, V)
     assert snr_close(g["snr"], snr).all() and g["nv"][0] == nv[0] == 2
 
@@ -479,35 +534,42 @@ def test_gather_replay_equals_stack(small):
     w = small
     g = gpu_run(w, ids=np.arange(w.elements.shape[0]))
     ctx, patch, orb, _, _ = g["_keep"]
-    ids = np.arange(orb.n)
-    off = dt.record_gathers(patch, orb, ids)
-    snr = dt.gather_replay(patch, off)
+    rec = dt.record_valid_gathers(patch, orb)
+    snr = dt.replay_valid_gathers(patch, rec)
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(snr.cpu().numpy(), np.where(g["nv"] >= 0, g["snr"], 0.0).astype(np.float32))
-    # offsets agree with the debug table: valid samples only, epoch order
-    o = off.cpu().numpy()
-    order = np.argsort([x["t"] for x in w.exps], kind="stable")
+    np.testing.assert_array_equal(snr.cpu().numpy(), np.where(g["nv"] > 0, g["snr"], 0.0).astype(np.float32))
+    # the recorded offsets are the exact walk's inside samples, in epoch order
+    lists = decode_gathers(rec)
     dbg = g["dbg"]
-    valid = (dbg["flags"] & 4) != 0
-    np.testing.assert_array_equal((o != -1).T, valid[:, order])
-    sizes = np.array([x["width"] * x["height"] for x in w.exps])[order]
-    base = np.concatenate([[0], np.cumsum(sizes)[:-1]])
-    W = np.array([x["width"] for x in w.exps])[order]
-    want = base[None, :] + dbg["iy"][:, order].astype(np.int64) * W[None, :] + dbg["ix"][:, order]
-    np.testing.assert_array_equal(o.T[valid[:, order]], want[valid[:, order]])
+    want, order = plane_offsets(dbg, w.exps)
+    inside = ((dbg["flags"] & 2) != 0)[:, order]
+    assert rec.count == int(inside.sum())
+    for i in range(orb.n):
+        k = int(inside[i].sum())
+        np.testing.assert_array_equal(lists[i, :k], want[i][inside[i]])
+        assert np.all(lists[i, k:] == -1)
 
 
 def _pruned_vs_exact(w):
     import torch
     import paper_2503_08854_amd as dt
-    g = gpu_run(w)
+    ids = np.arange(w.elements.shape[0])
+    g = gpu_run(w, ids=ids)
     ctx, patch, orb, _, _ = g["_keep"]
-    off = dt.record_gathers(patch, orb, np.arange(orb.n))
-    snr = dt.gather_replay(patch, off)
+    rec = dt.record_valid_gathers(patch, orb)
+    snr = dt.replay_valid_gathers(patch, rec)
     torch.cuda.synchronize()
-    nv_exact = (off.cpu().numpy() != -1).sum(axis=0)
+    nv_exact = ((g["dbg"]["flags"] & 4) != 0).sum(axis=1)
     np.testing.assert_array_equal(np.maximum(g["nv"], 0), nv_exact)
-    np.testing.assert_array_equal(snr.cpu().numpy(), np.where(g["nv"] >= 0, g["snr"], 0.0).astype(np.float32))
+    np.testing.assert_array_equal(snr.cpu().numpy(), np.where(g["nv"] > 0, g["snr"], 0.0).astype(np.float32))
+    # the walk the stack runs solves every sample the exact walk finds inside, identically
+    st = {k: v.cpu().numpy() for k, v in dt.debug_samples(patch, orb, ids, walk="stack").items()}
+    ex = g["dbg"]
+    inside = (ex["flags"] & 2) != 0
+    assert np.all((st["flags"][inside] & 8) != 0)
+    np.testing.assert_array_equal(st["ix"][inside], ex["ix"][inside])
+    np.testing.assert_array_equal(st["iy"][inside], ex["iy"][inside])
+    np.testing.assert_array_equal(st["flags"][inside] & 7, ex["flags"][inside] & 7)
     return int(nv_exact.sum())
 
 
