@@ -46,10 +46,11 @@ FLOPS_PER_SOLVE = 125
 FLOPS_PER_TAIL_SAMPLE = 82
 FLOPS_PER_TAIL_FULL = 60
 CK_SPAN_DAYS = 16.0  # the kernel's checkpoint span (epoch days)
-# HBM bytes of one full-size stack launch on the survey workload from the
-# committed FETCH_SIZE / WRITE_SIZE passes; reported only while the kernel's
-# sources are the ones those counters were taken on.
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_stack_track_survey_traffic.json")
+# HBM bytes of one full-size stack launch per workload from the committed
+# FETCH_SIZE / WRITE_SIZE passes; reported only while the kernel's sources
+# are the ones those counters were taken on.
+TRAFFIC_RECORDS = {"survey": os.path.join(ROOT, "profiles", "k_stack_track_survey_traffic.json"),
+                   "distant": os.path.join(ROOT, "profiles", "k_stack_generated_track_distant_traffic.json")}
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
@@ -71,11 +72,10 @@ def checkpoints(exps):
 def stack_traffic(workload_name):
     import hashlib
     import json as _json
-    if not os.path.exists(TRAFFIC_RECORD):
+    path = TRAFFIC_RECORDS.get(workload_name)
+    if path is None or not os.path.exists(path):
         return None
-    rec = _json.load(open(TRAFFIC_RECORD))
-    if rec.get("workload", "survey") != workload_name:
-        return None
+    rec = _json.load(open(path))
     h = hashlib.sha256()
     for f in rec["sources"]:
         h.update((hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() + "  " + f + "\n").encode())
@@ -520,7 +520,7 @@ def _yardstick(patch, sub, stack_fn, dev, reps=3):
     useful = 8.0 * valid
     res = dict(orbits=m, valid_samples=valid, dense_samples=m * patch.n_exp, stack_ms=t_stack, replay_ms=t_rep,
                stack_useful_GBs=useful / (t_stack * 1e-3) / 1e9, replay_useful_GBs=useful / (t_rep * 1e-3) / 1e9,
-               replay_index_bytes=float(rec.index_bytes), frac_of_achievable_gather=t_rep / t_stack,
+               replay_index_bytes_read_max=8.0 * (valid + 7 * m), frac_of_achievable_gather=t_rep / t_stack,
                replay_equals_stack=same)
     log(f"gather yardstick: stack {t_stack:.3f} ms vs replay {t_rep:.3f} ms on {m} orbits, {valid} valid gathers "
         f"({t_rep / t_stack:.2f} of the achievable gather rate)")

@@ -121,6 +121,30 @@ StackArgs stack_args(const dt_patch* p, const dt_orbits* o) {
   return a;
 }
 
+dt_status defer_setup(dt_ctx* c, int64_t n, StackArgs& a) {
+  const int64_t need = (n + 63) / 64;
+  if (!c->d_defer_count) {
+    dt_status st = ctx_alloc(c, reinterpret_cast<void**>(&c->d_defer_count), sizeof(unsigned int), "deferral count");
+    if (st != DT_OK) return st;
+  }
+  if (need > c->defer_cap) {
+    // the old list may still be read by enqueued work: wait before freeing it
+    if (c->d_defer) {
+      hipError_t e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return hip_fail(e, "deferral list resize");
+      ctx_free(c, c->d_defer, sizeof(int64_t) * c->defer_cap);
+      c->d_defer = nullptr;
+      c->defer_cap = 0;
+    }
+    dt_status st = ctx_alloc(c, reinterpret_cast<void**>(&c->d_defer), sizeof(int64_t) * need, "deferral list");
+    if (st != DT_OK) return st;
+    c->defer_cap = need;
+  }
+  a.defer_list = c->d_defer;
+  a.defer_count = c->d_defer_count;
+  return DT_OK;
+}
+
 dt_status run_prepass(dt_patch* p, hipStream_t s) {
   if (p->images_released) return fail(DT_E_STATE, "the patch's images were released; the pre-pass cannot run");
   if (p->est_noise) {
@@ -194,6 +218,8 @@ dt_status dt_ctx_destroy(dt_ctx* c) {
   ctx_free(c, c->noise_ws, c->noise_bytes);
   ctx_free(c, c->d_counter, sizeof(unsigned long long));
   ctx_free(c, c->d_work, sizeof(unsigned long long) * WORK_SLOTS * WORK_N);
+  ctx_free(c, c->d_defer, sizeof(int64_t) * c->defer_cap);
+  ctx_free(c, c->d_defer_count, sizeof(unsigned int));
   c->alive = false;
   delete c;
   return DT_OK;
@@ -477,6 +503,10 @@ dt_status dt_stack(dt_patch* p, const dt_orbits* o, float* d_snr, float* d_flux,
   a.snr = d_snr;
   a.flux = d_flux;
   a.nvalid = d_nvalid;
+  if (o->n > 0 && p->vobs < __builtin_inf()) {
+    st = defer_setup(p->ctx, o->n, a);
+    if (st != DT_OK) return st;
+  }
   hipError_t e = launch_stack(a, p->ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "stack launch");
   return DT_OK;

@@ -86,6 +86,12 @@ struct StackArgs {
   // Work counters of the checkpoint walk (measurement only; NULL = off):
   // WORK_SLOTS slots of WORK_N counters, slot = workgroup index mod WORK_SLOTS.
   unsigned long long* work = nullptr;
+  // Deferral (NULL = not allowed): a wavefront of the checkpoint walk whose
+  // samples land often appends its first orbit index to defer_list (slot from
+  // *defer_count, zeroed before the launch) and writes no outputs; the
+  // deferred-walk kernel then stacks those orbits per sample.
+  int64_t* defer_list = nullptr;
+  unsigned int* defer_count = nullptr;
 };
 
 // Work counters (one slot; see dt_ctx_count_work): samples tested by
@@ -111,7 +117,11 @@ struct WorkItem {
   int64_t begin;
 };
 
+// The stack: the checkpoint walk (then, when a.defer_list is set, the
+// per-sample walk of the wavefronts it deferred), or the per-sample walk for
+// an unbounded observer speed.
 hipError_t launch_stack(const StackArgs& a, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, hipStream_t s);
 hipError_t launch_batched(const StackArgs* d_descs, const WorkItem* d_items, int n_items, unsigned int* d_counter,
                           int n_wg, hipStream_t s);
 hipError_t launch_debug(const StackArgs& a, const DebugArgs& d, hipStream_t s);

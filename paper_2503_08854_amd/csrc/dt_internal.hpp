@@ -31,6 +31,9 @@ struct dt_ctx {
   hipStream_t capture_stream = nullptr;
   unsigned long long* d_work = nullptr;  // work counters (dt_ctx_count_work), WORK_SLOTS x WORK_N
   bool count_work = false;
+  int64_t* d_defer = nullptr;            // deferral list of the checkpoint walk (first orbit of 64)
+  int64_t defer_cap = 0;                 // its entries
+  unsigned int* d_defer_count = nullptr;
   bool alive = true;
 };
 
@@ -66,6 +69,9 @@ namespace dtk {
 dt_status ctx_alloc(dt_ctx* c, void** p, size_t bytes, const char* what);
 void ctx_free(dt_ctx* c, void* p, size_t bytes);
 dt_status check_orbits(const dt_orbits* o);
+// Deferral list for a checkpoint-walk launch of n orbits (grown on demand);
+// sets a.defer_list / a.defer_count.
+dt_status defer_setup(dt_ctx* c, int64_t n, StackArgs& a);
 StackArgs stack_args(const dt_patch* p, const dt_orbits* o);
 dt_status run_prepass(dt_patch* p, hipStream_t s);
 void batch_graph_drop(dt_ctx* c);

@@ -110,6 +110,10 @@ dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t fir
   a.snr = d_snr;
   a.flux = d_flux;
   a.nvalid = d_nvalid;
+  if (n > 0 && p->vobs < __builtin_inf()) {
+    st = defer_setup(p->ctx, n, a);
+    if (st != DT_OK) return st;
+  }
   hipError_t e = launch_stack_generated(a, *S, first, p->ctx->stream);
   return e == hipSuccess ? DT_OK : hip_fail(e, "generate-and-stack launch");
 }

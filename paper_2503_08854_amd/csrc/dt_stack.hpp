@@ -45,7 +45,8 @@ __device__ __forceinline__ void rec_sample(const DebugArgs& d, int n_exp, int64_
 }
 
 // Compensated sums of one prepared orbit over exposures [ex0, ex0 + cnt)
-// (epoch order; no debug table).  Each gather is accumulated one exposure
+// (epoch order; REC: the debug table of the samples solved; n_full counts
+// the samples that took the full path, in a register).  Each gather is accumulated one exposure
 // later, still in epoch order, so its load latency overlaps the next sample's
 // arithmetic (deeper deferral measured slower: the loads are conditional, so
 // the wait before a use covers all of them).
@@ -55,7 +56,7 @@ struct StackPart {
 };
 template <bool REC = false>
 __device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob, int ex0, int cnt, StackPart& P,
-                                            const DebugArgs* dbg = nullptr, int64_t row = 0) {
+                                            const DebugArgs* dbg, int64_t row, int& n_full) {
   P.ps.init();
   P.ph.init();
   P.nv = 0;
@@ -72,8 +73,15 @@ __device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob,
     take(pend);
     pend = so.inside ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
     if (REC && so.solved) rec_sample(*dbg, A.n_exp, row, x, so, pend);
+    n_full += so.solved ? 1 : 0;
   });
   take(pend);
+}
+template <bool REC = false>
+__device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob, int ex0, int cnt, StackPart& P,
+                                            const DebugArgs* dbg = nullptr, int64_t row = 0) {
+  int n_full = 0;
+  stack_range<REC>(A, ob, ex0, cnt, P, dbg, row, n_full);
 }
 
 // S/N = Psi / sqrt(Phi), flux = Psi / Phi (0 when Phi = 0).

@@ -25,10 +25,12 @@
 // per-sample walk.
 //
 // The prediction pays while most samples miss.  A wavefront whose orbits land
-// often (more than TRACK_SWITCH of its lane-exposures queued, e.g. distant
-// objects followed by the field for months) serves its queue and walks the
-// remaining exposures per sample instead, warm from each lane's checkpoint,
-// with the per-sample walk's own sky-cone test; the sums keep epoch order.
+// often (more than TRACK_SWITCH of its lane-exposures queued, once
+// TRACK_SWITCH_MIN exposures are tested, e.g. distant objects the field
+// follows for months) gives its orbits up when the launch allows it:
+// it appends its first orbit index to the deferral list and writes nothing;
+// a second, persistent kernel walks the deferred wavefronts per sample from
+// the first exposure (the per-sample walk's own sky-cone test, no queue).
 #pragma once
 #include "dt_stack.hpp"
 
@@ -41,7 +43,7 @@ constexpr int TQ_CAP = 128;          // queued samples per wavefront (< 64 held 
 constexpr int TQ_LIST = 8;           // queued samples per lane between flushes
 constexpr int CK_ANCHOR = 8;         // checkpoints between full sincos re-anchors of sin E, cos E
 constexpr float TRACK_SWITCH = 0.05f; // queued fraction of lane-exposures above which a wavefront walks per sample
-constexpr int TRACK_SWITCH_MIN = 8;   // exposures walked before the fraction is trusted
+constexpr int TRACK_SWITCH_MIN = 3;   // exposures tested before the fraction is trusted
 
 // One wavefront's state in LDS: the queue, and each lane's prepared orbit and
 // checkpoint Kepler state (read by whichever lane solves that orbit's queued
@@ -76,67 +78,6 @@ __device__ __forceinline__ void track_bound(double a, double e, const Orbit& o, 
   b.vmax = vmax;
 }
 
-// Per-sample tail of a wavefront's walk from exposure ex on (see the file
-// comment): Kepler warm from the lane's checkpoint state in Qm, the light
-// time started at tg0 (this exposure's predicted distance; rate 0 until the
-// second tail sample), the per-sample walk's sky-cone test, gathers
-// accumulated one exposure later, added to P in epoch order.  The prepared
-// orbit comes back from LDS (held in registers through the main loop it
-// would spill); its cone slack mq is formed from vmax as orbit_prep forms it
-// (vmax < 0: bound coefficients overflowed, never pruned).
-template <bool REC>
-__device__ __forceinline__ void track_tail(const StackArgs& A, TrackQueue& Qm, int ex, double tg0,
-                                                     double vmax, bool live, StackPart& P, int& n_full,
-                                                     const DebugArgs* dbg, int64_t rowbase) {
-  volatile LdsTrackQueue& Q = *(volatile LdsTrackQueue*)(&Qm);
-  const int lane = (int)__lane_id();
-  const ExpMeta* __restrict__ meta = A.meta;
-  Orbit ot;
-  ot.e = Q.orb[0][lane];
-  ot.n = Q.orb[1][lane];
-  ot.m0 = Q.orb[2][lane];
-  ot.aP0 = Q.orb[3][lane];
-  ot.aP1 = Q.orb[4][lane];
-  ot.aP2 = Q.orb[5][lane];
-  ot.bQ0 = Q.orb[6][lane];
-  ot.bQ1 = Q.orb[7][lane];
-  ot.bQ2 = Q.orb[8][lane];
-  ot.he = -0.5 * ot.e;
-  ot.mq = vmax >= 0.0 ? 1.1002 * LT_LINEAR_MAX * vmax * (1.0 + vmax * (1.0 / C_AU_DAY)) : __builtin_inf();
-  KepState k;
-  k.E = Q.kep[0][lane];
-  k.sE = Q.kep[1][lane];
-  k.cE = Q.kep[2][lane];
-  k.g = Q.kep[3][lane];
-  k.M = fma(-ot.e, k.sE, k.E);
-  LtState lt;
-  lt.tau = tg0;
-  lt.rate = 0.0;
-  float2 pend = make_float2(0.f, 0.f);
-  const int ex0 = ex;
-#pragma unroll 1
-  for (; ex < A.n_exp; ++ex) {
-    const ExpMeta& x = meta[ex];
-    SampleOut so;
-    const bool first = ex == ex0;
-    sample<false, false>(ot, k, lt, x, A.epoch, first ? 0.0 : x.gap, first ? 0.0 : x.inv_gap,
-                         !first && (ex % ANCHOR) == 0, so);
-    if (pend.y > 0.f) {
-      P.ps.add(pend.x);
-      P.ph.add(pend.y);
-      P.nv++;
-    }
-    pend = (live && so.inside) ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
-    if (REC && live && so.solved) rec_sample(*dbg, A.n_exp, rowbase + lane, x, so, pend);
-    n_full += __builtin_popcountll(__builtin_amdgcn_ballot_w64(live && so.solved));
-  }
-  if (pend.y > 0.f) {
-    P.ps.add(pend.x);
-    P.ph.add(pend.y);
-    P.nv++;
-  }
-}
-
 // The walk of one wavefront.  All 64 lanes call it together; lanes with
 // live = false (no orbit, or one outside the domain) carry any valid
 // prepared orbit and queue nothing.  P receives each live lane's sums.
@@ -146,15 +87,16 @@ __device__ __forceinline__ void track_tail(const StackArgs& A, TrackQueue& Qm, i
 // a lane's list is full, or after the last exposure; then the checkpoint
 // solve of every lane when due.  Both are one loop over jobs so the exact
 // solve exists once in the code.  Then the cone test of the prediction
-// queues the samples that may land.  After a service step the wavefront may
-// leave the prediction for the per-sample tail (see the file comment).
+// queues the samples that may land.  After a cone test a wavefront of a
+// launch that allows it may give its orbits up (*deferred = true; P is then
+// meaningless), see the file comment.
 //
 // REC (debug kernels only): every sample the walk solves exactly is written
 // to row rowbase + lane of dbg (the owner's row for queued samples).
 template <bool REC = false>
 __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, const TrackBound& bd, bool live,
-                                           TrackQueue& Qm, StackPart& P, const DebugArgs* dbg = nullptr,
-                                           int64_t rowbase = 0) {
+                                           TrackQueue& Qm, StackPart& P, bool& deferred,
+                                           const DebugArgs* dbg = nullptr, int64_t rowbase = 0) {
   // LDS address space explicitly: volatile accesses through a generic pointer
   // would be kept generic (flat) by the compiler
   volatile LdsTrackQueue& Q = *(volatile LdsTrackQueue*)(&Qm);
@@ -191,8 +133,8 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   int queued = 0;    // samples queued so far (wave-uniform)
   bool full = false; // the queue must be served before more samples are pushed
   int ex = 0;
-  bool tail = false; // leave the prediction at exposure ex for the per-sample walk
-  double tg_tail = 0.0;
+  bool tail = false; // give the orbits up for the per-sample walk
+  const bool may_defer = A.defer_list != nullptr;
 
   for (; ex <= A.n_exp && !tail; ++ex) {
     const bool last = ex == A.n_exp;
@@ -297,9 +239,6 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
         queued += count;
         count = 0;
         len = 0;
-        // most samples land: walk the rest per sample (the checkpoint due at
-        // this exposure, if any, has just been taken and starts the tail)
-        tail = !last && ex >= TRACK_SWITCH_MIN && (float)queued > TRACK_SWITCH * 64.f * (float)ex;
       }
       // prediction state from the checkpoint kept in LDS (recomputed after every
       // service step, so it holds no registers while the solves run): the
@@ -346,8 +285,6 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
     const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
     const double m = fma(j6 * D * D, D, fma(l1, D, s0));
     const double R = fma(x.cone_tan, sc, m);
-    // leaving for the tail: this exposure's predicted distance starts its light time
-    tg_tail = d2 * __builtin_amdgcn_rsq(d2) * IC;
     const bool may = live & !tail & (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
     const uint64_t mask = __builtin_amdgcn_ballot_w64(may);
     if (mask) {
@@ -361,32 +298,31 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       }
       count += __builtin_popcountll(mask);
       full = count >= 64 || __builtin_amdgcn_ballot_w64(len >= TQ_LIST) != 0;
+      // most samples may land: leave these orbits to the per-sample walk
+      // (nothing queued is served; the loop ends at its next test)
+      tail = may_defer && ex + 1 >= TRACK_SWITCH_MIN &&
+             (float)(queued + count) > TRACK_SWITCH * 64.f * (float)(ex + 1);
     }
   }
-  int n_full = 0;
-  if (tail) track_tail<REC>(A, Qm, ex - 1, tg_tail, bounded ? vmax : -1.0, live, P, n_full, dbg, rowbase);
+  deferred = tail;
   const unsigned long long nl = (unsigned long long)__builtin_popcountll(__builtin_amdgcn_ballot_w64(live));
   if (A.work && lane == 0) {
     // wave totals (uniform values) into this workgroup's slot
     unsigned long long* w = A.work + WORK_N * (blockIdx.x % WORK_SLOTS);
-    const int ex_pred = tail ? ex - 1 : A.n_exp;
-    atomicAdd(w + WORK_PRED, nl * (unsigned long long)ex_pred);
+    atomicAdd(w + WORK_PRED, nl * (unsigned long long)(tail ? ex : A.n_exp));  // a deferral ends the loop after the cone test of ex - 1
     atomicAdd(w + WORK_QUEUED, (unsigned long long)queued);
     atomicAdd(w + WORK_CKPT, nl * (unsigned long long)n_ck);
-    if (tail) {
-      atomicAdd(w + WORK_TAIL, nl * (unsigned long long)(A.n_exp - ex_pred));
-      atomicAdd(w + WORK_TAIL_FULL, (unsigned long long)n_full);
-      atomicAdd(w + WORK_SWITCHED, 1ull);
-    }
+    if (tail) atomicAdd(w + WORK_SWITCHED, 1ull);
   }
 }
 
 // One lane's orbit through the walk of its wavefront: `el` holds the
 // elements when `live` (any values otherwise); the outputs are those of the
-// per-sample stack (NaN, NaN, -1 for an orbit that is not live).  All 64
-// lanes of the wavefront call it together; Q is the wavefront's LDS queue.
+// per-sample stack (NaN, NaN, -1 for an orbit that is not live), or nothing
+// when the wavefront deferred its orbits (returns true).  All 64 lanes of the
+// wavefront call it together; Q is the wavefront's LDS queue.
 template <bool REC = false>
-__device__ __forceinline__ void track_stack_lane(const StackArgs& A, const double el[6], bool live, TrackQueue& Q,
+__device__ __forceinline__ bool track_stack_lane(const StackArgs& A, const double el[6], bool live, TrackQueue& Q,
                                                  float& snr, float& flux, int& nv, const DebugArgs* dbg = nullptr,
                                                  int64_t rowbase = 0) {
   double a = el[0], e = el[1], inc = el[2], node = el[3], peri = el[4], m0 = el[5];
@@ -399,10 +335,48 @@ __device__ __forceinline__ void track_stack_lane(const StackArgs& A, const doubl
   TrackBound bd;
   track_bound(a, e, ob, A.vobs, bd);
   StackPart P;
-  track_walk<REC>(A, ob, bd, live, Q, P, dbg, rowbase);
+  bool deferred = false;
+  track_walk<REC>(A, ob, bd, live, Q, P, deferred, dbg, rowbase);
   snr = flux = __builtin_nanf("");
   nv = -1;
+  if (deferred) return true;
   if (live) stack_finish(P, snr, flux, nv);
+  return false;
+}
+
+// A deferring wavefront's list entry: its first orbit index (lane 0 writes).
+__device__ __forceinline__ void defer_wave(const StackArgs& A, int64_t first) {
+  if (__lane_id() == 0) {
+    const unsigned int slot = atomicAdd(A.defer_count, 1u);
+    A.defer_list[slot] = first;
+  }
+}
+
+// Per-sample walk of orbit o (its elements el, valid when live) for the
+// deferred wavefronts: the walk of stack_walk, with the work counters.
+__device__ __forceinline__ void deferred_lane(const StackArgs& A, const double el[6], bool live, float& snr,
+                                              float& flux, int& nv) {
+  snr = flux = __builtin_nanf("");
+  nv = -1;
+  StackPart P;
+  int n_full = 0;
+  if (live) {
+    Orbit ob;
+    orbit_prep(el[0], el[1], el[2], el[3], el[4], el[5], ob);
+    stack_range(A, ob, 0, A.n_exp, P, nullptr, 0, n_full);
+    stack_finish(P, snr, flux, nv);
+  }
+  if (A.work) {
+    const unsigned long long nl = (unsigned long long)__builtin_popcountll(__builtin_amdgcn_ballot_w64(live));
+    int tot = n_full;  // wavefront sum
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) tot += __shfl_xor(tot, m, 64);
+    if (__lane_id() == 0) {
+      unsigned long long* w = A.work + WORK_N * (blockIdx.x % WORK_SLOTS);
+      atomicAdd(w + WORK_TAIL, nl * (unsigned long long)A.n_exp);
+      atomicAdd(w + WORK_TAIL_FULL, (unsigned long long)tot);
+    }
+  }
 }
 
 }  // namespace dtk

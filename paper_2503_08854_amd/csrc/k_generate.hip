@@ -123,7 +123,32 @@ __global__ __launch_bounds__(256, 4) void k_stack_generated_track(StackArgs A, d
                     orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
   float snr, flux;
   int nv;
-  track_stack_lane(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv);
+  if (track_stack_lane(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv)) {
+    defer_wave(A, i - (int64_t)__lane_id());
+    return;
+  }
+  if (!in) return;
+  if (A.snr) A.snr[i] = snr;
+  if (A.flux) A.flux[i] = flux;
+  if (A.nvalid) A.nvalid[i] = nv;
+}
+
+// The deferred wavefronts of k_stack_generated_track, walked per sample: one
+// wavefront per list entry (the first orbit index of 64); wavefronts past the
+// number of entries return at once.  (A persistent loop over the entries kept
+// loop-invariant sampler and metadata values live across the walk and
+// spilled.)
+__global__ __launch_bounds__(256, 4) void k_stack_generated_deferred(StackArgs A, dt_orbit_sampler S, int64_t first) {
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= (int64_t)*A.defer_count) return;
+  const int64_t i = A.defer_list[j] + (int64_t)__lane_id();
+  const bool in = i < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool live = in && gen_orbit(S, (uint64_t)(first + i), el) &&
+                    orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
+  float snr, flux;
+  int nv;
+  deferred_lane(A, el, live, snr, flux, nv);
   if (!in) return;
   if (A.snr) A.snr[i] = snr;
   if (A.flux) A.flux[i] = flux;
@@ -140,10 +165,18 @@ hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, 
 
 hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  if (a.vobs < __builtin_inf())
+  if (a.vobs < __builtin_inf()) {
+    if (a.defer_list) {
+      hipError_t e = launch_zero_u32(a.defer_count, s);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_stack_generated_track, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
-  else
+    if (a.defer_list)
+      hipLaunchKernelGGL(k_stack_generated_deferred, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S,
+                         first);
+  } else {
     hipLaunchKernelGGL(k_stack_generated, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
+  }
   return hipGetLastError();
 }
 

@@ -41,13 +41,39 @@ __global__ __launch_bounds__(256, 4) void k_stack_track(StackArgs A) {
   }
   float snr, flux;
   int nv;
-  track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr,
-                   flux, nv);
+  if (track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr,
+                       flux, nv)) {
+    defer_wave(A, o - (int64_t)__lane_id());
+    return;
+  }
   if (!in) return;
   if (A.snr) A.snr[o] = snr;
   if (A.flux) A.flux[o] = flux;
   if (A.nvalid) A.nvalid[o] = nv;
 }
+
+// The wavefronts k_stack_track deferred, walked per sample: one wavefront
+// per list entry (the first orbit of 64); wavefronts past the number of
+// entries return at once.
+__global__ __launch_bounds__(256, 4) void k_stack_deferred(StackArgs A) {
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= (int64_t)*A.defer_count) return;
+  const int64_t o = A.defer_list[j] + (int64_t)__lane_id();
+  const bool in = o < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (in) {
+    el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+  }
+  float snr, flux;
+  int nv;
+  deferred_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), snr, flux, nv);
+  if (!in) return;
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
 
 __global__ __launch_bounds__(64) void k_stack_debug(StackArgs A, DebugArgs D) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -82,8 +108,18 @@ __global__ __launch_bounds__(256, 4) void k_stack_track_debug(StackArgs A, Debug
   __syncthreads();  // the rows' initial values land before any lane's solves overwrite them
   float snr, flux;
   int nv;
-  track_stack_lane<true>(A, el, has && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6],
-                         snr, flux, nv, &D, r - lane);
+  const bool live = has && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
+  if (track_stack_lane<true>(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv, &D, r - lane)) {
+    // deferred: as the deferred-walk kernel, the per-sample walk from the start
+    __threadfence_block();
+    if (in) rec_init_row(D, A.meta, A.n_exp, r);
+    if (live) {
+      Orbit ob;
+      orbit_prep(el[0], el[1], el[2], el[3], el[4], el[5], ob);
+      StackPart P;
+      stack_range<true>(A, ob, 0, A.n_exp, P, &D, r);
+    }
+  }
 }
 
 __global__ __launch_bounds__(64) void k_stack_walk_debug(StackArgs A, DebugArgs D) {
@@ -139,9 +175,11 @@ __global__ __launch_bounds__(256) void k_record_gathers(StackArgs A, int64_t* __
   }
 }
 
-// Lane o loads its recorded offsets (eight gathers in flight; a padded slot
-// reads the first plane element and drops it) and sums them exactly as the
-// stack does, in epoch order: its S/N equals the stack's.
+// Lane o loads its recorded offsets (eight gathers in flight; a slot past
+// the lane's list reads the first plane element and drops it) and sums them
+// exactly as the stack does, in epoch order: its S/N equals the stack's.  A
+// lane's list is compacted, so it stops after the batch that reaches its
+// first -1: at most REPLAY_DEPTH - 1 padding entries are read per lane.
 constexpr int REPLAY_DEPTH = 8;
 __global__ __launch_bounds__(256) void k_gather_replay(const float2* __restrict__ planes,
                                                        const int64_t* __restrict__ gstart,
@@ -157,8 +195,9 @@ __global__ __launch_bounds__(256) void k_gather_replay(const float2* __restrict_
   Kahan ps, ph;
   ps.init();
   ph.init();
+  bool done = false;
 #pragma unroll 1
-  for (int64_t k = 0; k < w; k += REPLAY_DEPTH) {
+  for (int64_t k = 0; k < w && !done; k += REPLAY_DEPTH) {
     int64_t off[REPLAY_DEPTH];
     float2 v[REPLAY_DEPTH];
 #pragma unroll
@@ -172,6 +211,7 @@ __global__ __launch_bounds__(256) void k_gather_replay(const float2* __restrict_
         ph.add(v[j].y);
       }
     }
+    done = off[REPLAY_DEPTH - 1] < 0;
   }
   const float Psi = ps.s - ps.c, Phi = ph.s - ph.c;
   snr[o] = Phi > 0.f ? Psi / sqrtf(Phi) : 0.f;
@@ -195,10 +235,18 @@ hipError_t launch_gather_replay(const float2* planes, const int64_t* gstart, con
 
 hipError_t launch_stack(const StackArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
-  if (a.vobs < __builtin_inf())
+  if (a.vobs < __builtin_inf()) {
+    if (a.defer_list) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, a.defer_count);
     hipLaunchKernelGGL(k_stack_track, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
-  else
+    if (a.defer_list) hipLaunchKernelGGL(k_stack_deferred, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+  } else {
     hipLaunchKernelGGL(k_stack, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned int* p, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, p);
   return hipGetLastError();
 }
 

@@ -271,20 +271,24 @@ def reference_orbit_general(rng, obs, a_rng, e_rng, inc_rng, near_earth=False):
 
 
 def batched(seed=4, n_patches=64, ne_rng=(30, 400), side_rng=(512, 2048), no_rng=(1e4, 1e6), span=30.0,
-            name="batched", n_near=4, width_step=64):
+            name="batched", n_near=4, width_step=64, extra=()):
     """Uneven patches: N_e log-uniform, square sides uniform on a 64-px grid,
     N_o log-uniform, FP16 images, NEO-to-MBA elements (a 0.8-3.5 AU,
     e 0-0.6, i 0-30 deg), one injection on each patch's reference orbit at
-    per-image S/N 1; the first n_near patches are near-Earth geometries."""
+    per-image S/N 1; the first n_near patches are near-Earth geometries.
+    `extra` appends patches of given (exposures, span in days, side, orbits)."""
     rng = synth.make_rng(seed, 9)
     patches = []
     p2 = sum_p2(3.0)
-    for p in range(n_patches):
+    for p in range(n_patches + len(extra)):
         ne = int(round(math.exp(rng.uniform(math.log(ne_rng[0]), math.log(ne_rng[1])))))
         side = int(rng.integers(side_rng[0] // width_step, side_rng[1] // width_step + 1)) * width_step
         no = int(round(math.exp(rng.uniform(math.log(no_rng[0]), math.log(no_rng[1])))))
+        p_span = span
+        if p >= n_patches:
+            ne, p_span, side, no = extra[p - n_patches]
         prng = synth.make_rng(seed, 10, p)
-        t, t0 = make_epochs(prng, ne, span)
+        t, t0 = make_epochs(prng, ne, p_span)
         lam = float(prng.uniform(0, 2 * math.pi))
         obs0 = synth.observer_circular([t0], t0, lam)[0]
         el_ref = reference_orbit_general(prng, obs0, (0.8, 3.5), (0.0, 0.6), (0.0, 30.0), near_earth=p < n_near)
@@ -300,9 +304,10 @@ def batched(seed=4, n_patches=64, ne_rng=(30, 400), side_rng=(512, 2048), no_rng
 
 def batched_small(seed=5):
     """Scaled-down batch for full oracle parity: 6 patches, N_e 5-40,
-    sides 128-320, N_o 300-3000, one near-Earth patch."""
+    sides 128-320, N_o 300-3000, one near-Earth patch, plus one patch of 90
+    exposures over 200 days (a dozen checkpoints and their re-anchors per orbit)."""
     return batched(seed=seed, n_patches=6, ne_rng=(5, 40), side_rng=(128, 320), no_rng=(300, 3000), span=6.0,
-                   name="batched_small", n_near=1, width_step=64)
+                   name="batched_small", n_near=1, width_step=64, extra=[(90, 200.0, 256, 2000)])
 
 
 def learned(seed=2, n_cells=10000, cell_size=1000, n_real=50, n_inj=20, name="learned", base=None,
