@@ -24,6 +24,17 @@
  *   - All GPU work is enqueued on the context's HIP stream; outputs are valid
  *     after that stream is synchronised.  A context is used by one host thread.
  *   - Units: days, AU, radians for orbital elements, degrees for WCS.
+ *
+ * Entry points by step of the method
+ *   image set, exposure metadata, matched-filter planes: dt_patch_create
+ *   propagate, project, gather, stack (orbits in HBM): dt_stack
+ *   the same with orbits drawn on the device:           dt_stack_generated
+ *   many patches in one persistent launch:               dt_stack_batched
+ *   threshold + top-k selection:                         dt_topk (dt_topk_noalloc)
+ *   learned cell proposer: dt_cell_stamps, dt_scorer_*, dt_cell_members_near,
+ *                          dt_stack_ids, dt_stack_cells
+ *   checking only: dt_debug_samples, dt_debug_stack_samples, dt_record_gathers,
+ *                  dt_gather_replay, dt_ctx_count_work
  */
 #ifndef DTRACK_H
 #define DTRACK_H
@@ -328,7 +339,8 @@ dt_status dt_clip_candidates(dt_patch *p, const dt_orbits *orbits, const int64_t
  * i.e. the paper's stack (Sec. 3) along the linearised tracks of the cell's
  * members.  Plus 16 features per cell: stamp max, centre, mean, std,
  * coverage, lattice distance of the max, fraction of exposures with the
- * representative inside, normalised a, e, i, max over the central 7x7,
+ * representative inside, normalised a, e, i, max over the central 7x7, the
+ * lattice coordinates (u, v) of the max (its first node in row-major order),
  * zeros.  Outputs (device, any may be NULL): stamps n x 441 (row-major) as
  * BF16 and/or FP32, features n x 16 as BF16 and/or FP32.  Enqueued on the
  * context stream; patches of at most 1024 exposures (the walks of a cell
@@ -346,6 +358,41 @@ dt_status dt_cell_stamps(dt_patch *p, const dt_orbits *reps, double da, double d
  * (deterministically for a given selection size). */
 dt_status dt_stack_cells(dt_patch *p, const dt_orbits *grid, const int64_t *d_cells, int64_t n_cells,
                          int32_t cell_size, float *d_snr, float *d_flux, int32_t *d_nvalid);
+
+/* Maximum of each of n_seg consecutive segments of seg values (device FP32
+ * in, device FP32 out, NaN ignored, -inf for a segment of NaN only): the
+ * coarse-to-fine ranking takes each cell's best sub-representative (Sec.
+ * 5.2.2).  Enqueued, no synchronisation. */
+dt_status dt_segment_max(dt_ctx *ctx, const float *d_x, int64_t n_seg, int32_t seg, float *d_out);
+
+/* Members of selected cells near their stamp peak (fine stacking around a
+ * coarse peak, Sec. 5.2.2): for each of the n_cells selected cells c (device
+ * int64 ids; negative ids are skipped) of a cell-major grid, member m
+ * (orbit c * cell_size + m; the representative is member 0) sits at lattice
+ * coordinates u = (a_m - a_rep) / da, v = (M0_m - M0_rep) / dm; it is listed
+ * when |u - u*| <= radius and |v - v*| <= radius, where (u*, v*) =
+ * (d_uv[c * uv_stride], d_uv[c * uv_stride + 1]) -- features 11 and 12 of
+ * dt_cell_stamps (FP32 output, uv_stride 16) give the stamp maximum's.
+ * d_ids (device, n_cells * cell_size capacity) receives the listed orbit ids
+ * in no particular order and *d_count (device int64) their number; the count
+ * is zeroed first by a kernel, so the call can be captured in a graph.
+ * Nothing synchronises. */
+dt_status dt_cell_members_near(dt_ctx *ctx, const dt_orbits *grid, const int64_t *d_cells, int64_t n_cells,
+                               int32_t cell_size, const float *d_uv, int32_t uv_stride, double da, double dm,
+                               double radius, int64_t *d_ids, int64_t *d_count);
+
+/* The plain stack (as dt_stack) on the orbits of a device id list: the first
+ * *d_count (device int64, at most m_max) entries of d_ids (device int64 ids
+ * into `orbits`; ids outside [0, orbits->n) are skipped).  Outputs are written
+ * at the orbits' own indices of d_snr / d_flux / d_nvalid (device, orbits->n
+ * each); other entries are left untouched.  Valid counts equal dt_stack's
+ * for the same orbits (up to samples within ~1e-11 px of a rounding
+ * boundary); lists of at most 2^18 entries are walked with each orbit's
+ * exposures split over eight wavefronts whose compensated sums are merged
+ * in exposure order, so S/N and flux agree with dt_stack's to rounding.  The
+ * count stays on the device: nothing synchronises. */
+dt_status dt_stack_ids(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, const int64_t *d_count,
+                       int64_t m_max, float *d_snr, float *d_flux, int32_t *d_nvalid);
 
 /* The scorer's GEMM on its own: C = op(A) op(B) (+ bias[n]) (ReLU if relu),
  * BF16 inputs, FP32 accumulation and output (device, row-major with leading
@@ -380,6 +427,13 @@ dt_status dt_scorer_forward(dt_scorer *s, const uint16_t *d_stamps, const uint16
  * roundings it moves.  d_logits: device, B floats. */
 dt_status dt_scorer_infer(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats, int32_t B,
                           float *d_logits);
+/* dt_scorer_infer on selected rows: cell i of the batch (i < B) is row
+ * d_rows[i] (device int64) of d_stamps (rows of 441) and d_feats (rows of
+ * 16), and its logit is written to d_logits[d_rows[i]]; other entries of
+ * d_logits are left untouched (a caller scoring a pre-selected subset of
+ * its cells fills the rest first).  Rows may repeat only with equal logits. */
+dt_status dt_scorer_infer_rows(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats,
+                               const int64_t *d_rows, int32_t B, float *d_logits);
 /* Loss (device float[1], may be NULL) and gradient (device FP32 vector of
  * num_params values, may be NULL) of the mean BCE at the current weights. */
 dt_status dt_scorer_grad(dt_scorer *s, const uint16_t *d_stamps, const uint16_t *d_feats, const float *d_labels,

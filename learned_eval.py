@@ -22,6 +22,10 @@ import numpy as np
 import synth
 
 
+C2F_SUB = 3  # coarse-to-fine: sub-representatives per cell side
+ARTIFACTS = (100, (20.0, 60.0))  # single-exposure point artifacts per image, per-image S/N range
+
+
 @dataclass
 class Setup:
     geom: dict
@@ -66,24 +70,37 @@ class Bench:
         self.coarse = proposer.coarse_patch(ctx, s.exps, self.D, self.V)
         self.grid = dt.OrbitSet(s.el, s.t0, device)
         self.reps = dt.OrbitSet(s.el[::s.cell_size], s.t0, device)
+        self.sub_k = C2F_SUB
+        self.subs = dt.OrbitSet(proposer.sub_representatives(s.el[::s.cell_size], s.da, s.dm, self.sub_k), s.t0,
+                                device)
 
-    def realize(self, seed: int, hits):
-        """Fresh noise (seeded) in place, then sources at hits (e, px, py, flux), then the pre-pass."""
+    def realize(self, seed: int, hits, artifacts=None):
+        """Fresh noise (seeded) in place, then sources at hits (e, px, py, flux),
+        then, with artifacts = (per_image, (s_lo, s_hi)), single-exposure point
+        artifacts of per-image S/N U(s_lo, s_hi) (seeded by the same seed), then
+        the pre-pass."""
         D, V = synth.noise_images(self.s.exps, seed, self.s.geom.get("nan_frac", 0.0), "f32", self.dev)
         for a, b in zip(self.D, D):
             a.copy_(b)
         for a, b in zip(self.V, V):
             a.copy_(b)
         synth.render_sources_fast(self.D, self.s.exps, hits, self.dev)
+        if artifacts:
+            art = synth.artifacts(self.s.exps, artifacts[0], artifacts[1], seed)
+            sig = np.array([x.get("sigma", 1.0) for x in self.s.exps])[art[:, 0].astype(int)]
+            art[:, 3] = art[:, 3] * sig / math.sqrt(_sum_p2(self.s.exps[0]["fwhm"]))
+            synth.render_sources_fast(self.D, self.s.exps, art, self.dev)
         self.patch.refresh()
         self.coarse.refresh()
 
 
-def training_set(bench: Bench, n_real: int, seed: int, pos_frac: float = 0.5, snr_rng=(3.0, 10.0), log=None):
+def training_set(bench: Bench, n_real: int, seed: int, pos_frac: float = 0.5, snr_rng=(3.0, 10.0), log=None,
+                 artifacts=None):
     """Method-generated stacks: per realization, sources on random members of
     pos_frac of the cells (stacked S/N target U(snr_rng) over their hits, the
-    tracks from the stack's own debug table); stamps of every cell; labels
-    1 for injected cells.  Returns device tensors (stamps, feats, labels)."""
+    tracks from the stack's own debug table), optional single-exposure
+    artifacts (see Bench.realize); stamps of every cell; labels 1 for injected
+    cells.  Returns device tensors (stamps, feats, labels)."""
     import torch
     import paper_2503_08854_amd as dt
     from paper_2503_08854_amd import proposer
@@ -102,7 +119,7 @@ def training_set(bench: Bench, n_real: int, seed: int, pos_frac: float = 0.5, sn
         flux = np.where(nh > 0, target / np.sqrt(np.maximum(nh, 1)) / math.sqrt(p2), 0.0)
         ii, ee = np.nonzero(inside)
         hits = np.stack([ee, px[ii, ee], py[ii, ee], flux[ii]], axis=1)
-        bench.realize(seed * 7919 + r, hits)
+        bench.realize(seed * 7919 + r, hits, artifacts)
         st = dt.cell_stamps(bench.patch, bench.reps, s.da, s.dm, bf16=True, f32=False)
         lab = np.zeros(s.n_cells, np.float32)
         lab[cells[nh > 0]] = 1.0
@@ -123,8 +140,69 @@ def train_scorer(ctx, stamps, feats, labels, epochs: int = 2, batch: int = 512, 
     return sc, hist
 
 
-def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None, log=None):
-    """Recall of plain / learned / coarse-max / coarse-to-fine selection over stored realizations, and timings."""
+def _clear(outs):
+    """Mark every output as not computed (NaN S/N and flux, -2 valid count)."""
+    import torch
+    for t in outs:
+        t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
+
+
+def pass_times(bench: Bench, scorer, budgets, radius=None, prefilter=None, artifacts=None, reps: int = 5,
+               seed: int = 10_000):
+    """Wall time (ms, median of reps after one warm-up) of one learned pass and
+    one coarse-max pass at each budget fraction, on one realization."""
+    import torch
+    import paper_2503_08854_amd as dt
+    from paper_2503_08854_amd import proposer
+    s = bench.s
+    bench.realize(seed, np.zeros((0, 4)), artifacts)
+    out = dt.batch_outputs([bench.grid])[0]
+    res = {"learned": [], "coarse": []}
+    for frac in budgets:
+        budget = max(1, int(round(frac * s.n_cells)))
+        pre = None if prefilter is None else max(budget, int(prefilter * s.n_cells))
+        runs = {
+            "learned": lambda: proposer.run_learned(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da,
+                                                    s.dm, scorer, budget, out=out, radius=radius, prefilter=pre),
+            "coarse": lambda: proposer.run_coarse(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da,
+                                                  s.dm, budget, out=out, radius=radius),
+        }
+        for name, run in runs.items():
+            ts = []
+            for i in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                run()
+                torch.cuda.synchronize()
+                if i:
+                    ts.append(time.perf_counter() - t0)
+            res[name].append(float(np.median(ts)) * 1e3)
+    return res
+
+
+def equal_time_budget(t_ms: float, budgets, coarse_ms) -> float:
+    """The coarse-max budget whose pass time equals t_ms, by linear
+    interpolation in the measured (budget, time) points (clamped to their
+    range)."""
+    b = np.asarray(budgets, float)
+    t = np.maximum.accumulate(np.asarray(coarse_ms, float))  # time grows with the budget
+    if t_ms <= t[0]:
+        return float(b[0])
+    if t_ms >= t[-1]:
+        return float(b[-1])
+    return float(np.interp(t_ms, t, b))
+
+
+def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None, log=None, artifacts=None,
+             radius=None, prefilter=None, coarse_equal_time_frac=None):
+    """Recall of plain / learned / coarse-max / coarse-to-fine selection over
+    stored realizations (optionally with single-exposure artifacts), and
+    timings.  radius: the learned and coarse-max paths stack only the
+    selected cells' members within it of the stamp peak; prefilter: the
+    fraction of cells (largest stamp maximum) the scorer sees;
+    coarse_equal_time_frac: a second coarse-max budget (the one whose pass
+    takes as long as the learned pass, see equal_time_budget) evaluated on
+    the same realizations."""
     import torch
     import paper_2503_08854_amd as dt
     from paper_2503_08854_amd import proposer
@@ -134,12 +212,12 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
     n = bench.grid.n
     out_full = dt.batch_outputs([bench.grid])[0]
     out_sel = tuple(torch.empty_like(t) for t in out_full)
-    found = dict(plain=0, learned=0, coarse=0, c2f=0)
+    found = dict(plain=0, learned=0, coarse=0, c2f=0, coarse_eq=0)
     tot = 0
-    t_plain, t_learn = [], []
+    t_plain, t_learn, t_coarse, t_coarse_eq = [], [], [], []
     for r, injs in enumerate(reals):
         hits = np.array([[h[0], h[1], h[2], inj["flux"]] for inj in injs for h in inj["hits"]])
-        bench.realize(10_000 + r, hits)
+        bench.realize(10_000 + r, hits, artifacts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         dt.stack(bench.patch, bench.grid, out_full)
@@ -150,19 +228,33 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, cells = proposer.run_learned(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da, s.dm,
-                                        scorer, budget, out=out_sel)
+                                        scorer, budget, out=out_sel, radius=radius,
+                                        prefilter=None if prefilter is None else max(budget, int(prefilter * s.n_cells)))
         torch.cuda.synchronize()
         t_learn.append(time.perf_counter() - t0)
         learned_snr = out_sel[0].cpu().numpy()
         for t in out_sel:
             t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         proposer.run_coarse(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da, s.dm, budget,
-                            out=out_sel)
+                            out=out_sel, radius=radius)
+        torch.cuda.synchronize()
+        t_coarse.append(time.perf_counter() - t0)
         coarse_snr = out_sel[0].cpu().numpy()
+        if coarse_equal_time_frac is not None:
+            _clear(out_sel)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            proposer.run_coarse(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da, s.dm,
+                                max(1, int(round(coarse_equal_time_frac * s.n_cells))), out=out_sel, radius=radius)
+            torch.cuda.synchronize()
+            t_coarse_eq.append(time.perf_counter() - t0)
+            coarse_eq_snr = out_sel[0].cpu().numpy()
         for t in out_sel:
             t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
-        proposer.run_coarse_to_fine(bench.ctx, bench.patch, bench.coarse, bench.grid, bench.reps, s.cell_size, budget,
-                                    out=out_sel)
+        proposer.run_coarse_to_fine(bench.ctx, bench.patch, bench.coarse, bench.grid, bench.subs,
+                                    bench.sub_k * bench.sub_k, s.cell_size, budget, out=out_sel)
         c2f_snr = out_sel[0].cpu().numpy()
         plain_snr = out_full[0].cpu().numpy()
         orbits = np.array([inj["orbit"] for inj in injs])
@@ -174,17 +266,26 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
         found["plain"] += int(pf.sum())
         found["learned"] += int((lf & pf).sum())
         found["coarse"] += int((cf & pf).sum())
+        if coarse_equal_time_frac is not None:
+            ce = np.nan_to_num(coarse_eq_snr[orbits], nan=-np.inf) >= 5.0
+            found["coarse_eq"] += int((ce & pf).sum())
         tot += len(orbits)
     # steady-state timings: drop the first realization (warm-up)
     tp = float(np.median(t_plain[1:] if len(t_plain) > 1 else t_plain))
     tl = float(np.median(t_learn[1:] if len(t_learn) > 1 else t_learn))
+    tc = float(np.median(t_coarse[1:] if len(t_coarse) > 1 else t_coarse))
     res = dict(injections=tot, plain_found=found["plain"], learned_found=found["learned"],
                coarse_found=found["coarse"], budget_cells=budget, cells=s.n_cells, budget_frac=budget / s.n_cells,
                recall_plain=found["plain"] / max(tot, 1),
                recall_ratio_learned=found["learned"] / max(found["plain"], 1),
                recall_ratio_coarse=found["coarse"] / max(found["plain"], 1),
                recall_ratio_coarse_to_fine=found["c2f"] / max(found["plain"], 1),
-               t_plain_ms=tp * 1e3, t_learned_ms=tl * 1e3, speedup=tp / tl, orbits=n)
+               t_plain_ms=tp * 1e3, t_learned_ms=tl * 1e3, t_coarse_ms=tc * 1e3, speedup=tp / tl,
+               speedup_coarse=tp / tc, radius=radius, prefilter=prefilter, orbits=n)
+    if coarse_equal_time_frac is not None:
+        tce = float(np.median(t_coarse_eq[1:] if len(t_coarse_eq) > 1 else t_coarse_eq))
+        res.update(coarse_equal_time_budget_frac=coarse_equal_time_frac, t_coarse_equal_time_ms=tce * 1e3,
+                   recall_ratio_coarse_equal_time=found["coarse_eq"] / max(found["plain"], 1))
     if log:
         log(f"learned eval: {res}")
     return res

@@ -11,5 +11,5 @@ from .binding import (  # noqa: F401
     exposure_struct, LIB_PATH, stack_batched, autotune_batched, batch_outputs, cell_stamps, stack_cells,
     gemm_bf16, Scorer, clip_candidates, image_noise, record_valid_gathers, replay_valid_gathers, GatherRecord,
     orbit_sampler, generate_orbits,
-    stack_generated, topk_noalloc,
+    stack_generated, topk_noalloc, cell_members_near, stack_ids, segment_max,
 )

@@ -97,12 +97,17 @@ def lib():
         "dt_debug_stack_samples": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P],
                                    C.c_int),
         "dt_scorer_infer": ([_P, _P, _P, C.c_int32, _P], C.c_int),
+        "dt_scorer_infer_rows": ([_P, _P, _P, _P, C.c_int32, _P], C.c_int),
         "dt_generate_orbits": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P, _P, _P, _P],
                                C.c_int),
         "dt_stack_generated": ([_P, C.POINTER(DtOrbitSampler), C.c_int64, C.c_int64, _P, _P, _P], C.c_int),
         "dt_clip_candidates": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, C.c_double, C.c_int32, _P, _P, _P],
                                C.c_int),
         "dt_stack_cells": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, C.c_int32, _P, _P, _P], C.c_int),
+        "dt_cell_members_near": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, C.c_int32, _P, C.c_int32, C.c_double,
+                                  C.c_double, C.c_double, _P, _P], C.c_int),
+        "dt_stack_ids": ([_P, C.POINTER(DtOrbits), _P, _P, C.c_int64, _P, _P, _P], C.c_int),
+        "dt_segment_max": ([_P, _P, C.c_int64, C.c_int32, _P], C.c_int),
         "dt_gemm_bf16": ([_P, _P, C.c_int32, C.c_int32, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                           _P, C.c_int32, _P, C.c_int32], C.c_int),
         "dt_scorer_num_params": ([], C.c_int64),
@@ -537,15 +542,18 @@ def clip_candidates(patch: Patch, orbits: OrbitSet, ids, kappa: float = 3.0, max
 
 
 # ------------------------------------------------------------ learned proposal
-def cell_stamps(patch: Patch, reps: OrbitSet, da: float, dm: float, bf16=True, f32=True):
-    """Coarse stamps (n x 21 x 21 over the cell's (a, M0) box) and features (n x 16) of representative orbits."""
+def cell_stamps(patch: Patch, reps: OrbitSet, da: float, dm: float, bf16=True, f32=True, feats_f32=None):
+    """Coarse stamps (n x 21 x 21 over the cell's (a, M0) box) and features (n x 16) of representative
+    orbits: BF16 stamps and features when bf16, FP32 stamps when f32, FP32 features when feats_f32
+    (default: f32)."""
     import torch
     dev = reps.soa.device
     n = reps.n
+    feats_f32 = f32 if feats_f32 is None else feats_f32
     sb = torch.empty((n, 21, 21), dtype=torch.bfloat16, device=dev) if bf16 else None
     sf = torch.empty((n, 21, 21), dtype=torch.float32, device=dev) if f32 else None
     fb = torch.empty((n, 16), dtype=torch.bfloat16, device=dev) if bf16 else None
-    ff = torch.empty((n, 16), dtype=torch.float32, device=dev) if f32 else None
+    ff = torch.empty((n, 16), dtype=torch.float32, device=dev) if feats_f32 else None
     _check(lib().dt_cell_stamps(patch.handle, C.byref(reps.struct()), float(da), float(dm), _ptr(sb), _ptr(sf),
                                 _ptr(fb), _ptr(ff)))
     return dict(stamps_bf16=sb, stamps=sf, feats_bf16=fb, feats=ff)
@@ -562,6 +570,51 @@ def stack_cells(patch: Patch, grid: OrbitSet, cells, cell_size: int, out=None):
     cells = torch.as_tensor(cells, dtype=torch.int64).to(dev)
     _check(lib().dt_stack_cells(patch.handle, C.byref(grid.struct()), _ptr(cells), int(cells.numel()),
                                 int(cell_size), _ptr(out[0]), _ptr(out[1]), _ptr(out[2])))
+    return out
+
+
+def cell_members_near(ctx: Context, grid: OrbitSet, cells, cell_size: int, uv, da: float, dm: float,
+                      radius: float, ids=None, count=None):
+    """Orbit ids of the selected cells' members within `radius` (lattice units)
+    of each cell's (u, v) in `uv` (device float rows, u and v first: the FP32
+    stamp features, columns 11 and 12, are passed as uv[:, 11:]).  Returns
+    (ids int64 [capacity], count int64 [1]) device tensors; only the first
+    count ids are meaningful."""
+    import torch
+    dev = grid.soa.device
+    cells = torch.as_tensor(cells, dtype=torch.int64).to(dev)
+    cap = max(int(cells.numel()) * int(cell_size), 1)
+    if ids is None or ids.numel() < cap:
+        ids = torch.empty(cap, dtype=torch.int64, device=dev)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(lib().dt_cell_members_near(ctx.handle, C.byref(grid.struct()), _ptr(cells), int(cells.numel()),
+                                      int(cell_size), _ptr(uv), int(uv.stride(0)), float(da), float(dm),
+                                      float(radius), _ptr(ids), _ptr(count)))
+    return ids, count
+
+
+def segment_max(ctx: Context, x, seg: int, out=None):
+    """Maximum of each run of `seg` consecutive values of a device float tensor (NaN ignored)."""
+    import torch
+    n_seg = int(x.numel()) // int(seg)
+    if out is None:
+        out = torch.empty(n_seg, dtype=torch.float32, device=x.device)
+    _check(lib().dt_segment_max(ctx.handle, _ptr(x), n_seg, int(seg), _ptr(out)))
+    return out
+
+
+def stack_ids(patch: Patch, orbits: OrbitSet, ids, count, out=None, m_max: int = None):
+    """The plain stack on the first count ids of a device id list; outputs at the orbits' indices."""
+    import torch
+    dev = orbits.soa.device
+    if out is None:
+        out = (torch.full((orbits.n,), float("nan"), dtype=torch.float32, device=dev),
+               torch.full((orbits.n,), float("nan"), dtype=torch.float32, device=dev),
+               torch.full((orbits.n,), -2, dtype=torch.int32, device=dev))
+    m = int(ids.numel()) if m_max is None else int(m_max)
+    _check(lib().dt_stack_ids(patch.handle, C.byref(orbits.struct()), _ptr(ids), _ptr(count), m, _ptr(out[0]),
+                              _ptr(out[1]), _ptr(out[2])))
     return out
 
 
@@ -620,6 +673,12 @@ class Scorer:
         _check(lib().dt_scorer_infer(self._h, _ptr(stamps_bf16.contiguous()), _ptr(feats_bf16.contiguous()), B,
                                      _ptr(z)))
         return z
+
+    def infer_rows(self, stamps_bf16, feats_bf16, rows, out):
+        """Logits of the cells at `rows` (device int64) written to out[rows]; other entries untouched."""
+        _check(lib().dt_scorer_infer_rows(self._h, _ptr(stamps_bf16.contiguous()), _ptr(feats_bf16.contiguous()),
+                                          _ptr(rows), int(rows.numel()), _ptr(out)))
+        return out
 
     def grad(self, stamps_bf16, feats_bf16, labels):
         import torch

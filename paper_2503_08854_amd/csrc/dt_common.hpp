@@ -166,6 +166,16 @@ hipError_t launch_init_params(float* w, int64_t off, int64_t n, int fan_in, uint
 constexpr int STAMP_MAX_EXP = 1024;  // the stamps keep three walks of every exposure in LDS
 hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, uint16_t* st_bf, float* st_f,
                               uint16_t* ft_bf, float* ft_f, hipStream_t s);
+hipError_t launch_segment_max(const float* x, int64_t n_seg, int seg, float* out, hipStream_t s);
+hipError_t launch_cell_members_near(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
+                                    const float* d_uv, int uv_stride, double da, double dm, double radius,
+                                    int64_t* d_ids, int64_t* d_count, hipStream_t s);
+// Id lists of at most STACK_IDS_SHORT entries are walked per sample with the
+// exposures split over eight wavefronts per 64 orbits (latency-bound sizes);
+// longer ones by the checkpoint walk with deferral.
+constexpr int64_t STACK_IDS_SHORT = (int64_t)1 << 18;
+hipError_t launch_stack_ids(const StackArgs& a, const int64_t* d_ids, const int64_t* d_count, int64_t m_max,
+                            hipStream_t s);
 hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
                               hipStream_t s);
 
@@ -184,6 +194,7 @@ struct ScorerFusedArgs {
   int64_t w_off[7], b_off[7], t_off[8];
   int K[7], N[7];
   float* z;                // B logits
+  const int64_t* rows;     // NULL, or cell i of the batch is row rows[i] of stamps / feats and of z
 };
 // Top-k of many S/N arrays at once (device tables, one entry per array or
 // per TOPK tile; see launch_topk_segmented).

@@ -118,6 +118,54 @@ dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t fir
   return e == hipSuccess ? DT_OK : hip_fail(e, "generate-and-stack launch");
 }
 
+dt_status dt_segment_max(dt_ctx* c, const float* d_x, int64_t n_seg, int32_t seg, float* d_out) {
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  if (n_seg < 0 || seg < 1 || (n_seg > 0 && (!d_x || !d_out))) return fail(DT_E_ARG, "bad segments or arrays");
+  DeviceGuard guard(c->device);
+  hipError_t e = launch_segment_max(d_x, n_seg, seg, d_out, c->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "segment maximum");
+}
+
+dt_status dt_cell_members_near(dt_ctx* c, const dt_orbits* grid, const int64_t* d_cells, int64_t n_cells,
+                               int32_t cell_size, const float* d_uv, int32_t uv_stride, double da, double dm,
+                               double radius, int64_t* d_ids, int64_t* d_count) {
+  if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
+  dt_status st = check_orbits(grid);
+  if (st != DT_OK) return st;
+  if (n_cells < 0 || (n_cells > 0 && (!d_cells || !d_uv || !d_ids))) return fail(DT_E_ARG, "bad cell or output array");
+  if (!d_count) return fail(DT_E_ARG, "d_count is NULL");
+  if (cell_size < 1 || uv_stride < 2) return fail(DT_E_ARG, "need cell_size >= 1 and uv_stride >= 2");
+  if (n_cells * (int64_t)cell_size >= ((int64_t)1 << 40)) return fail(DT_E_ARG, "too many orbits");
+  if (!(da > 0.0 && dm > 0.0 && radius >= 0.0)) return fail(DT_E_DOMAIN, "need da > 0, dm > 0, radius >= 0");
+  DeviceGuard guard(c->device);
+  StackArgs a{};
+  a.n = grid->n;
+  a.a = grid->a;
+  a.m0 = grid->m0;
+  hipError_t e = launch_cell_members_near(a, d_cells, n_cells, cell_size, d_uv, uv_stride, da, dm, radius, d_ids,
+                                          d_count, c->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "cell member selection");
+}
+
+dt_status dt_stack_ids(dt_patch* p, const dt_orbits* orbits, const int64_t* d_ids, const int64_t* d_count,
+                       int64_t m_max, float* d_snr, float* d_flux, int32_t* d_nvalid) {
+  if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
+  dt_status st = check_orbits(orbits);
+  if (st != DT_OK) return st;
+  if (m_max < 0 || (m_max > 0 && (!d_ids || !d_count))) return fail(DT_E_ARG, "bad id list or count");
+  DeviceGuard guard(p->ctx->device);
+  StackArgs a = stack_args(p, orbits);
+  a.snr = d_snr;
+  a.flux = d_flux;
+  a.nvalid = d_nvalid;
+  if (m_max > STACK_IDS_SHORT && p->vobs < __builtin_inf()) {
+    st = defer_setup(p->ctx, m_max, a);
+    if (st != DT_OK) return st;
+  }
+  hipError_t e = launch_stack_ids(a, d_ids, d_count, m_max, p->ctx->stream);
+  return e == hipSuccess ? DT_OK : hip_fail(e, "id-list stack launch");
+}
+
 dt_status dt_stack_cells(dt_patch* p, const dt_orbits* grid, const int64_t* d_cells, int64_t n_cells,
                          int32_t cell_size, float* d_snr, float* d_flux, int32_t* d_nvalid) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");

@@ -270,6 +270,11 @@ dt_status dt_scorer_forward(dt_scorer* s, const uint16_t* d_stamps, const uint16
 
 dt_status dt_scorer_infer(dt_scorer* s, const uint16_t* d_stamps, const uint16_t* d_feats, int32_t B,
                           float* d_logits) {
+  return dt_scorer_infer_rows(s, d_stamps, d_feats, nullptr, B, d_logits);
+}
+
+dt_status dt_scorer_infer_rows(dt_scorer* s, const uint16_t* d_stamps, const uint16_t* d_feats,
+                               const int64_t* d_rows, int32_t B, float* d_logits) {
   if (!s || !s->ctx) return fail(DT_E_ARG, "invalid scorer");
   if (B < 0) return fail(DT_E_ARG, "B < 0");
   if (B == 0) return DT_OK;
@@ -293,6 +298,7 @@ dt_status dt_scorer_infer(dt_scorer* s, const uint16_t* d_stamps, const uint16_t
   a.t_off[NL] = t;
   a.wt = s->wt;
   a.z = d_logits;
+  a.rows = d_rows;
   // the transposed weights are rebuilt only after the weights changed
   hipError_t e = launch_scorer_fused(a, s->wt_ver != s->wver, s->ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "scorer inference");

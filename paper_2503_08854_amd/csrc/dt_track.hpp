@@ -38,11 +38,11 @@ namespace dtk {
 
 constexpr double CK_SPAN = 16.0;      // days: checkpoints at least this often (epoch span)
 constexpr double CK_REACH = 0.3;     // rad: largest Kepler start step taken warm from a checkpoint
-constexpr double PRED_SLACK = 1e-9;  // AU: rounding of the checkpoint state and of the prediction
+constexpr float PRED_SLACK = 1e-9f;  // AU: rounding of the checkpoint state and of the prediction
 constexpr int TQ_CAP = 128;          // queued samples per wavefront (< 64 held + 64 pushed)
 constexpr int TQ_LIST = 8;           // queued samples per lane between flushes
 constexpr int CK_ANCHOR = 8;         // checkpoints between full sincos re-anchors of sin E, cos E
-constexpr float TRACK_SWITCH = 0.05f; // queued fraction of lane-exposures above which a wavefront walks per sample
+constexpr float TRACK_SWITCH = 0.20f; // queued fraction of lane-exposures above which a wavefront defers
 constexpr int TRACK_SWITCH_MIN = 3;   // exposures tested before the fraction is trusted
 
 // One wavefront's state in LDS: the queue, and each lane's prepared orbit and
@@ -57,7 +57,7 @@ struct TrackQueue {
   unsigned char list[TQ_LIST][64]; // queue slots of each lane, in push order
   double orb[9][64];               // e, n, M0, aP, bQ of each lane's orbit
   double kep[4][64];               // E, sin E, cos E, g at the lane's checkpoint (M = E - e sin E)
-  float bnd[2][64];                // j6, l1 of TrackBound, rounded up
+  float bnd[3][64];                // j6, l1, vmax of TrackBound, rounded up (vmax -1: never pruned)
 };
 typedef __attribute__((address_space(3))) TrackQueue LdsTrackQueue;
 
@@ -122,10 +122,10 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   const bool bounded = bd.j6 < 1e30 && bd.l1 < 1e30 && bd.vmax < 1e30;
   Q.bnd[0][lane] = bounded ? __double2float_ru(bd.j6) : 0.f;
   Q.bnd[1][lane] = bounded ? __double2float_ru(bd.l1) : 0.f;
-  const double vmax = bounded ? bd.vmax : 0.0;
+  Q.bnd[2][lane] = bounded ? __double2float_ru(bd.vmax) : -1.f;  // read back at checkpoints only
   double j6 = 0.0, l1 = 0.0;  // reloaded after every service step
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
-  double s0 = 0.0;   // 1.1 PRED_SLACK, or 1e300 after a checkpoint whose light time did not converge
+  float s0 = 0.f;    // slack (AU, rounded up), or +inf after a checkpoint whose light time did not converge
   double tc = 0.0;   // checkpoint epoch
   int n_ck = 0;      // checkpoints so far
   int count = 0;     // queued samples (wave-uniform)
@@ -147,10 +147,10 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
     const bool fl = count > 0 && (last || ck || full);
     if (fl || ck) {
       const int nb = fl ? (count + 63) >> 6 : 0;
-      double tg_ck = 0.0;
+      float tg_ck = 0.f;  // a Newton start only
       if (ck && ex > 0) {
         const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
-        tg_ck = d2 * __builtin_amdgcn_rsq(d2) * IC;
+        tg_ck = (float)(d2 * __builtin_amdgcn_rsq(d2) * IC);
       }
 #pragma unroll 1
       for (int jb = 0; jb < nb + (ck ? 1 : 0); ++jb) {
@@ -179,7 +179,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
           const ExpMeta& xm = meta[ent >> 6];
           const double dt = xm.t - A.epoch;
           const double b0 = -xm.ox, b1 = -xm.oy, b2 = -xm.oz;
-          double tg = ckj ? tg_ck : (double)Q.tg[i];
+          double tg = (double)(ckj ? tg_ck : Q.tg[i]);
           // exact solve: Kepler (cold at the first exposure, else warm from the
           // checkpoint state, re-anchored every CK_ANCHOR checkpoints), light time
           double M = fma(oo.n, dt - tg, oo.m0);
@@ -207,8 +207,12 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
             Q.kep[1][lane] = kk.sE;
             Q.kep[2][lane] = kk.cE;
             Q.kep[3][lane] = kk.g;
-            const double dtau = 1.01 * fabs(s.D) + 1e-9;
-            s0 = bounded && dtau < 1.0 ? 1.1 * (PRED_SLACK + vmax * dtau) : 1e300;
+            // in FP32 (no FP64 constants held across the walk): each of the
+            // three roundings is below 1e-7 relative, and the factor
+            // 1.1 * (1 + 1e-6) keeps s0 above 1.1 (PRED_SLACK + vmax dtau)
+            const float dtau = fmaf(1.01f, fabsf((float)s.D), 1e-9f);
+            const float vmax = Q.bnd[2][lane];
+            s0 = vmax >= 0.f && dtau < 1.f ? 1.1000011f * fmaf(vmax, dtau, PRED_SLACK) : __builtin_inff();
           } else {
             SampleOut so;
             project(xm, s, so);
@@ -283,7 +287,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
     // cone test of the prediction (bitwise logic, no branches)
     const double sc = fma(x.ux, p0, fma(x.uy, p1, x.uz * p2));
     const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
-    const double m = fma(j6 * D * D, D, fma(l1, D, s0));
+    const double m = fma(j6 * D * D, D, fma(l1, D, (double)s0));
     const double R = fma(x.cone_tan, sc, m);
     const bool may = live & !tail & (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
     const uint64_t mask = __builtin_amdgcn_ballot_w64(may);
@@ -342,6 +346,22 @@ __device__ __forceinline__ bool track_stack_lane(const StackArgs& A, const doubl
   if (deferred) return true;
   if (live) stack_finish(P, snr, flux, nv);
   return false;
+}
+
+// First global thread index of the calling wavefront, from wave-uniform parts
+// only (scalar registers), so that no 64-bit per-lane index has to stay live
+// in vector registers through the walk.
+__device__ __forceinline__ int64_t wave_base() {
+  return (int64_t)blockIdx.x * blockDim.x + (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+}
+
+// This lane's global thread index again after the walk, from the wave-uniform
+// base and an opaque copy of the lane id, so that the compiler cannot reuse
+// (and therefore keep live, or spill) the index computed before the walk.
+__device__ __forceinline__ int64_t thread_index_after_walk() {
+  int lane = (int)__lane_id();
+  asm volatile("" : "+v"(lane));
+  return wave_base() + lane;
 }
 
 // A deferring wavefront's list entry: its first orbit index (lane 0 writes).

@@ -23,25 +23,37 @@ __global__ __launch_bounds__(256, 4) void k_stack_persistent(const StackArgs* __
   while (true) {
     if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
     __syncthreads();
-    const int it = s_item;
+    // uniform across the workgroup: scalar loads of the item and its
+    // descriptor, held in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();  // every lane has read s_item before it is overwritten
     if (it >= n_items) break;
     const WorkItem w = items[it];
-    const StackArgs A = descs[w.patch];
+    const StackArgs& A = descs[w.patch];
     const int64_t end = w.begin + w.count;
     if (A.vobs < __builtin_inf()) {
-      // checkpoint prediction, one wavefront per 64 orbits (as k_stack_track)
-      for (int64_t o = w.begin + threadIdx.x; o - (int64_t)__lane_id() < end; o += blockDim.x) {
-        const bool in = o < end;
-        double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (in) {
-          el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
-        }
+      // checkpoint prediction, one wavefront per 64 orbits (as k_stack_track);
+      // b is the wavefront's first orbit
+      const int64_t wofs = (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+      for (int64_t b = w.begin + wofs; b < end; b += blockDim.x) {
+        bool in;
         float snr, flux;
         int nv;
-        track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6],
-                         snr, flux, nv);
+        {
+          const int64_t o = b + __lane_id();
+          in = o < end;
+          double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+          if (in) {
+            el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+          }
+          track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6],
+                           snr, flux, nv);
+        }
         if (in) {
+          // the lane id again, opaque to the compiler (see thread_index_after_walk)
+          int lane = (int)__lane_id();
+          asm volatile("" : "+v"(lane));
+          const int64_t o = b + lane;
           if (A.snr) A.snr[o] = snr;
           if (A.flux) A.flux[o] = flux;
           if (A.nvalid) A.nvalid[o] = nv;

@@ -115,19 +115,23 @@ __global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_s
 // The same by checkpoint prediction (one wavefront per 64 generated orbits).
 __global__ __launch_bounds__(256, 4) void k_stack_generated_track(StackArgs A, dt_orbit_sampler S, int64_t first) {
   __shared__ TrackQueue tq[4];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i - (int64_t)__lane_id() >= A.n) return;  // the whole wavefront is past the end
-  const bool in = i < A.n;
-  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  const bool live = in && gen_orbit(S, (uint64_t)(first + i), el) &&
-                    orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
+  if (wave_base() >= A.n) return;  // the whole wavefront is past the end
+  bool in;
   float snr, flux;
   int nv;
-  if (track_stack_lane(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv)) {
-    defer_wave(A, i - (int64_t)__lane_id());
-    return;
+  {
+    const int64_t i = wave_base() + __lane_id();
+    in = i < A.n;
+    double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool live = in && gen_orbit(S, (uint64_t)(first + i), el) &&
+                      orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
+    if (track_stack_lane(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv)) {
+      defer_wave(A, wave_base());
+      return;
+    }
   }
   if (!in) return;
+  const int64_t i = thread_index_after_walk();
   if (A.snr) A.snr[i] = snr;
   if (A.flux) A.flux[i] = flux;
   if (A.nvalid) A.nvalid[i] = nv;

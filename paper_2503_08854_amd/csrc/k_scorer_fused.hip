@@ -72,6 +72,7 @@ __global__ void k_scorer_transpose(const uint16_t* __restrict__ wb, uint16_t* __
   wt[i] = wb[A.w_off[l] + (int64_t)k * N + n];
 }
 
+template <bool ROWS>
 __global__ __launch_bounds__(NTH) void k_scorer_fused(ScorerFusedArgs A) {
   // A workgroup owns 16 cells at a time; the cells are the M (row) dimension
   // of every MFMA tile, so all pixel / tap index arithmetic is uniform.
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(NTH) void k_scorer_fused(ScorerFusedArgs A) {
   __shared__ __align__(16) uint16_t ftg[G * FTS];
   __shared__ __align__(16) uint16_t cat[G * CTS];
   __shared__ __align__(16) uint16_t h6[G * H6S];
+  __shared__ int srow[G];  // the group's rows of the inputs and logits
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, kq = lane >> 4;
   const uint16_t* wt = A.wt;
@@ -143,8 +145,12 @@ __global__ __launch_bounds__(NTH) void k_scorer_fused(ScorerFusedArgs A) {
   for (int i = tid; i < SPAD * G; i += NTH) stg[i] = 0;
   const int n_groups = (A.B + G - 1) / G;
   for (int grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
-    __syncthreads();  // the previous group's readers of stg / h3s / cat / h6 are done; weights loaded
+    __syncthreads();  // the previous group's readers of stg / h3s / cat / h6 / srow are done; weights loaded
     const int cell0 = grp * G;
+    if (ROWS) {
+      if (tid < G) srow[tid] = cell0 + tid < A.B ? (int)A.rows[cell0 + tid] : 0;
+      __syncthreads();
+    }
     {
       // the group's stamps: all loads of a thread issued together, then stored [pixel][cell]
       constexpr int NQ = (441 * G + NTH - 1) / NTH;
@@ -153,7 +159,8 @@ __global__ __launch_bounds__(NTH) void k_scorer_fused(ScorerFusedArgs A) {
       for (int q = 0; q < NQ; ++q) {
         const int i = tid + NTH * q;
         const int c = i / 441;
-        v[q] = (i < 441 * G && cell0 + c < A.B) ? A.stamps[(int64_t)cell0 * 441 + i] : (uint16_t)0;
+        const bool in = i < 441 * G && cell0 + c < A.B;
+        v[q] = in ? A.stamps[ROWS ? (int64_t)srow[c] * 441 + (i - 441 * c) : (int64_t)cell0 * 441 + i] : (uint16_t)0;
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -164,7 +171,8 @@ __global__ __launch_bounds__(NTH) void k_scorer_fused(ScorerFusedArgs A) {
     }
     for (int i = tid; i < G * 16; i += NTH) {
       const int r = i / 16, c = i % 16;
-      ftg[r * FTS + c] = cell0 + r < A.B ? A.feats[(int64_t)(cell0 + r) * 16 + c] : (uint16_t)0;
+      ftg[r * FTS + c] = cell0 + r < A.B ? A.feats[(ROWS ? (int64_t)srow[r] : (int64_t)(cell0 + r)) * 16 + c]
+                                         : (uint16_t)0;
     }
     __syncthreads();
     const short4_t bw1 = ld4(&w1s[r16 * W1K + 4 * kq]);
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(NTH) void k_scorer_fused(ScorerFusedArgs A) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int cell = cell0 + 4 * kq + r;
-          if (cell < A.B) A.z[cell] = acc[r] + bias7;
+          if (cell < A.B) A.z[ROWS ? (int64_t)srow[4 * kq + r] : (int64_t)cell] = acc[r] + bias7;
         }
       }
     }
@@ -308,7 +316,10 @@ hipError_t launch_scorer_fused(const ScorerFusedArgs& a, bool transpose, hipStre
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   const int groups = (a.B + G - 1) / G;
   const int grid = groups < n_cu ? groups : n_cu;
-  hipLaunchKernelGGL(k_scorer_fused, dim3((unsigned)grid), dim3(NTH), 0, s, a);
+  if (a.rows)
+    hipLaunchKernelGGL(k_scorer_fused<true>, dim3((unsigned)grid), dim3(NTH), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_scorer_fused<false>, dim3((unsigned)grid), dim3(NTH), 0, s, a);
   return hipGetLastError();
 }
 

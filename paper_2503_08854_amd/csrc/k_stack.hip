@@ -32,21 +32,25 @@ __global__ __launch_bounds__(256) void k_stack(StackArgs A) {
 // together; used when the patch has a finite observer speed bound).
 __global__ __launch_bounds__(256, 4) void k_stack_track(StackArgs A) {
   __shared__ TrackQueue tq[4];
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o - (int64_t)__lane_id() >= A.n) return;  // the whole wavefront is past the end
-  const bool in = o < A.n;
-  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (in) {
-    el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
-  }
+  if (wave_base() >= A.n) return;  // the whole wavefront is past the end
+  bool in;
   float snr, flux;
   int nv;
-  if (track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr,
-                       flux, nv)) {
-    defer_wave(A, o - (int64_t)__lane_id());
-    return;
+  {
+    const int64_t o = wave_base() + __lane_id();
+    in = o < A.n;
+    double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (in) {
+      el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+    }
+    if (track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6],
+                         snr, flux, nv)) {
+      defer_wave(A, wave_base());
+      return;
+    }
   }
   if (!in) return;
+  const int64_t o = thread_index_after_walk();
   if (A.snr) A.snr[o] = snr;
   if (A.flux) A.flux[o] = flux;
   if (A.nvalid) A.nvalid[o] = nv;

@@ -189,10 +189,11 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
     if (j == SP / 2) center = snr;
   }
   const float gmax = wave_max(smax);
-  // offset of the maximum: the lowest index among lanes holding it
-  const unsigned long long ball = __ballot(smax == gmax);
-  const int src = __ffsll(ball) - 1;
-  const int jmax = __shfl(amax, src, 64);
+  // node of the maximum: the lowest node index holding it (a lane's amax is
+  // its own first maximum; lanes hold nodes lane, lane + 64, ...)
+  int jmax = smax == gmax ? amax : SP;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) jmax = min(jmax, __shfl_xor(jmax, m, 64));
   ssum = wave_sum(ssum);
   ssq = wave_sum(ssq);
   cov = wave_sum(cov);
@@ -215,6 +216,8 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
       case 8: f = (float)(ee[cell] / 0.3); break;
       case 9: f = (float)(ei[cell] / 0.2618); break;
       case 10: f = smax_c; break;
+      case 11: f = dxm / SH; break;  // lattice coordinates (u, v) of the maximum
+      case 12: f = dym / SH; break;
       default: f = 0.f; break;
     }
     if (ft_bf) ft_bf[cell * NFEAT + lane] = f2bf_s(f);
@@ -318,6 +321,217 @@ __global__ __launch_bounds__(256, 4) void k_stack_cells_track(StackArgs A, const
   if (A.snr) A.snr[o] = snr;
   if (A.flux) A.flux[o] = flux;
   if (A.nvalid) A.nvalid[o] = nv;
+}
+
+// Members of selected cells near their stamp peak: member m of cell c sits at
+// lattice coordinates u = (a_m - a_rep) / da, v = (M0_m - M0_rep) / dm (the
+// representative is the cell's first member); it is listed when |u - u*| and
+// |v - v*| are both at most `radius`, (u*, v*) = uv[c * uv_stride + 0, 1].
+// One lane per member; a wavefront appends its listed members with one atomic.
+__global__ __launch_bounds__(256) void k_cell_members_near(StackArgs A, const int64_t* __restrict__ cells,
+                                                           int64_t n_sel, int cell_size, const float* __restrict__ uv,
+                                                           int uv_stride, double ida, double idm, double radius,
+                                                           int64_t* __restrict__ ids, int64_t* __restrict__ count) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool take = false;
+  int64_t o = -1;
+  if (r < n_sel * cell_size) {
+    const int64_t c = cells[r / cell_size];
+    if (c >= 0) {
+      const int64_t rep = c * cell_size;
+      o = rep + r % cell_size;
+      if (o < A.n && rep < A.n) {
+        const double u = (A.a[o] - A.a[rep]) * ida, v = (A.m0[o] - A.m0[rep]) * idm;
+        const double us = (double)uv[c * uv_stride], vs = (double)uv[c * uv_stride + 1];
+        take = fabs(u - us) <= radius && fabs(v - vs) <= radius;
+      }
+    }
+  }
+  const uint64_t mask = __builtin_amdgcn_ballot_w64(take);
+  if (!mask) return;
+  const int lane = (int)__lane_id();
+  const int leader = __builtin_ffsll((long long)mask) - 1;
+  int64_t base = 0;
+  if (lane == leader) base = (int64_t)atomicAdd((unsigned long long*)count, (unsigned long long)__builtin_popcountll(mask));
+  base = __shfl(base, leader, 64);
+  if (take) {
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    ids[base + rank] = o;
+  }
+}
+
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
+// The plain stack on a device list of orbit ids (the first *count of them;
+// outputs at the orbits' own indices), by checkpoint prediction with deferral
+// of wavefronts whose samples land often (list index of their first lane).
+__global__ __launch_bounds__(256, 4) void k_stack_ids_track(StackArgs A, const int64_t* __restrict__ ids,
+                                                            const int64_t* __restrict__ count) {
+  __shared__ TrackQueue tq[4];
+  const int64_t m = *count;
+  if (wave_base() >= m) return;  // the whole wavefront is past the end
+  bool ok;
+  float snr, flux;
+  int nv;
+  {
+    const int64_t r = wave_base() + __lane_id();
+    const int64_t o = r < m ? ids[r] : -1;
+    ok = o >= 0 && o < A.n;
+    double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ok) {
+      el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+    }
+    if (track_stack_lane(A, el, ok && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr,
+                         flux, nv)) {
+      defer_wave(A, wave_base());
+      return;
+    }
+  }
+  if (!ok) return;
+  const int64_t o = ids[thread_index_after_walk()];  // read again rather than kept through the walk
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
+__global__ __launch_bounds__(256, 4) void k_stack_ids_deferred(StackArgs A, const int64_t* __restrict__ ids,
+                                                               const int64_t* __restrict__ count) {
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (j >= (int64_t)*A.defer_count) return;
+  const int64_t r = A.defer_list[j] + (int64_t)__lane_id();
+  const int64_t o = r < *count ? ids[r] : -1;
+  const bool ok = o >= 0 && o < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (ok) {
+    el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+  }
+  float snr, flux;
+  int nv;
+  deferred_lane(A, el, ok && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), snr, flux, nv);
+  if (!ok) return;
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
+// Per-sample walk of a listed orbit (patches without an observer speed bound).
+__global__ __launch_bounds__(256) void k_stack_ids(StackArgs A, const int64_t* __restrict__ ids,
+                                                   const int64_t* __restrict__ count) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= *count) return;
+  const int64_t o = ids[r];
+  if (o < 0 || o >= A.n) return;
+  float snr, flux;
+  int nv;
+  stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
+// The id-list stack for short lists: a few thousand orbits walk 200
+// exposures in about the time one wavefront takes, so IDS_SPLIT wavefronts of
+// a workgroup share 64 listed orbits, wavefront j walking the j-th contiguous
+// range of exposures per sample (cold start, range uniform over the
+// wavefront), and the first merges the ranges' compensated sums in range
+// order through LDS (S/N agrees with the full walk's to rounding).
+constexpr int IDS_SPLIT = 8;
+__global__ __launch_bounds__(64 * IDS_SPLIT) void k_stack_ids_split(StackArgs A, const int64_t* __restrict__ ids,
+                                                                    const int64_t* __restrict__ count) {
+  __shared__ float part[IDS_SPLIT][4][64];  // [wavefront][ps.s, ps.c, ph.s, ph.c][lane]
+  __shared__ int part_nv[IDS_SPLIT][64];
+  const int64_t m = *count;
+  const int j = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  if ((int64_t)blockIdx.x * 64 >= m) return;  // the whole workgroup is past the end
+  const int64_t o = r < m ? ids[r] : -1;
+  const bool ok = o >= 0 && o < A.n;
+  double a = 0, e = 0, inc = 0, node = 0, peri = 0, m0 = 0;
+  if (ok) {
+    a = A.a[o]; e = A.e[o]; inc = A.inc[o]; node = A.node[o]; peri = A.peri[o]; m0 = A.m0[o];
+  }
+  const bool good = ok && orbit_ok(a, e, inc, node, peri, m0);
+  StackPart P;
+  P.ps.init();
+  P.ph.init();
+  P.nv = 0;
+  const int ch = (A.n_exp + IDS_SPLIT - 1) / IDS_SPLIT;
+  const int ex0 = j * ch;
+  const int cnt = min(ch, A.n_exp - ex0);
+  if (good && cnt > 0) {
+    Orbit ob;
+    orbit_prep(a, e, inc, node, peri, m0, ob);
+    stack_range(A, ob, ex0, cnt, P);
+  }
+  part[j][0][lane] = P.ps.s;
+  part[j][1][lane] = P.ps.c;
+  part[j][2][lane] = P.ph.s;
+  part[j][3][lane] = P.ph.c;
+  part_nv[j][lane] = P.nv;
+  __syncthreads();
+  if (j != 0 || !ok) return;
+  for (int q = 1; q < IDS_SPLIT; ++q) {
+    P.ps.merge(part[q][0][lane], part[q][1][lane]);
+    P.ph.merge(part[q][2][lane], part[q][3][lane]);
+    P.nv += part_nv[q][lane];
+  }
+  float snr = __builtin_nanf(""), flux = __builtin_nanf("");
+  int nv = -1;
+  if (good) stack_finish(P, snr, flux, nv);
+  if (A.snr) A.snr[o] = snr;
+  if (A.flux) A.flux[o] = flux;
+  if (A.nvalid) A.nvalid[o] = nv;
+}
+
+// out[i] = max(x[i * seg], ..., x[i * seg + seg - 1]) (NaN entries ignored;
+// -inf when all are NaN): one lane per segment.
+__global__ __launch_bounds__(256) void k_segment_max(const float* __restrict__ x, int64_t n_seg, int seg,
+                                                     float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_seg) return;
+  float m = -__builtin_inff();
+  for (int k = 0; k < seg; ++k) {
+    const float v = x[i * seg + k];
+    if (v > m) m = v;
+  }
+  out[i] = m;
+}
+
+hipError_t launch_segment_max(const float* x, int64_t n_seg, int seg, float* out, hipStream_t s) {
+  if (n_seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segment_max, dim3((unsigned)((n_seg + 255) / 256)), dim3(256), 0, s, x, n_seg, seg, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_members_near(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
+                                    const float* d_uv, int uv_stride, double da, double dm, double radius,
+                                    int64_t* d_ids, int64_t* d_count, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, d_count);
+  const int64_t n = n_sel * cell_size;
+  if (n > 0)
+    hipLaunchKernelGGL(k_cell_members_near, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d_cells, n_sel,
+                       cell_size, d_uv, uv_stride, 1.0 / da, 1.0 / dm, radius, d_ids, d_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_stack_ids(const StackArgs& a, const int64_t* d_ids, const int64_t* d_count, int64_t m_max,
+                            hipStream_t s) {
+  if (m_max <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((m_max + 255) / 256);
+  if (m_max <= STACK_IDS_SHORT) {
+    hipLaunchKernelGGL(k_stack_ids_split, dim3((unsigned)((m_max + 63) / 64)), dim3(64 * IDS_SPLIT), 0, s, a, d_ids,
+                       d_count);
+  } else if (a.vobs < __builtin_inf()) {
+    if (a.defer_list) {
+      hipError_t e = launch_zero_u32(a.defer_count, s);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_stack_ids_track, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
+    if (a.defer_list) hipLaunchKernelGGL(k_stack_ids_deferred, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
+  } else {
+    hipLaunchKernelGGL(k_stack_ids, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, uint16_t* st_bf, float* st_f,

@@ -26,6 +26,7 @@ __all__ = [
     "tangent_basis", "orbits_through", "Workload", "load_geometry", "exposures_of",
     "candidate_orbits", "perturbed_cloud", "noise_images", "render_sources", "build_workload",
     "radec_to_vec", "vec_to_radec", "hw_pixscale_deg", "cell_grid", "render_sources_fast", "grid_sampler",
+    "artifacts",
 ]
 
 # Mean motion (rad/day) of the synthetic observer on a circular 1 AU orbit.
@@ -321,6 +322,21 @@ def cell_grid(gf: dict, n_cells: int, cell_size: int, seed: int, a_rng, e_rng, i
     el[:, 0] += da * pert[:, 0]
     el[:, 5] += dm * pert[:, 1]
     return el
+
+
+def artifacts(exps, per_image: int, snr_rng, seed: int):
+    """Single-exposure point artifacts (transients that appear in one image
+    only): per_image positions uniform over every image, each with a
+    per-image S/N drawn from U(snr_rng).  Returns an (n, 4) array of
+    (exposure, px, py, s); the caller turns s into a flux."""
+    rng = make_rng(seed, 606)
+    out = []
+    for e, x in enumerate(exps):
+        px = rng.uniform(-0.5, x["width"] - 0.5, per_image)
+        py = rng.uniform(-0.5, x["height"] - 0.5, per_image)
+        s = rng.uniform(*snr_rng, per_image)
+        out.append(np.stack([np.full(per_image, float(e)), px, py, s], axis=1))
+    return np.concatenate(out, axis=0) if out else np.zeros((0, 4))
 
 
 def render_sources_fast(D, exps, hits, device=None):

@@ -160,6 +160,14 @@ def test_scorer_fused_inference_matches_forward_and_oracle(ctx):
     assert _rel(zi, zl) < 2e-3, _rel(zi, zl)
     assert np.max(np.abs(zi - zl)) < 2e-2 * max(1.0, np.max(np.abs(zl)))
     assert big.infer(Xb[:0], Fb[:0]).numel() == 0
+    # scoring a subset of rows: the same logits at those rows, nothing written elsewhere
+    rows = torch.from_numpy(rng.choice(5000, 1234, replace=False)).cuda()
+    zr = torch.full((5000,), -7.0, dtype=torch.float32, device="cuda")
+    big.infer_rows(Xb, Fb, rows, zr)
+    zr = zr.cpu().numpy()
+    r = rows.cpu().numpy()
+    np.testing.assert_array_equal(zr[r], zi[r])
+    assert np.all(np.delete(zr, r) == -7.0)
     big.close()
 
 
@@ -280,6 +288,8 @@ def test_cell_stamps_match_oracle_planes(cells):
     for r in range(reps.shape[0]):
         assert ft[r, 0] == pytest.approx(st[r].max(), abs=1e-6)
         assert ft[r, 1] == pytest.approx(st[r][10, 10], abs=1e-6)
+        row, col = divmod(int(np.argmax(st[r])), 21)   # the first node holding the maximum
+        assert ft[r, 11] == np.float32((col - 10) / 10.0) and ft[r, 12] == np.float32((row - 10) / 10.0)
 
 
 def test_cell_stamps_peak_at_a_member_source(cells):
@@ -348,26 +358,82 @@ def test_stack_cells_equals_full_stack(cells):
     assert np.all(b[2][~mask] == -2)
 
 
+def test_members_near_and_id_stack(cells):
+    """The member window around given lattice points lists exactly the
+    members the rule selects (u = (a_m - a_rep) / da, v = (M0_m - M0_rep) / dm
+    within the radius of (u*, v*)), and the stack of the listed ids equals
+    the full stack on those orbits; other outputs are untouched."""
+    import torch
+    import paper_2503_08854_amd as dt
+    c = cells
+    cg = c["g"]["cell_grid"]
+    cs, da, dm = cg["cell_size"], cg["da"], cg["dm"]
+    el = c["el"]
+    rng = np.random.default_rng(5)
+    sel = np.array([3, 17, 0, 150, -1, 199])
+    uv = np.zeros((cg["cells"], 16), np.float32)
+    uv[:, 11:13] = rng.uniform(-1, 1, (cg["cells"], 2)).astype(np.float32)
+    uv_t = torch.from_numpy(uv).cuda()
+    for radius in (0.0, 0.3, 2.0):
+        ids, cnt = dt.cell_members_near(c["ctx"], c["grid"], sel, cs, uv_t[:, 11:], da, dm, radius)
+        torch.cuda.synchronize()
+        got = np.sort(ids.cpu().numpy()[:int(cnt.cpu()[0])])
+        want = []
+        for cc in sel[sel >= 0]:
+            o = cc * cs + np.arange(cs)
+            u = (el[o, 0] - el[cc * cs, 0]) / da
+            v = (el[o, 5] - el[cc * cs, 5]) / dm
+            d = np.maximum(np.abs(u - uv[cc, 11]), np.abs(v - uv[cc, 12]))
+            assert not np.any(np.abs(d - radius) < 1e-9)     # no member on the window's edge
+            want.extend(o[d <= radius])
+        np.testing.assert_array_equal(got, np.sort(np.array(want, dtype=np.int64)))
+        if radius == 2.0:
+            assert got.size == (sel >= 0).sum() * cs       # the whole (u, v) box of every selected cell
+    ids, cnt = dt.cell_members_near(c["ctx"], c["grid"], sel, cs, uv_t[:, 11:], da, dm, 0.8)
+    full = [t.cpu().numpy() for t in dt.stack(c["patch"], c["grid"])]
+    part = [t.cpu().numpy() for t in dt.stack_ids(c["patch"], c["grid"], ids, cnt)]
+    torch.cuda.synchronize()
+    listed = np.zeros(c["grid"].n, bool)
+    listed[ids.cpu().numpy()[:int(cnt.cpu()[0])]] = True
+    assert listed.sum() > 30
+    np.testing.assert_array_equal(part[2][listed], full[2][listed])
+    for k in (0, 1):
+        np.testing.assert_allclose(part[k][listed], full[k][listed], rtol=1e-6, atol=1e-6)
+    assert np.all(part[2][~listed] == -2) and np.all(np.isnan(part[0][~listed]))
+
+
 def test_coarse_to_fine_matches_oracle(cells):
+    """Coarse-to-fine: 3 x 3 sub-representatives per cell stacked on the
+    widened-PSF planes (against the oracle on the same widened exposures),
+    each cell ranked by its best one, the top cells stacked in full."""
     import torch
     import paper_2503_08854_amd as dt
     from paper_2503_08854_amd import proposer
     c = cells
-    cs = c["g"]["cell_grid"]["cell_size"]
+    cg = c["g"]["cell_grid"]
+    cs = cg["cell_size"]
     Dt, Vt = c["keep"]
     coarse = proposer.coarse_patch(c["ctx"], c["exps"], Dt, Vt, factor=2.5)
-    budget = 20
-    out, sel, snr_c = proposer.run_coarse_to_fine(c["ctx"], c["patch"], coarse, c["grid"], c["reps"], cs, budget)
-    torch.cuda.synchronize()
-    snr_c = snr_c.cpu().numpy()
-    sel = sel.cpu().numpy()
-    # coarse S/N of the representatives vs the oracle on widened-PSF planes
+    budget, k = 20, 3
     reps = c["el"][::cs]
+    sub_el = proposer.sub_representatives(reps, cg["da"], cg["dm"], k)
+    assert sub_el.shape == (reps.shape[0] * k * k, 6)
+    # the centre sub-representative is the representative itself
+    np.testing.assert_array_equal(sub_el[k * k // 2::k * k], reps)
+    subs = dt.OrbitSet(sub_el, c["g"]["t0"])
+    out, sel, score = proposer.run_coarse_to_fine(c["ctx"], c["patch"], coarse, c["grid"], subs, k * k, cs, budget)
+    snr_sub = dt.stack(coarse, subs)[0]
+    torch.cuda.synchronize()
+    score = score.cpu().numpy()
+    snr_sub = snr_sub.cpu().numpy()
+    sel = sel.cpu().numpy()
+    # coarse S/N of the sub-representatives vs the oracle on widened-PSF planes
     wide = proposer.coarse_exposures(c["exps"], 2.5)
-    snr_o, _, _ = oracle.stack(reps, c["g"]["t0"], wide, c["D"], c["V"])
-    assert snr_close(snr_c, snr_o).all()
-    # selection: the top `budget` of the GPU's coarse S/N (same precision on both sides)
-    np.testing.assert_array_equal(sel, oracle.topk(snr_c.astype(np.float64), budget))
+    snr_o, _, _ = oracle.stack(sub_el, c["g"]["t0"], wide, c["D"], c["V"])
+    assert snr_close(snr_sub, snr_o).all()
+    np.testing.assert_array_equal(score, snr_sub.reshape(-1, k * k).max(axis=1))
+    # selection: the top `budget` of the GPU's cell scores (same precision on both sides)
+    np.testing.assert_array_equal(sel, oracle.topk(score.astype(np.float64), budget))
     # fine stack on the selected cells vs the oracle on those orbits
     ids = (sel[:, None] * cs + np.arange(cs)[None, :]).ravel()
     snr_f, _, nv_f = oracle.stack(c["el"][ids], c["g"]["t0"], c["exps"], c["D"], c["V"])
@@ -375,3 +441,36 @@ def test_coarse_to_fine_matches_oracle(cells):
     np.testing.assert_array_equal(out[2].cpu().numpy()[ids], nv_f)
     assert snr_close(got[ids], snr_f).all()
     assert np.all(np.isnan(np.delete(got, ids)))
+
+
+def test_learned_beats_coarse_max_on_artifacts(ctx):
+    """What the trained network adds to the method.  With single-exposure
+    point artifacts in every image the stamp maximum ranks the artifact cells
+    first; on held-out realizations (the stored injections) at a 2 % budget
+    the scorer, trained on 30 fresh realizations, keeps most of what the
+    exhaustive stack finds while coarse-max at the same budget keeps almost
+    nothing.  At equal time (coarse-max given the budget its pass can afford
+    in the learned pass's time) the figures are printed for the record."""
+    import learned_eval as le
+    s = le.load_setup("learned")
+    b = le.Bench(s, ctx, "cuda")
+    X, F, Y = le.training_set(b, 30, seed=3, artifacts=le.ARTIFACTS)
+    sc, hist = le.train_scorer(ctx, X, F, Y, epochs=2, batch=512, lr=1e-3)
+    del X, F, Y
+    assert hist[-1][1] < hist[0][1]
+    curve_b = (0.01, 0.02, 0.04, 0.08, 0.16)
+    curve = le.pass_times(b, sc, curve_b, radius=0.35, prefilter=0.2, artifacts=le.ARTIFACTS, reps=3)
+    b_eq = le.equal_time_budget(float(np.interp(0.02, curve_b, curve["learned"])), curve_b, curve["coarse"])
+    r = le.evaluate(b, sc, budget_frac=0.02, n_real=12, artifacts=le.ARTIFACTS, radius=0.35, prefilter=0.2,
+                    coarse_equal_time_frac=b_eq)
+    print(f"learned {r['recall_ratio_learned']:.3f} coarse-max {r['recall_ratio_coarse']:.3f} at 2 %; coarse-max at "
+          f"equal time ({b_eq:.1%}) {r['recall_ratio_coarse_equal_time']:.3f}; coarse-to-fine "
+          f"{r['recall_ratio_coarse_to_fine']:.3f}; times (ms) learned {r['t_learned_ms']:.3f} coarse "
+          f"{r['t_coarse_ms']:.3f} coarse at equal time {r['t_coarse_equal_time_ms']:.3f}")
+    assert r["plain_found"] >= 100
+    assert r["recall_ratio_learned"] >= 0.85
+    assert r["recall_ratio_learned"] - r["recall_ratio_coarse"] >= 0.5
+    assert b_eq >= 0.02
+    sc.close()
+    b.patch.close()
+    b.coarse.close()
