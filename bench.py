@@ -226,9 +226,24 @@ def bench_batched(dev, steps=5, check=True, per_patch=200):
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
     samples = sum(o.n * p.n_exp for o, p in zip(sets, patches))
+    # the same orbits as 64 single-patch stacks (one dt_stack per patch), to
+    # separate the cost of this patch mix from that of the persistent launch
+    single = []
+    for _ in range(3):
+        e0.record()
+        for p, o, out in zip(patches, sets, outs):
+            dt.stack(p, o, out)
+        e1.record()
+        torch.cuda.synchronize()
+        single.append(e0.elapsed_time(e1))
+    # one more (eager) launch with the walk's work counters, per dense sample
+    work, flops = counted_work(ctx, lambda: dt.stack_batched(ctx, patches, sets, outs=outs, k=10, threshold=5.0,
+                                                             cfg=cfg, eager=True, topk_out=tk))
     res = dict(workload=f"batched: {len(patches)} patches, {sum(p.n_exp for p in patches)} FP16 exposures, "
                         f"{sum(o.n for o in sets)} orbits", samples=samples, ms_per_step=ms_step,
-               samples_per_s=samples / (ms_step * 1e-3), cfg={"chunk": cfg[0], "wg_per_cu": cfg[1]}, pixels=n_px)
+               samples_per_s=samples / (ms_step * 1e-3), cfg={"chunk": cfg[0], "wg_per_cu": cfg[1]}, pixels=n_px,
+               work=work, work_per_sample={k: v / samples for k, v in work.items()}, fp64_flops=flops,
+               orbits=sum(o.n for o in sets), single_patch_stacks_ms=float(np.median(single)))
     if check:
         g_all, o_all, nv_diff = [], [], 0
         for (ids, so, nvo), o in zip(checks, outs):

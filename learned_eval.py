@@ -291,35 +291,42 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
     return res
 
 
-def stage_times(bench: Bench, scorer, budget_frac: float = 0.02, reps: int = 4):
-    """Per-stage device times (ms, median over reps after one warm-up) of the
-    learned path on the current images, and of the exhaustive stack."""
+def stage_times(bench: Bench, scorer, budget_frac: float = 0.02, reps: int = 4, radius=None, prefilter=None):
+    """Per-stage device times (ms, median over reps after one warm-up) of one
+    learned pass on the current images (stamps, scores, selection, stack), its
+    wall time, and the exhaustive stack's time."""
     import torch
     import paper_2503_08854_amd as dt
     from paper_2503_08854_amd import proposer
     s = bench.s
     budget = max(1, int(round(budget_frac * s.n_cells)))
+    pre = None if prefilter is None else max(budget, int(prefilter * s.n_cells))
     out = dt.batch_outputs([bench.grid])[0]
     rows = []
     for it in range(reps + 1):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        e[0].record()
-        st, ft = proposer.cell_inputs(bench.patch, bench.reps, s.da, s.dm)
-        e[1].record()
-        z = proposer.score_cells(scorer, st, ft)
-        e[2].record()
-        cells = proposer.select_cells(bench.ctx, z, budget)
-        e[3].record()
-        dt.stack_cells(bench.patch, bench.grid, cells, s.cell_size, out=out)
-        e[4].record()
+        evs = [torch.cuda.Event(enable_timing=True)]
+
+        def mark(stage):
+            evs.append(torch.cuda.Event(enable_timing=True))
+            evs[-1].record()
+
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs[0].record()
+        proposer.run_learned(bench.ctx, bench.patch, bench.grid, bench.reps, s.cell_size, s.da, s.dm, scorer, budget,
+                             out=out, radius=radius, prefilter=pre, mark=mark)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         dt.stack(bench.patch, bench.grid, out)
-        e[5].record()
+        e1.record()
         torch.cuda.synchronize()
         if it:
-            rows.append([e[i].elapsed_time(e[i + 1]) for i in range(5)])
+            rows.append([evs[i].elapsed_time(evs[i + 1]) for i in range(4)] + [wall, e0.elapsed_time(e1)])
     m = np.median(np.array(rows), axis=0)
-    return dict(stamps_ms=m[0], scorer_ms=m[1], topk_ms=m[2], stack_cells_ms=m[3], full_stack_ms=m[4],
-                budget_cells=budget)
+    return dict(stamps_ms=m[0], scores_ms=m[1], select_ms=m[2], stack_ms=m[3], learned_wall_ms=m[4],
+                full_stack_ms=m[5], budget_cells=budget, radius=radius, prefilter=prefilter)
 
 
 def main():
@@ -331,16 +338,20 @@ def main():
     ap.add_argument("--setup", default="learned")
     ap.add_argument("--train-realizations", type=int, default=4)
     ap.add_argument("--budget", type=float, default=0.02)
+    ap.add_argument("--radius", type=float, default=0.35)
+    ap.add_argument("--prefilter", type=float, default=0.2)
+    ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     s = load_setup(args.setup)
     ctx = dt.Context(0)
     b = Bench(s, ctx)
-    X, F, Y = training_set(b, args.train_realizations, seed=1)
+    X, F, Y = training_set(b, args.train_realizations, seed=1, artifacts=ARTIFACTS)
     sc, _ = train_scorer(ctx, X, F, Y, epochs=1)
+    del X, F, Y
     injs = s.geom["realizations"][0]
     hits = np.array([[h[0], h[1], h[2], inj["flux"]] for inj in injs for h in inj["hits"]])
-    b.realize(10_000, hits)
-    print(stage_times(b, sc, args.budget), flush=True)
+    b.realize(10_000, hits, ARTIFACTS)
+    print(stage_times(b, sc, args.budget, args.reps, args.radius, args.prefilter), flush=True)
     sc.close()
     b.patch.close()
     b.coarse.close()

@@ -44,6 +44,14 @@ __device__ __forceinline__ void rec_sample(const DebugArgs& d, int n_exp, int64_
   if (d.phi) d.phi[q] = valid ? v.y : 0.f;
 }
 
+// {psi, phi} of one pixel, loaded with the non-temporal hint: the gathers of
+// the per-sample walk are scattered over the planes and almost never reused,
+// and a 16 GB random-gather probe ran 10 % faster with the hint.
+__device__ __forceinline__ float2 gather_nt(const float2* __restrict__ planes, int64_t i) {
+  const uint64_t v = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(planes) + i);
+  return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+}
+
 // Compensated sums of one prepared orbit over exposures [ex0, ex0 + cnt)
 // (epoch order; REC: the debug table of the samples solved; n_full counts
 // the samples that took the full path, in a register).  Each gather is accumulated one exposure
@@ -71,7 +79,7 @@ __device__ __forceinline__ void stack_range(const StackArgs& A, const Orbit& ob,
   walk_orbit<false>(ob, A.meta + ex0, cnt, A.epoch, [&](int i, const SampleOut& so) {
     const ExpMeta& x = A.meta[ex0 + i];
     take(pend);
-    pend = so.inside ? A.planes[x.plane_off + (int64_t)so.iy * x.W + so.ix] : make_float2(0.f, 0.f);
+    pend = so.inside ? gather_nt(A.planes, x.plane_off + (int64_t)so.iy * x.W + so.ix) : make_float2(0.f, 0.f);
     if (REC && so.solved) rec_sample(*dbg, A.n_exp, row, x, so, pend);
     n_full += so.solved ? 1 : 0;
   });

@@ -30,6 +30,9 @@ __device__ __forceinline__ double u01(uint64_t seed, uint64_t idx, int att, int 
   return (double)(h >> 11) * (1.0 / 9007199254740992.0);
 }
 
+// Writes el[] only for an index that yields an orbit (returns true); the
+// caller fills el[] for the other case (storing it on both exits kept el[] in
+// scratch memory).
 __device__ inline bool gen_orbit(const dt_orbit_sampler& S, uint64_t idx, double el[6]) {
   for (int att = 0; att < 16; ++att) {
     const double xi = (2.0 * u01(S.seed, idx, att, 0) - 1.0) * S.half_w;
@@ -47,13 +50,15 @@ __device__ inline bool gen_orbit(const dt_orbit_sampler& S, uint64_t idx, double
     const double nu = PI * (2.0 * u01(S.seed, idx, att, 5) - 1.0);
     const bool branch = u01(S.seed, idx, att, 6) < 0.5;
     const double r = a * (1.0 - e * e) / (1.0 + e * cos(nu));
-    const double* O = S.obs_xyz_au;
-    const double ou = d0 * O[0] + d1 * O[1] + d2 * O[2];
-    const double disc = ou * ou - (O[0] * O[0] + O[1] * O[1] + O[2] * O[2]) + r * r;
+    // the observer by value (a pointer into the argument struct would put a
+    // copy of it in scratch memory)
+    const double O0 = S.obs_xyz_au[0], O1 = S.obs_xyz_au[1], O2 = S.obs_xyz_au[2];
+    const double ou = d0 * O0 + d1 * O1 + d2 * O2;
+    const double disc = ou * ou - (O0 * O0 + O1 * O1 + O2 * O2) + r * r;
     if (!(disc > 0.0)) continue;
     const double s = -ou + sqrt(disc);
     if (!(s > 0.0)) continue;
-    const double X0 = O[0] + s * d0, X1 = O[1] + s * d1, X2 = O[2] + s * d2;
+    const double X0 = O0 + s * d0, X1 = O1 + s * d1, X2 = O2 + s * d2;
     const double xn = sqrt(X0 * X0 + X1 * X1 + X2 * X2);
     const double beta = asin(fmin(fmax(X2 / xn, -1.0), 1.0));
     const double lam = atan2(X1, X0);
@@ -73,8 +78,6 @@ __device__ inline bool gen_orbit(const dt_orbit_sampler& S, uint64_t idx, double
     el[5] = (M0 + PI) - tp * floor((M0 + PI) / tp) - PI;
     return true;
   }
-  el[0] = __builtin_nan("");
-  el[1] = el[2] = el[3] = el[4] = el[5] = 0.0;
   return false;
 }
 
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(256) void k_generate(dt_orbit_sampler S, int64_t fi
                                                   double* __restrict__ m0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double el[6];
+  double el[6] = {__builtin_nan(""), 0.0, 0.0, 0.0, 0.0, 0.0};  // a = NaN: no orbit at this index
   gen_orbit(S, (uint64_t)(first + i), el);
   a[i] = el[0];
   e[i] = el[1];
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(256) void k_generate(dt_orbit_sampler S, int64_t fi
 __global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_sampler S, int64_t first) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
-  double el[6];
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   float snr = __builtin_nanf(""), flux = __builtin_nanf("");
   int nv = -1;
   if (gen_orbit(S, (uint64_t)(first + i), el) && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5])) {

@@ -4,17 +4,19 @@
 // cross-entropy loss, Adam and parameter initialisation.
 //
 // GEMM: C[M x N] = op(A)[M x K] op(B)[K x N], A and B bfloat16, FP32
-// accumulation on v_mfma_f32_16x16x16_bf16.  A workgroup of four waves owns a
-// 64 x 64 tile of C (each wave 32 x 32 = 2 x 2 MFMA tiles); K advances in
-// steps of 32 through LDS tiles stored K-contiguous so that every lane's MFMA
-// operand (four consecutive K values) is one 8-byte LDS read.  Split-K writes
+// accumulation on gfx950's v_mfma_f32_16x16x32_bf16.  A workgroup of four
+// waves owns a 64 x 64 tile of C (each wave 32 x 32 = 2 x 2 MFMA tiles); K
+// advances in steps of 32 (one MFMA per tile) through LDS tiles stored
+// K-contiguous so that every lane's MFMA operand (eight consecutive K values)
+// is one 16-byte LDS read.  A lane's A and B operands cover the same eight K
+// indices, so the products the instruction pairs are those of one K.  Split-K writes
 // FP32 partial tiles that a second kernel sums in a fixed order, so results
 // are deterministic.
 #include "dt_common.hpp"
 
 namespace dtk {
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -34,8 +36,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ 
                                                    int N, int K, int k_per_split, float* __restrict__ part,
                                                    const float* __restrict__ bias, int relu, float* __restrict__ Cf,
                                                    int ldcf, uint16_t* __restrict__ Cb, int ldcb) {
-  __shared__ uint16_t sA[GT_M][GT_K + 4];  // [m][k]
-  __shared__ uint16_t sB[GT_N][GT_K + 4];  // [n][k]
+  // [m][k] and [n][k]; rows of 80 bytes keep every 8-element operand 16-byte aligned
+  __shared__ __attribute__((aligned(16))) uint16_t sA[GT_M][GT_K + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[GT_N][GT_K + 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * GT_M, n0 = blockIdx.y * GT_N;
   const int kb = blockIdx.z * k_per_split;
@@ -65,21 +68,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ 
       sB[r][c] = vb;
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < GT_K; ks += 16) {
-      const int kk = ks + 4 * (lane >> 4);
-      short4_t a[2], b[2];
+    {
+      const int kk = 8 * (lane >> 4);
+      bf16x8_t a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        const uint16_t* pa = &sA[wm + 16 * i + (lane & 15)][kk];
-        a[i] = short4_t{(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
-        const uint16_t* pb = &sB[wn + 16 * i + (lane & 15)][kk];
-        b[i] = short4_t{(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
+        a[i] = *(const bf16x8_t*)&sA[wm + 16 * i + (lane & 15)][kk];
+        b[i] = *(const bf16x8_t*)&sB[wn + 16 * i + (lane & 15)][kk];
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }

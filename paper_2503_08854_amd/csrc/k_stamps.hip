@@ -327,8 +327,9 @@ __global__ __launch_bounds__(256, 4) void k_stack_cells_track(StackArgs A, const
 // lattice coordinates u = (a_m - a_rep) / da, v = (M0_m - M0_rep) / dm (the
 // representative is the cell's first member); it is listed when |u - u*| and
 // |v - v*| are both at most `radius`, (u*, v*) = uv[c * uv_stride + 0, 1].
-// One lane per member; a wavefront appends its listed members with one atomic.
-__global__ __launch_bounds__(256) void k_cell_members_near(StackArgs A, const int64_t* __restrict__ cells,
+// One lane per member; a workgroup appends its listed members with one atomic.
+constexpr int NEAR_WG = 1024;  // members per workgroup (one atomic per workgroup)
+__global__ __launch_bounds__(NEAR_WG) void k_cell_members_near(StackArgs A, const int64_t* __restrict__ cells,
                                                            int64_t n_sel, int cell_size, const float* __restrict__ uv,
                                                            int uv_stride, double ida, double idm, double radius,
                                                            int64_t* __restrict__ ids, int64_t* __restrict__ count) {
@@ -347,16 +348,27 @@ __global__ __launch_bounds__(256) void k_cell_members_near(StackArgs A, const in
       }
     }
   }
+  // the workgroup's listed members get consecutive slots from one atomic
+  // (one per wavefront made the atomics on the single counter the cost)
+  __shared__ int wcnt[NEAR_WG / 64];
+  __shared__ int64_t wbase[NEAR_WG / 64];
   const uint64_t mask = __builtin_amdgcn_ballot_w64(take);
-  if (!mask) return;
-  const int lane = (int)__lane_id();
-  const int leader = __builtin_ffsll((long long)mask) - 1;
-  int64_t base = 0;
-  if (lane == leader) base = (int64_t)atomicAdd((unsigned long long*)count, (unsigned long long)__builtin_popcountll(mask));
-  base = __shfl(base, leader, 64);
+  const int lane = (int)__lane_id(), wave = (int)(threadIdx.x >> 6);
+  if (lane == 0) wcnt[wave] = __builtin_popcountll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t tot = 0;
+    for (int w = 0; w < NEAR_WG / 64; ++w) {
+      wbase[w] = tot;
+      tot += wcnt[w];
+    }
+    const int64_t b = tot > 0 ? (int64_t)atomicAdd((unsigned long long*)count, (unsigned long long)tot) : 0;
+    for (int w = 0; w < NEAR_WG / 64; ++w) wbase[w] += b;
+  }
+  __syncthreads();
   if (take) {
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-    ids[base + rank] = o;
+    ids[wbase[wave] + rank] = o;
   }
 }
 
@@ -509,8 +521,8 @@ hipError_t launch_cell_members_near(const StackArgs& a, const int64_t* d_cells, 
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, d_count);
   const int64_t n = n_sel * cell_size;
   if (n > 0)
-    hipLaunchKernelGGL(k_cell_members_near, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, d_cells, n_sel,
-                       cell_size, d_uv, uv_stride, 1.0 / da, 1.0 / dm, radius, d_ids, d_count);
+    hipLaunchKernelGGL(k_cell_members_near, dim3((unsigned)((n + NEAR_WG - 1) / NEAR_WG)), dim3(NEAR_WG), 0, s, a,
+                       d_cells, n_sel, cell_size, d_uv, uv_stride, 1.0 / da, 1.0 / dm, radius, d_ids, d_count);
   return hipGetLastError();
 }
 

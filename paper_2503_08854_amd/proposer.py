@@ -54,13 +54,16 @@ def stack_selected(ctx, patch, grid, cells, cell_size: int, da: float, dm: float
 
 
 def run_learned(ctx, patch, grid, reps, cell_size: int, da: float, dm: float, scorer, budget: int, out=None,
-                radius=None, prefilter=None):
+                radius=None, prefilter=None, mark=None):
     """Stamps -> scores -> top cells -> stack on their orbits (all members, or
     those near the stamp peak). With prefilter = m, only the m cells of
-    largest stamp maximum are scored (the rest rank last).  Returns
-    (outputs, selected cell ids)."""
+    largest stamp maximum are scored (the rest rank last).  mark(stage), if
+    given, is called after each stage (for timing).  Returns (outputs,
+    selected cell ids)."""
+    mark = mark or (lambda stage: None)
     o = B.cell_stamps(patch, reps, da, dm, bf16=True, f32=False,
                       feats_f32=radius is not None or prefilter is not None)
+    mark("stamps")
     if prefilter is None:
         z = score_cells(scorer, o["stamps_bf16"], o["feats_bf16"])
     else:
@@ -68,8 +71,11 @@ def run_learned(ctx, patch, grid, reps, cell_size: int, da: float, dm: float, sc
         rows = select_cells(ctx, o["feats"][:, 0].contiguous(), prefilter)
         z = torch.full((reps.n,), float("-inf"), dtype=torch.float32, device=rows.device)
         scorer.infer_rows(o["stamps_bf16"], o["feats_bf16"], rows, z)
+    mark("scores")
     cells = select_cells(ctx, z, budget)
+    mark("select")
     out = stack_selected(ctx, patch, grid, cells, cell_size, da, dm, o["feats"], radius, out=out)
+    mark("stack")
     return out, cells
 
 
