@@ -387,10 +387,10 @@ dt_status dt_cell_members_near(dt_ctx *ctx, const dt_orbits *grid, const int64_t
  * at the orbits' own indices of d_snr / d_flux / d_nvalid (device, orbits->n
  * each); other entries are left untouched.  Valid counts equal dt_stack's
  * for the same orbits (up to samples within ~1e-11 px of a rounding
- * boundary); lists of at most 2^18 entries are walked with each orbit's
+ * boundary); a list whose count is at most 2^17 is walked with each orbit's
  * exposures split over eight wavefronts whose compensated sums are merged
  * in exposure order, so S/N and flux agree with dt_stack's to rounding.  The
- * count stays on the device: nothing synchronises. */
+ * count stays on the device (the kernels read it; nothing synchronises). */
 dt_status dt_stack_ids(dt_patch *p, const dt_orbits *orbits, const int64_t *d_ids, const int64_t *d_count,
                        int64_t m_max, float *d_snr, float *d_flux, int32_t *d_nvalid);
 

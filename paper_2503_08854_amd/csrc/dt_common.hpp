@@ -170,10 +170,12 @@ hipError_t launch_segment_max(const float* x, int64_t n_seg, int seg, float* out
 hipError_t launch_cell_members_near(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,
                                     const float* d_uv, int uv_stride, double da, double dm, double radius,
                                     int64_t* d_ids, int64_t* d_count, hipStream_t s);
-// Id lists of at most STACK_IDS_SHORT entries are walked per sample with the
-// exposures split over eight wavefronts per 64 orbits (latency-bound sizes);
-// longer ones by the checkpoint walk with deferral.
-constexpr int64_t STACK_IDS_SHORT = (int64_t)1 << 18;
+// Id lists whose count (read on the device) is at most STACK_IDS_SHORT are
+// walked per sample with the exposures split over eight wavefronts per 64
+// orbits (latency-bound sizes); longer ones by the checkpoint walk with
+// deferral.  Both kernels are launched when m_max exceeds STACK_IDS_SHORT;
+// the one not meant for the count returns at once.
+constexpr int64_t STACK_IDS_SHORT = (int64_t)1 << 17;
 hipError_t launch_stack_ids(const StackArgs& a, const int64_t* d_ids, const int64_t* d_count, int64_t m_max,
                             hipStream_t s);
 hipError_t launch_stack_cells(const StackArgs& a, const int64_t* d_cells, int64_t n_sel, int cell_size,

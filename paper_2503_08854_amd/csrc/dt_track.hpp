@@ -26,8 +26,9 @@
 //
 // The prediction pays while most samples miss.  A wavefront whose orbits land
 // often (more than TRACK_SWITCH of its lane-exposures queued, once
-// TRACK_SWITCH_MIN exposures are tested, e.g. distant objects the field
-// follows for months) gives its orbits up when the launch allows it:
+// TRACK_SWITCH_MIN exposures are tested or its queue is full, e.g. distant
+// objects the field follows for months) gives its orbits up when the launch
+// allows it:
 // it appends its first orbit index to the deferral list and writes nothing;
 // a second, persistent kernel walks the deferred wavefronts per sample from
 // the first exposure (the per-sample walk's own sky-cone test, no queue).
@@ -303,8 +304,10 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       count += __builtin_popcountll(mask);
       full = count >= 64 || __builtin_amdgcn_ballot_w64(len >= TQ_LIST) != 0;
       // most samples may land: leave these orbits to the per-sample walk
-      // (nothing queued is served; the loop ends at its next test)
-      tail = may_defer && ex + 1 >= TRACK_SWITCH_MIN &&
+      // (nothing queued is served; the loop ends at its next test).  A queue
+      // that fills before TRACK_SWITCH_MIN exposures decides at once, rather
+      // than serving solves the per-sample walk would repeat.
+      tail = may_defer && (ex + 1 >= TRACK_SWITCH_MIN || full) &&
              (float)(queued + count) > TRACK_SWITCH * 64.f * (float)(ex + 1);
     }
   }

@@ -381,7 +381,8 @@ __global__ __launch_bounds__(256, 4) void k_stack_ids_track(StackArgs A, const i
                                                             const int64_t* __restrict__ count) {
   __shared__ TrackQueue tq[4];
   const int64_t m = *count;
-  if (wave_base() >= m) return;  // the whole wavefront is past the end
+  if (m <= STACK_IDS_SHORT) return;  // a short list: k_stack_ids_split walks it
+  if (wave_base() >= m) return;      // the whole wavefront is past the end
   bool ok;
   float snr, flux;
   int nv;
@@ -430,7 +431,8 @@ __global__ __launch_bounds__(256, 4) void k_stack_ids_deferred(StackArgs A, cons
 __global__ __launch_bounds__(256) void k_stack_ids(StackArgs A, const int64_t* __restrict__ ids,
                                                    const int64_t* __restrict__ count) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= *count) return;
+  const int64_t m = *count;
+  if (m <= STACK_IDS_SHORT || r >= m) return;  // a short list: k_stack_ids_split walks it
   const int64_t o = ids[r];
   if (o < 0 || o >= A.n) return;
   float snr, flux;
@@ -455,6 +457,7 @@ __global__ __launch_bounds__(64 * IDS_SPLIT) void k_stack_ids_split(StackArgs A,
   const int64_t m = *count;
   const int j = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  if (m > STACK_IDS_SHORT) return;            // a long list: k_stack_ids_track walks it
   if ((int64_t)blockIdx.x * 64 >= m) return;  // the whole workgroup is past the end
   const int64_t o = r < m ? ids[r] : -1;
   const bool ok = o >= 0 && o < A.n;
@@ -530,18 +533,20 @@ hipError_t launch_stack_ids(const StackArgs& a, const int64_t* d_ids, const int6
                             hipStream_t s) {
   if (m_max <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((m_max + 255) / 256);
-  if (m_max <= STACK_IDS_SHORT) {
-    hipLaunchKernelGGL(k_stack_ids_split, dim3((unsigned)((m_max + 63) / 64)), dim3(64 * IDS_SPLIT), 0, s, a, d_ids,
-                       d_count);
-  } else if (a.vobs < __builtin_inf()) {
-    if (a.defer_list) {
-      hipError_t e = launch_zero_u32(a.defer_count, s);
-      if (e != hipSuccess) return e;
+  const int64_t m_short = m_max < STACK_IDS_SHORT ? m_max : STACK_IDS_SHORT;
+  hipLaunchKernelGGL(k_stack_ids_split, dim3((unsigned)((m_short + 63) / 64)), dim3(64 * IDS_SPLIT), 0, s, a, d_ids,
+                     d_count);
+  if (m_max > STACK_IDS_SHORT) {  // the count may be long: the kernels for long lists too
+    if (a.vobs < __builtin_inf()) {
+      if (a.defer_list) {
+        hipError_t e = launch_zero_u32(a.defer_count, s);
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(k_stack_ids_track, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
+      if (a.defer_list) hipLaunchKernelGGL(k_stack_ids_deferred, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
+    } else {
+      hipLaunchKernelGGL(k_stack_ids, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
     }
-    hipLaunchKernelGGL(k_stack_ids_track, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
-    if (a.defer_list) hipLaunchKernelGGL(k_stack_ids_deferred, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
-  } else {
-    hipLaunchKernelGGL(k_stack_ids, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
   }
   return hipGetLastError();
 }

@@ -402,6 +402,36 @@ def test_members_near_and_id_stack(cells):
     assert np.all(part[2][~listed] == -2) and np.all(np.isnan(part[0][~listed]))
 
 
+def test_id_stack_short_and_long_lists(cells):
+    """The id-list stack picks its walk from the count on the device: a short
+    list in a long buffer (the per-sample split walk, with the long-list
+    kernels launched and returning at once) and a list longer than 2^17 (the
+    checkpoint walk with deferral; every orbit listed several times) both
+    give the full stack's valid counts and S/N on the listed orbits."""
+    import torch
+    import paper_2503_08854_amd as dt
+    c = cells
+    n = c["grid"].n
+    full = [t.cpu().numpy() for t in dt.stack(c["patch"], c["grid"])]
+    rng = np.random.default_rng(9)
+    reps = (1 << 17) // n + 2
+    long_ids = np.tile(np.arange(n, dtype=np.int64), reps)
+    rng.shuffle(long_ids)
+    ids = torch.from_numpy(long_ids).cuda()
+    for count, name in ((min(n, 5000), "short"), (long_ids.size, "long")):
+        assert (count > (1 << 17)) == (name == "long")
+        cnt = torch.tensor([count], dtype=torch.int64, device="cuda")
+        part = [t.cpu().numpy() for t in dt.stack_ids(c["patch"], c["grid"], ids, cnt)]
+        torch.cuda.synchronize()
+        listed = np.zeros(n, bool)
+        listed[long_ids[:count]] = True
+        assert listed.sum() > 100, name
+        np.testing.assert_array_equal(part[2][listed], full[2][listed], err_msg=name)
+        for k in (0, 1):
+            np.testing.assert_allclose(part[k][listed], full[k][listed], rtol=1e-6, atol=1e-6, err_msg=name)
+        assert np.all(part[2][~listed] == -2), name
+
+
 def test_coarse_to_fine_matches_oracle(cells):
     """Coarse-to-fine: 3 x 3 sub-representatives per cell stacked on the
     widened-PSF planes (against the oracle on the same widened exposures),
