@@ -93,8 +93,9 @@ __device__ __forceinline__ void track_bound(double a, double e, const Orbit& o, 
 // meaningless), see the file comment.
 //
 // REC (debug kernels only): every sample the walk solves exactly is written
-// to row rowbase + lane of dbg (the owner's row for queued samples).
-template <bool REC = false>
+// to row rowbase + lane of dbg (the owner's row for queued samples).  DEFER
+// false compiles the deferral out (launches that never defer).
+template <bool REC = false, bool DEFER = true>
 __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, const TrackBound& bd, bool live,
                                            TrackQueue& Qm, StackPart& P, bool& deferred,
                                            const DebugArgs* dbg = nullptr, int64_t rowbase = 0) {
@@ -134,8 +135,9 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   int queued = 0;    // samples queued so far (wave-uniform)
   bool full = false; // the queue must be served before more samples are pushed
   int ex = 0;
+  int n_tested = 0;  // exposures tested by prediction (wave-uniform)
   bool tail = false; // give the orbits up for the per-sample walk
-  const bool may_defer = A.defer_list != nullptr;
+  const bool may_defer = DEFER && A.defer_list != nullptr;
 
   for (; ex <= A.n_exp && !tail; ++ex) {
     const bool last = ex == A.n_exp;
@@ -146,7 +148,11 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
     double p2 = fma(fma(h2, D, v2), D, r2) - x.oz;
     const bool ck = !last && (ex == 0 || D > CK_SPAN);
     const bool fl = count > 0 && (last || ck || full);
-    if (fl || ck) {
+    // a wavefront due to serve its queue whose queued fraction is already
+    // above TRACK_SWITCH defers now rather than solve samples the per-sample
+    // walk repeats (nothing more is queued; the loop ends at its next test)
+    tail = may_defer && fl && !last && (float)(queued + count) > TRACK_SWITCH * 64.f * (float)n_tested;
+    if ((fl || ck) && !tail) {
       const int nb = fl ? (count + 63) >> 6 : 0;
       float tg_ck = 0.f;  // a Newton start only
       if (ck && ex > 0) {
@@ -285,6 +291,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       p2 = fma(fma(h2, D, v2), D, r2) - y.oz;
     }
     if (last) break;
+    n_tested += tail ? 0 : 1;
     // cone test of the prediction (bitwise logic, no branches)
     const double sc = fma(x.ux, p0, fma(x.uy, p1, x.uz * p2));
     const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
@@ -307,8 +314,8 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       // (nothing queued is served; the loop ends at its next test).  A queue
       // that fills before TRACK_SWITCH_MIN exposures decides at once, rather
       // than serving solves the per-sample walk would repeat.
-      tail = may_defer && (ex + 1 >= TRACK_SWITCH_MIN || full) &&
-             (float)(queued + count) > TRACK_SWITCH * 64.f * (float)(ex + 1);
+      tail = may_defer && (n_tested >= TRACK_SWITCH_MIN || full) &&
+             (float)(queued + count) > TRACK_SWITCH * 64.f * (float)n_tested;
     }
   }
   deferred = tail;
@@ -316,7 +323,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   if (A.work && lane == 0) {
     // wave totals (uniform values) into this workgroup's slot
     unsigned long long* w = A.work + WORK_N * (blockIdx.x % WORK_SLOTS);
-    atomicAdd(w + WORK_PRED, nl * (unsigned long long)(tail ? ex : A.n_exp));  // a deferral ends the loop after the cone test of ex - 1
+    atomicAdd(w + WORK_PRED, nl * (unsigned long long)n_tested);
     atomicAdd(w + WORK_QUEUED, (unsigned long long)queued);
     atomicAdd(w + WORK_CKPT, nl * (unsigned long long)n_ck);
     if (tail) atomicAdd(w + WORK_SWITCHED, 1ull);
@@ -328,7 +335,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
 // per-sample stack (NaN, NaN, -1 for an orbit that is not live), or nothing
 // when the wavefront deferred its orbits (returns true).  All 64 lanes of the
 // wavefront call it together; Q is the wavefront's LDS queue.
-template <bool REC = false>
+template <bool REC = false, bool DEFER = true>
 __device__ __forceinline__ bool track_stack_lane(const StackArgs& A, const double el[6], bool live, TrackQueue& Q,
                                                  float& snr, float& flux, int& nv, const DebugArgs* dbg = nullptr,
                                                  int64_t rowbase = 0) {
@@ -343,7 +350,7 @@ __device__ __forceinline__ bool track_stack_lane(const StackArgs& A, const doubl
   track_bound(a, e, ob, A.vobs, bd);
   StackPart P;
   bool deferred = false;
-  track_walk<REC>(A, ob, bd, live, Q, P, deferred, dbg, rowbase);
+  track_walk<REC, DEFER>(A, ob, bd, live, Q, P, deferred, dbg, rowbase);
   snr = flux = __builtin_nanf("");
   nv = -1;
   if (deferred) return true;
