@@ -305,7 +305,14 @@ typedef struct {
 dt_status dt_generate_orbits(dt_ctx *ctx, const dt_orbit_sampler *sampler, int64_t first, int64_t n, double *d_a,
                              double *d_e, double *d_inc, double *d_node, double *d_peri, double *d_m0);
 /* dt_stack on orbits first .. first + n - 1 of the sampler, generated in
- * registers (no element arrays); outputs (device, n each) as dt_stack. */
+ * registers (no element arrays); outputs (device, n each) as dt_stack.
+ * With a finite observer-speed bound and n > 2^23, the first 2^22 orbits
+ * run the checkpoint walk first; if at least 90 % of their wavefronts defer
+ * to the per-sample walk (orbits that land in most exposures), the other
+ * orbits go to the per-sample walk directly.  That decision reads one count
+ * back, so such a call synchronises the context stream once (it cannot be
+ * captured into a graph); it depends only on those orbits and the
+ * exposures, so results stay deterministic. */
 dt_status dt_stack_generated(dt_patch *p, const dt_orbit_sampler *sampler, int64_t first, int64_t n, float *d_snr,
                              float *d_flux, int32_t *d_nvalid);
 

@@ -114,7 +114,30 @@ dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t fir
     st = defer_setup(p->ctx, n, a);
     if (st != DT_OK) return st;
   }
-  hipError_t e = launch_stack_generated(a, *S, first, p->ctx->stream);
+  if (n <= 2 * GEN_PROBE || !a.defer_list) {
+    hipError_t e = launch_stack_generated(a, *S, first, p->ctx->stream);
+    return e == hipSuccess ? DT_OK : hip_fail(e, "generate-and-stack launch");
+  }
+  // Probe: the first GEN_PROBE orbits with the checkpoint walk.  The orbits
+  // of one sampler are alike, so the share of its wavefronts that defer
+  // (read back once; a pure function of those orbits and the exposures)
+  // picks the walk for the rest.
+  StackArgs a1 = a;
+  a1.n = GEN_PROBE;
+  hipError_t e = launch_stack_generated(a1, *S, first, p->ctx->stream);
+  unsigned int deferred = 0;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&deferred, a.defer_count, sizeof(deferred), hipMemcpyDeviceToHost, p->ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "generate-and-stack probe");
+  StackArgs a2 = a;
+  a2.n = n - GEN_PROBE;
+  if (a2.snr) a2.snr += GEN_PROBE;
+  if (a2.flux) a2.flux += GEN_PROBE;
+  if (a2.nvalid) a2.nvalid += GEN_PROBE;
+  const bool walk = (double)deferred >= GEN_PROBE_DEFER * (double)(GEN_PROBE / 64);
+  e = walk ? launch_stack_generated_walk(a2, *S, first + GEN_PROBE, p->ctx->stream)
+           : launch_stack_generated(a2, *S, first + GEN_PROBE, p->ctx->stream);
   return e == hipSuccess ? DT_OK : hip_fail(e, "generate-and-stack launch");
 }
 

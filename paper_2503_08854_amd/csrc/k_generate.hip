@@ -170,6 +170,31 @@ hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, 
   return hipGetLastError();
 }
 
+// The per-sample walk of orbits first + i with the work counters (all
+// wavefronts walk; used for the orbits after a probe whose wavefronts almost
+// all deferred).
+__global__ __launch_bounds__(256, 4) void k_stack_generated_walk(StackArgs A, dt_orbit_sampler S, int64_t first) {
+  if (wave_base() >= A.n) return;  // the whole wavefront is past the end
+  const int64_t i = wave_base() + __lane_id();
+  const bool in = i < A.n;
+  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool live = in && gen_orbit(S, (uint64_t)(first + i), el) &&
+                    orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
+  float snr, flux;
+  int nv;
+  deferred_lane(A, el, live, snr, flux, nv);
+  if (!in) return;
+  if (A.snr) A.snr[i] = snr;
+  if (A.flux) A.flux[i] = flux;
+  if (A.nvalid) A.nvalid[i] = nv;
+}
+
+hipError_t launch_stack_generated_walk(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stack_generated_walk, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
+  return hipGetLastError();
+}
+
 hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   if (a.vobs < __builtin_inf()) {

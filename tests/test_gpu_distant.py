@@ -26,7 +26,14 @@ def test_distant_full_size_sampled():
     patch = dt.Patch(ctx, w.exps, w.D, w.V)
     out = (torch.empty(n, dtype=torch.float32, device="cuda"), torch.empty(n, dtype=torch.float32, device="cuda"),
            torch.empty(n, dtype=torch.int32, device="cuda"))
+    ctx.count_work(True)
     dt.stack_generated(patch, gpu_sampler(gs), 0, n, out)
+    wk = ctx.work()
+    ctx.count_work(False)
+    # these orbits land in most exposures: the probe's wavefronts all defer and
+    # the rest go straight to the per-sample walk
+    assert wk["switched_waves"] == (1 << 22) // 64, wk
+    assert wk["tail_samples"] == n * len(w.exps), wk
     k = 100
     idx, val, cnt = dt.topk(ctx, out[0], k, 5.0)
     torch.cuda.synchronize()

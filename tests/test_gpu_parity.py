@@ -445,6 +445,35 @@ def test_generate_and_stack_matches_stack_and_oracle(small):
     assert (nv_o > 0).sum() > 100
 
 
+def test_generated_probe_then_rest_matches_stack(small):
+    """More than 2^23 generated orbits: the first 2^22 run the checkpoint walk
+    as a probe, whose deferral rate picks the walk for the rest.  Whichever
+    it picks, valid counts equal those of dt_stack on the same generated
+    elements and S/N agrees to rounding."""
+    import torch
+    import paper_2503_08854_amd as dt
+    w = small
+    ctx = dt.Context(0)
+    Dt, Vt = to_torch_images(w.D, w.V)
+    patch = dt.Patch(ctx, w.exps, Dt, Vt)
+    S, So = _sampler_pair(21)
+    n, first = (1 << 23) + 3 * (1 << 16) + 37, 5
+    ctx.count_work(True)
+    snr_g, flux_g, nv_g = dt.stack_generated(patch, S, first, n)
+    wk = ctx.work()
+    ctx.count_work(False)
+    el = dt.generate_orbits(ctx, S, first, n)
+    orb = dt.OrbitSet(el.cpu().numpy(), So["epoch"], "cuda")
+    snr_s, flux_s, nv_s = dt.stack(patch, orb)
+    torch.cuda.synchronize()
+    print("probe path:", wk)
+    np.testing.assert_array_equal(nv_g.cpu().numpy(), nv_s.cpu().numpy())
+    a, b = snr_g.cpu().numpy(), snr_s.cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    assert snr_close(a[~np.isnan(a)], b[~np.isnan(b)], 1e-6).all()
+    assert (nv_g.cpu().numpy() > 0).sum() > 1000
+
+
 def _noise_images(rng):
     ims = []
     x = rng.normal(0.0, 2.0, (256, 256)).astype(np.float32)
