@@ -466,7 +466,8 @@ def bench_distant(args, dev):
                                f"{n} candidate orbits (a 30-60 AU) generated in the stack, top-{args.k} at S/N>=5",
                    "orbits": n, "exposures": ne, "valid_samples": valid, "valid_frac": valid / samples,
                    "phase_ms": {"prepass": pre, "stack": stk, "topk": tk}},
-        "roofline": roofline_block("k_stack_generated_track + k_stack_generated_deferred", stk, n, ne, valid,
+        "roofline": roofline_block("k_stack_generated_track + k_stack_generated_deferred + k_stack_generated_walk",
+                                   stk, n, ne, valid,
                                    flops, False, stack_traffic("distant")),
         "work": work,
         "detections": int(cnt[0]),
