@@ -306,7 +306,7 @@ dt_status dt_generate_orbits(dt_ctx *ctx, const dt_orbit_sampler *sampler, int64
                              double *d_e, double *d_inc, double *d_node, double *d_peri, double *d_m0);
 /* dt_stack on orbits first .. first + n - 1 of the sampler, generated in
  * registers (no element arrays); outputs (device, n each) as dt_stack.
- * With a finite observer-speed bound and n > 2^23, the first 2^22 orbits
+ * With a finite observer-speed bound and n > 2^26, the first 2^22 orbits
  * run the checkpoint walk first; if at least 90 % of their wavefronts defer
  * to the per-sample walk (orbits that land in most exposures), the other
  * orbits go to the per-sample walk directly.  That decision reads one count

@@ -251,11 +251,7 @@ hipError_t launch_generate(const dt_orbit_sampler& S, int64_t first, int64_t n, 
 hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s);
 // Per-sample walk of every generated orbit (no checkpoint kernel, no list).
 hipError_t launch_stack_generated_walk(const StackArgs& a, const dt_orbit_sampler& S, int64_t first, hipStream_t s);
-// Generated-orbit calls larger than 2 GEN_PROBE orbits run the first
-// GEN_PROBE with the checkpoint walk; when at least GEN_PROBE_DEFER of its
-// wavefronts defer, the rest go straight to the per-sample walk.
-constexpr int64_t GEN_PROBE = (int64_t)1 << 22;
-constexpr double GEN_PROBE_DEFER = 0.9;
+
 
 // Resolves, with `device` current, the device address of the allocation-free
 // top-k's fixed scratch array (once per device).

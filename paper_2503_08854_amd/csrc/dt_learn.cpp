@@ -92,6 +92,15 @@ dt_status dt_generate_orbits(dt_ctx* c, const dt_orbit_sampler* S, int64_t first
   return e == hipSuccess ? DT_OK : hip_fail(e, "orbit generation");
 }
 
+// Generated-orbit calls of more than GEN_PROBE_MIN orbits run the first
+// GEN_PROBE with the checkpoint walk; when at least GEN_PROBE_DEFER of its
+// wavefronts defer, the rest go straight to the per-sample walk.  (The
+// probe's read-back costs a stream synchronisation, under 1 % of a call
+// this large.)
+constexpr int64_t GEN_PROBE = (int64_t)1 << 22;
+constexpr int64_t GEN_PROBE_MIN = (int64_t)1 << 26;
+constexpr double GEN_PROBE_DEFER = 0.9;
+
 dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t first, int64_t n, float* d_snr,
                              float* d_flux, int32_t* d_nvalid) {
   if (!p || !p->ctx) return fail(DT_E_ARG, "invalid patch");
@@ -114,7 +123,7 @@ dt_status dt_stack_generated(dt_patch* p, const dt_orbit_sampler* S, int64_t fir
     st = defer_setup(p->ctx, n, a);
     if (st != DT_OK) return st;
   }
-  if (n <= 2 * GEN_PROBE || !a.defer_list) {
+  if (n <= GEN_PROBE_MIN || !a.defer_list) {
     hipError_t e = launch_stack_generated(a, *S, first, p->ctx->stream);
     return e == hipSuccess ? DT_OK : hip_fail(e, "generate-and-stack launch");
   }

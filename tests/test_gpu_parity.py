@@ -446,7 +446,7 @@ def test_generate_and_stack_matches_stack_and_oracle(small):
 
 
 def test_generated_probe_then_rest_matches_stack(small):
-    """More than 2^23 generated orbits: the first 2^22 run the checkpoint walk
+    """More than 2^26 generated orbits: the first 2^22 run the checkpoint walk
     as a probe, whose deferral rate picks the walk for the rest.  Whichever
     it picks, valid counts equal those of dt_stack on the same generated
     elements and S/N agrees to rounding."""
@@ -457,13 +457,14 @@ def test_generated_probe_then_rest_matches_stack(small):
     Dt, Vt = to_torch_images(w.D, w.V)
     patch = dt.Patch(ctx, w.exps, Dt, Vt)
     S, So = _sampler_pair(21)
-    n, first = (1 << 23) + 3 * (1 << 16) + 37, 5
+    n, first = (1 << 26) + 3 * (1 << 16) + 37, 5
     ctx.count_work(True)
     snr_g, flux_g, nv_g = dt.stack_generated(patch, S, first, n)
     wk = ctx.work()
     ctx.count_work(False)
     el = dt.generate_orbits(ctx, S, first, n)
-    orb = dt.OrbitSet(el.cpu().numpy(), So["epoch"], "cuda")
+    orb = dt.OrbitSet(el, So["epoch"], "cuda")   # device to device
+    del el
     snr_s, flux_s, nv_s = dt.stack(patch, orb)
     torch.cuda.synchronize()
     print("probe path:", wk)
