@@ -268,21 +268,23 @@ TIME_CURVE = (0.005, 0.01, 0.02, 0.03, 0.05, 0.08, 0.12, 0.2, 0.3)  # budgets ti
 
 
 def bench_learned(dev, n_train=100, n_eval=50, budgets=(0.01, 0.02, 0.05), n_eval_side=20, radius=LEARNED_RADIUS,
-                  prefilter=LEARNED_PREFILTER):
-    """Learned vs plain recall at S/N >= 5 and speedup on the cell-structured
-    survey grid, on two populations: the injections alone ("clean") and with
-    single-exposure point artifacts in every image ("artifacts", where the
-    stamp maximum alone no longer ranks cells).  One scorer, trained on
-    method-generated stacks with artifacts.  Coarse-max is evaluated at the
-    same budget and at equal time: at the budget whose pass takes as long as
-    the learned pass (interpolated in a timed budget curve)."""
+                  prefilter=LEARNED_PREFILTER, setup="learned", coarse_to_fine=True):
+    """Learned vs plain recall at S/N >= 5 and speedup on a cell-structured
+    grid (the survey exposures, or with setup="distant_cells" the distant-
+    object exposures), on two populations: the injections alone ("clean")
+    and with single-exposure point artifacts in every image ("artifacts",
+    where the stamp maximum alone no longer ranks cells).  One scorer,
+    trained on method-generated stacks with artifacts.  Coarse-max is
+    evaluated at the same budget and at equal time: at the budget whose pass
+    takes as long as the learned pass (interpolated in a timed budget
+    curve); coarse-to-fine when its widened-PSF patch is built."""
     import torch
     import learned_eval as le
     import paper_2503_08854_amd as dt
     t = time.time()
-    s = le.load_setup("learned")
+    s = le.load_setup(setup)
     ctx = dt.Context(0)
-    b = le.Bench(s, ctx, dev)
+    b = le.Bench(s, ctx, dev, coarse_to_fine=coarse_to_fine)
     X, F, Y = le.training_set(b, n_train, seed=1, artifacts=le.ARTIFACTS)
     torch.cuda.synchronize()
     log(f"learned: {X.shape[0]} method-generated stacks with artifacts ({time.time() - t:.1f} s)")
@@ -295,9 +297,11 @@ def bench_learned(dev, n_train=100, n_eval=50, budgets=(0.01, 0.02, 0.05), n_eva
     keys = ("budget_frac", "injections", "plain_found", "recall_ratio_learned", "recall_ratio_coarse",
             "recall_ratio_coarse_to_fine", "t_plain_ms", "t_learned_ms", "t_coarse_ms", "speedup", "speedup_coarse",
             "coarse_equal_time_budget_frac", "recall_ratio_coarse_equal_time", "t_coarse_equal_time_ms")
-    res = dict(train_stacks=n_train * s.n_cells, train_s=t_train, loss_first=hist[0][1], loss_last=hist[-1][1],
+    res = dict(setup=f"{setup}: {s.n_cells} cells x {s.cell_size} orbits on {len(s.exps)} exposures "
+                     f"({s.geom.get('dtype', 'f32')})", train_stacks=n_train * s.n_cells, train_s=t_train,
+               loss_first=hist[0][1], loss_last=hist[-1][1],
                artifacts={"per_image": le.ARTIFACTS[0], "snr": list(le.ARTIFACTS[1])}, radius=radius,
-               prefilter=prefilter, coarse_to_fine_subs=b.sub_k * b.sub_k)
+               prefilter=prefilter, coarse_to_fine_subs=b.sub_k * b.sub_k if coarse_to_fine else None)
     for pop, art in (("clean", None), ("artifacts", le.ARTIFACTS)):
         curve = le.pass_times(b, sc, TIME_CURVE, radius=radius, prefilter=prefilter, artifacts=art)
         res[f"time_curve_{pop}"] = dict(budget_frac=list(TIME_CURVE), learned_ms=curve["learned"],
@@ -309,9 +313,10 @@ def bench_learned(dev, n_train=100, n_eval=50, budgets=(0.01, 0.02, 0.05), n_eva
             r = le.evaluate(b, sc, budget_frac=bud, n_real=n_eval if bud == 0.02 else n_eval_side, artifacts=art,
                             radius=radius, prefilter=prefilter, coarse_equal_time_frac=b_eq)
             rows.append({k: r[k] for k in keys})
-            log(f"learned {pop} {bud:.0%}: recall ratio learned {r['recall_ratio_learned']:.3f} coarse "
+            c2f = r['recall_ratio_coarse_to_fine']
+            log(f"{setup} {pop} {bud:.0%}: recall ratio learned {r['recall_ratio_learned']:.3f} coarse "
                 f"{r['recall_ratio_coarse']:.3f} (equal time, {b_eq:.1%}: {r['recall_ratio_coarse_equal_time']:.3f}) "
-                f"c2f {r['recall_ratio_coarse_to_fine']:.3f}; speedup {r['speedup']:.1f}x "
+                f"c2f {'-' if c2f is None else f'{c2f:.3f}'}; speedup {r['speedup']:.1f}x "
                 f"(coarse {r['speedup_coarse']:.1f}x)")
         res[pop] = rows
     # headline fields: both populations at a 2 % budget
@@ -323,10 +328,18 @@ def bench_learned(dev, n_train=100, n_eval=50, budgets=(0.01, 0.02, 0.05), n_eva
                population="artifacts", clean_recall_ratio_learned=c["recall_ratio_learned"],
                clean_speedup=c["speedup"])
     sc.close()
-    b.patch.close()
-    b.coarse.close()
+    b.close()
     ctx.close()
     return res
+
+
+def bench_learned_distant(dev):
+    """The learned proposer against the plain stack on the distant-object
+    exposures (400 FP16 4096^2 images, 365 days): 10^4 cells x 10^3 orbits,
+    scorer trained on 30 realizations, 20 (2 %) or 10 evaluation
+    realizations; no coarse-to-fine (its widened-PSF patch would add 54 GB of
+    planes)."""
+    return bench_learned(dev, n_train=30, n_eval=20, n_eval_side=10, setup="distant_cells", coarse_to_fine=False)
 
 
 def timed_steps(step, steps, warmup, n_ev):
@@ -661,7 +674,7 @@ def main():
     ap.add_argument("--probe-copy", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--headline-only", action="store_true", help="only the headline workload's block")
-    ap.add_argument("--only", choices=["survey", "batched", "learned"], default=None,
+    ap.add_argument("--only", choices=["survey", "batched", "learned", "learned_distant"], default=None,
                     help="run only this block (for profiling; prints its JSON)")
     ap.add_argument("--skip-survey", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
@@ -686,7 +699,8 @@ def main():
         fn = {"survey": lambda: bench_survey(args, dev, steps=args.steps or 10,
                                              warmup=args.warmup if args.warmup is not None else 2),
               "batched": lambda: bench_batched(dev, steps=args.steps or 5, check=not args.no_cpu),
-              "learned": lambda: bench_learned(dev)}[args.only]
+              "learned": lambda: bench_learned(dev),
+              "learned_distant": lambda: bench_learned_distant(dev)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     if args.workload == "distant":
@@ -717,6 +731,11 @@ def main():
         L = rec["learned"]
         log(f"learned (artifacts, 2 %): recall ratio {L['recall_ratio_learned']:.3f} (coarse "
             f"{L['recall_ratio_coarse']:.3f}), speedup {L['speedup']:.1f}x")
+        torch.cuda.empty_cache()
+        rec["learned_distant"] = bench_learned_distant(dev)
+        L = rec["learned_distant"]
+        log(f"learned on the distant exposures (artifacts, 2 %): recall ratio {L['recall_ratio_learned']:.3f} "
+            f"(coarse {L['recall_ratio_coarse']:.3f}), speedup {L['speedup']:.1f}x")
         torch.cuda.empty_cache()
     print(json.dumps(rec), flush=True)
 

@@ -59,15 +59,17 @@ def _sum_p2(fwhm: float) -> float:
 class Bench:
     """Device state for one setup: images (refilled per realization), patch, grids."""
 
-    def __init__(self, s: Setup, ctx, device="cuda"):
+    def __init__(self, s: Setup, ctx, device="cuda", coarse_to_fine=True):
         import paper_2503_08854_amd as dt
         self.s = s
         self.ctx = ctx
         self.dev = device
-        self.D, self.V = synth.noise_images(s.exps, 1, s.geom.get("nan_frac", 0.0), "f32", device)
+        self.dtype = s.geom.get("dtype", "f32")
+        self.D, self.V = synth.noise_images(s.exps, 1, s.geom.get("nan_frac", 0.0), self.dtype, device)
         self.patch = dt.Patch(ctx, s.exps, self.D, self.V)
         from paper_2503_08854_amd import proposer
-        self.coarse = proposer.coarse_patch(ctx, s.exps, self.D, self.V)
+        # coarse-to-fine needs a second patch (widened-PSF planes); optional for large image sets
+        self.coarse = proposer.coarse_patch(ctx, s.exps, self.D, self.V) if coarse_to_fine else None
         self.grid = dt.OrbitSet(s.el, s.t0, device)
         self.reps = dt.OrbitSet(s.el[::s.cell_size], s.t0, device)
         self.sub_k = C2F_SUB
@@ -79,11 +81,12 @@ class Bench:
         then, with artifacts = (per_image, (s_lo, s_hi)), single-exposure point
         artifacts of per-image S/N U(s_lo, s_hi) (seeded by the same seed), then
         the pre-pass."""
-        D, V = synth.noise_images(self.s.exps, seed, self.s.geom.get("nan_frac", 0.0), "f32", self.dev)
+        D, V = synth.noise_images(self.s.exps, seed, self.s.geom.get("nan_frac", 0.0), self.dtype, self.dev)
         for a, b in zip(self.D, D):
             a.copy_(b)
         for a, b in zip(self.V, V):
             a.copy_(b)
+        del D, V
         synth.render_sources_fast(self.D, self.s.exps, hits, self.dev)
         if artifacts:
             art = synth.artifacts(self.s.exps, artifacts[0], artifacts[1], seed)
@@ -91,7 +94,13 @@ class Bench:
             art[:, 3] = art[:, 3] * sig / math.sqrt(_sum_p2(self.s.exps[0]["fwhm"]))
             synth.render_sources_fast(self.D, self.s.exps, art, self.dev)
         self.patch.refresh()
-        self.coarse.refresh()
+        if self.coarse is not None:
+            self.coarse.refresh()
+
+    def close(self):
+        self.patch.close()
+        if self.coarse is not None:
+            self.coarse.close()
 
 
 def training_set(bench: Bench, n_real: int, seed: int, pos_frac: float = 0.5, snr_rng=(3.0, 10.0), log=None,
@@ -253,8 +262,9 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
             coarse_eq_snr = out_sel[0].cpu().numpy()
         for t in out_sel:
             t.fill_(float("nan")) if t.dtype == torch.float32 else t.fill_(-2)
-        proposer.run_coarse_to_fine(bench.ctx, bench.patch, bench.coarse, bench.grid, bench.subs,
-                                    bench.sub_k * bench.sub_k, s.cell_size, budget, out=out_sel)
+        if bench.coarse is not None:
+            proposer.run_coarse_to_fine(bench.ctx, bench.patch, bench.coarse, bench.grid, bench.subs,
+                                        bench.sub_k * bench.sub_k, s.cell_size, budget, out=out_sel)
         c2f_snr = out_sel[0].cpu().numpy()
         plain_snr = out_full[0].cpu().numpy()
         orbits = np.array([inj["orbit"] for inj in injs])
@@ -279,7 +289,8 @@ def evaluate(bench: Bench, scorer, budget_frac: float = 0.05, n_real: int = None
                recall_plain=found["plain"] / max(tot, 1),
                recall_ratio_learned=found["learned"] / max(found["plain"], 1),
                recall_ratio_coarse=found["coarse"] / max(found["plain"], 1),
-               recall_ratio_coarse_to_fine=found["c2f"] / max(found["plain"], 1),
+               recall_ratio_coarse_to_fine=(found["c2f"] / max(found["plain"], 1)) if bench.coarse is not None
+               else None,
                t_plain_ms=tp * 1e3, t_learned_ms=tl * 1e3, t_coarse_ms=tc * 1e3, speedup=tp / tl,
                speedup_coarse=tp / tc, radius=radius, prefilter=prefilter, orbits=n)
     if coarse_equal_time_frac is not None:
@@ -353,8 +364,7 @@ def main():
     b.realize(10_000, hits, ARTIFACTS)
     print(stage_times(b, sc, args.budget, args.reps, args.radius, args.prefilter), flush=True)
     sc.close()
-    b.patch.close()
-    b.coarse.close()
+    b.close()
     ctx.close()
 
 

@@ -311,14 +311,15 @@ def batched_small(seed=5):
 
 
 def learned(seed=2, n_cells=10000, cell_size=1000, n_real=50, n_inj=20, name="learned", base=None,
-            snr_rng=(4.0, 12.0), da=2e-3, dm=5e-6):
-    """Cell-structured grid on the survey exposures for the learned proposer:
-    n_cells representatives x cell_size members (perturbed a and M0);
-    n_real realizations of n_inj injections, each on a random member of a
-    random cell, flux set for a stacked S/N target U(4, 12) over its hits."""
+            snr_rng=(4.0, 12.0), da=2e-3, dm=5e-6, a_rng=(2.0, 3.5), e_rng=(0.0, 0.3), inc_rng=(0.0, 15.0)):
+    """Cell-structured grid on the survey exposures (or those of `base`) for
+    the learned proposer: n_cells representatives x cell_size members
+    (perturbed a and M0); n_real realizations of n_inj injections, each on a
+    random member of a random cell, flux set for a stacked S/N target
+    U(snr_rng) over its hits."""
     g = base if base is not None else survey(seed=seed)
     gf = g["grid_field"]
-    grid = dict(cells=n_cells, cell_size=cell_size, a=[2.0, 3.5], e=[0.0, 0.3], inc_deg=[0.0, 15.0], da=da, dm=dm,
+    grid = dict(cells=n_cells, cell_size=cell_size, a=list(a_rng), e=list(e_rng), inc_deg=list(inc_rng), da=da, dm=dm,
                 seed=seed + 100)
     el = synth.cell_grid(gf, n_cells, cell_size, grid["seed"], grid["a"], grid["e"], grid["inc_deg"], da, dm)
     rng = synth.make_rng(seed, 66)
@@ -338,8 +339,8 @@ def learned(seed=2, n_cells=10000, cell_size=1000, n_real=50, n_inj=20, name="le
             injs.append(dict(orbit=o, cell=c, el=[float(v) for v in el[o]], s=s, flux=s / math.sqrt(p2),
                              target=target, hits=hits))
         reals.append(injs)
-    return dict(name=name, seed=seed, t0=g["t0"], dtype="f32", nan_frac=g["nan_frac"], exposures=g["exposures"],
-                grid_field=gf, cell_grid=grid, realizations=reals)
+    return dict(name=name, seed=seed, t0=g["t0"], dtype=g.get("dtype", "f32"), nan_frac=g["nan_frac"],
+                exposures=g["exposures"], grid_field=gf, cell_grid=grid, realizations=reals)
 
 
 def learned_small(seed=3):
@@ -348,9 +349,21 @@ def learned_small(seed=3):
                    base=survey_small(seed=seed))
 
 
+def distant_cells(seed=9):
+    """The learned proposer on the distant-object exposures (400 FP16 4096^2
+    images over 365 days, 0.2"/px): 10^4 cells x 10^3 members drawn like the
+    distant candidates (a 30-60 AU, e 0-0.3, i 0-40 deg), the box +-0.02 AU in
+    a and +-1.5e-5 rad in M0 (member tracks within about +-15 px of the
+    representative's); 20 realizations of 20 injections at stacked S/N
+    U(5, 12)."""
+    return learned(seed=seed, n_cells=10000, cell_size=1000, n_real=20, n_inj=20, name="distant_cells",
+                   base=distant(), snr_rng=(5.0, 12.0), da=0.02, dm=1.5e-5, a_rng=(30.0, 60.0), e_rng=(0.0, 0.3),
+                   inc_rng=(0.0, 40.0))
+
+
 WORKLOADS = {"tiny": tiny, "survey": survey, "survey_small": survey_small, "batched": batched,
              "batched_small": batched_small, "learned": learned, "learned_small": learned_small,
-             "distant_small": distant_small, "distant": distant}
+             "distant_small": distant_small, "distant": distant, "distant_cells": distant_cells}
 
 
 def main(names):

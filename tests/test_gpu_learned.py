@@ -502,5 +502,4 @@ def test_learned_beats_coarse_max_on_artifacts(ctx):
     assert r["recall_ratio_learned"] - r["recall_ratio_coarse"] >= 0.5
     assert b_eq >= 0.02
     sc.close()
-    b.patch.close()
-    b.coarse.close()
+    b.close()
