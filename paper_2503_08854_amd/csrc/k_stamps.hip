@@ -48,6 +48,9 @@ __device__ __forceinline__ float wave_max(float v) {
 // domain) go to this wave's LDS, 3 x n_exp x 16 bytes.
 constexpr int STAMP_CHUNKS = 21;
 
+// GB: usable exposures whose gathers are issued together (more loads in
+// flight per lane where a cell has many usable exposures).
+template <int GB>
 __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, double dm, uint16_t* __restrict__ st_bf,
                                                     float* __restrict__ st_f, uint16_t* __restrict__ ft_bf,
                                                     float* __restrict__ ft_f) {
@@ -111,26 +114,10 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
     return __builtin_isfinite(pa.x) && __builtin_isfinite(pm.x) && p0.x + rx >= -0.5 && p0.x - rx < x.W - 0.5 &&
            p0.y + ry >= -0.5 && p0.y - ry < x.H - 0.5;
   };
-  // The gathers of one usable exposure are accumulated while the next
-  // exposure's are in flight.  Every lane issues all its loads (a node off
-  // the image reads the plane's first pixel and is dropped), so the wait
-  // before an accumulation covers only the older loads.
-  float2 pend[PER];
-  bool pend_ok[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    pend[q] = make_float2(0.f, 0.f);
-    pend_ok[q] = false;
-  }
-  auto accumulate = [&]() {
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      if (pend_ok[q] && pend[q].y > 0.f) {
-        ps[q] += pend[q].x;
-        ph[q] += pend[q].y;
-      }
-    }
-  };
+  // The gathers of up to GB usable exposures are issued together, then
+  // accumulated in exposure order.  Every lane issues all its loads (a node
+  // off the image reads the plane's first pixel and is dropped), so the wait
+  // before each accumulation covers only the older loads.
   for (int c0 = 0; c0 < n_exp; c0 += 64) {
     bool use = false;
     if (c0 + lane < n_exp) {
@@ -140,35 +127,44 @@ __global__ __launch_bounds__(64) void k_cell_stamps(StackArgs R, double da, doub
     }
     uint64_t mask = __ballot(use);
     while (mask) {
-      const int ex = c0 + __builtin_ctzll(mask);
-      mask &= mask - 1;
-      double2 p0;
-      double Ax, Ay, Bx, By;
-      (void)usable(ex, p0, Ax, Ay, Bx, By);
-      const ExpMeta& x = meta[ex];
-      near += (p0.x >= -0.5 && p0.x < x.W - 0.5 && p0.y >= -0.5 && p0.y < x.H - 0.5) ? 1 : 0;
-      float2 cur[PER];
-      bool cur_ok[PER];
+      float2 cur[GB][PER];
+      bool cur_ok[GB][PER];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int j = lane + 64 * q;
-        // the node's track point p0 + u A + v B (two fused multiply-adds)
-        const double px = fma(v[q], Bx, fma(u[q], Ax, p0.x));
-        const double py = fma(v[q], By, fma(u[q], Ay, p0.y));
-        const double fx = floor(px + 0.5), fy = floor(py + 0.5);
-        cur_ok[q] = j < SP && fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H;
-        const int64_t off = cur_ok[q] ? (int64_t)fy * x.W + (int64_t)fx : 0;
-        cur[q] = planes[x.plane_off + off];
+      for (int b = 0; b < GB; ++b) {
+        // no branch: a stage past the last usable exposure reloads exposure
+        // c0's first pixel and drops it, so all GB x PER loads are in flight
+        const bool has = mask != 0;  // wave-uniform
+        const int ex = c0 + (has ? __builtin_ctzll(mask) : 0);
+        mask &= mask - 1;
+        double2 p0;
+        double Ax, Ay, Bx, By;
+        (void)usable(ex, p0, Ax, Ay, Bx, By);
+        const ExpMeta& x = meta[ex];
+        near += (has && p0.x >= -0.5 && p0.x < x.W - 0.5 && p0.y >= -0.5 && p0.y < x.H - 0.5) ? 1 : 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int j = lane + 64 * q;
+          // the node's track point p0 + u A + v B (two fused multiply-adds)
+          const double px = fma(v[q], Bx, fma(u[q], Ax, p0.x));
+          const double py = fma(v[q], By, fma(u[q], Ay, p0.y));
+          const double fx = floor(px + 0.5), fy = floor(py + 0.5);
+          cur_ok[b][q] = has && j < SP && fx >= 0.0 && fx < (double)x.W && fy >= 0.0 && fy < (double)x.H;
+          const int64_t off = cur_ok[b][q] ? (int64_t)fy * x.W + (int64_t)fx : 0;
+          cur[b][q] = planes[x.plane_off + off];
+        }
       }
-      accumulate();
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        pend[q] = cur[q];
-        pend_ok[q] = cur_ok[q];
+      for (int b = 0; b < GB; ++b) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          if (cur_ok[b][q] && cur[b][q].y > 0.f) {
+            ps[q] += cur[b][q].x;
+            ph[q] += cur[b][q].y;
+          }
+        }
       }
     }
   }
-  accumulate();
   float smax = -1e30f, ssum = 0.f, ssq = 0.f, cov = 0.f, smax_c = -1e30f, center = 0.f;
   int amax = 0;
   for (int q = 0; q < PER; ++q) {
@@ -556,7 +552,12 @@ hipError_t launch_cell_stamps(const StackArgs& reps, double da, double dm, uint1
   if (reps.n <= 0) return hipSuccess;
   if (reps.n_exp > STAMP_MAX_EXP) return hipErrorInvalidValue;
   const size_t lds = sizeof(double2) * 3 * (size_t)reps.n_exp;
-  hipLaunchKernelGGL(k_cell_stamps, dim3((unsigned)reps.n), dim3(64), lds, s, reps, da, dm, st_bf, st_f, ft_bf, ft_f);
+  if (reps.n_exp > 256)
+    hipLaunchKernelGGL(k_cell_stamps<4>, dim3((unsigned)reps.n), dim3(64), lds, s, reps, da, dm, st_bf, st_f, ft_bf,
+                       ft_f);
+  else
+    hipLaunchKernelGGL(k_cell_stamps<2>, dim3((unsigned)reps.n), dim3(64), lds, s, reps, da, dm, st_bf, st_f, ft_bf,
+                       ft_f);
   return hipGetLastError();
 }
 
