@@ -44,3 +44,28 @@ def test_noise_and_mask_recipe():
         np.testing.assert_array_equal(m, np.isnan(v))
         assert np.allclose(v[~m], np.float32(x["sigma"] ** 2))
         assert abs(np.nanstd(d) - x["sigma"]) < 0.02 * x["sigma"] + 0.05
+
+
+def test_cell_grid_geometries_match_their_injections():
+    """The learned geometries (survey and distant exposures): the cell grid
+    rebuilt from the stored recipe holds every injection's elements at its
+    orbit index, and the stored hits are the oracle's landing pixels of that
+    orbit (checked on three injections per geometry)."""
+    for name in ("learned_small", "distant_cells"):
+        g = synth.load_geometry(name)
+        cg = g["cell_grid"]
+        el = synth.cell_grid(g["grid_field"], cg["cells"], cg["cell_size"], cg["seed"], cg["a"], cg["e"],
+                             cg["inc_deg"], cg["da"], cg["dm"])
+        exps = synth.exposures_of(g)
+        injs = [i for r in g["realizations"] for i in r]
+        for inj in injs:
+            np.testing.assert_array_equal(el[inj["orbit"]], np.asarray(inj["el"]))
+            assert inj["orbit"] // cg["cell_size"] == inj["cell"] and inj["orbit"] % cg["cell_size"] != 0
+        for inj in injs[:3]:
+            s = oracle.samples(np.asarray(inj["el"])[None, :], g["t0"], exps)
+            land = np.nonzero((s["flags"][0] & 3) == 3)[0]
+            h = np.asarray(inj["hits"], dtype=np.float64)
+            np.testing.assert_array_equal(h[:, 0].astype(int), land)
+            np.testing.assert_allclose(h[:, 1], s["px"][0, land], atol=1e-9)
+            np.testing.assert_allclose(h[:, 2], s["py"][0, land], atol=1e-9)
+    assert g["dtype"] == "f16" and len(exps) == 400 and np.mean([len(i["hits"]) for i in injs]) > 100
