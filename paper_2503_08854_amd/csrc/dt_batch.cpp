@@ -69,6 +69,12 @@ BatchPlan make_plan(dt_patch* const* patches, const dt_orbits* sets, int32_t n_p
   std::stable_sort(pl.items.begin(), pl.items.end(), [&](const WorkItem& x, const WorkItem& y) {
     return (int64_t)patches[x.patch]->n_exp * x.count > (int64_t)patches[y.patch]->n_exp * y.count;
   });
+  // the kernel's wavefronts pull 64 orbits at a time, in this order
+  std::vector<WorkItem> waves;
+  for (const WorkItem& w : pl.items)
+    for (int32_t j = 0; j < w.count; j += 64)
+      waves.push_back(WorkItem{w.patch, std::min<int32_t>(64, w.count - j), w.begin + j});
+  pl.items.swap(waves);
   return pl;
 }
 

@@ -2,13 +2,15 @@
 // orbit-set sizes in one persistent launch.
 //
 // The host splits every patch's orbit set into work items of up to `chunk`
-// orbits and orders them by cost (exposures x orbits, largest first).  A
-// grid sized to the machine, not to the work, then pulls items from one
-// device counter: each workgroup takes the next item, runs the same per-orbit
-// stack as the single-patch kernel over that patch's exposures, and asks for
-// another until the counter passes the end.  Large and small patches share
-// the CUs, and the tail is made of the cheapest items.  The counter is zeroed
-// by a one-thread kernel so the whole sequence can be captured in a graph.
+// orbits, orders them by cost (exposures x orbits, largest first) and cuts
+// them into wavefront items of at most 64 orbits in that order.  A grid
+// sized to the machine, not to the work, then pulls items from one device
+// counter: each wavefront takes the next item, runs the same per-orbit stack
+// as the single-patch kernel over that patch's exposures (the checkpoint
+// walk without deferral), and asks for another until the counter passes the
+// end.  Large and small patches share the CUs, and the tail is made of the
+// cheapest items.  The counter is zeroed by a one-thread kernel so the whole
+// sequence can be captured in a graph.
 #include "dt_track.hpp"
 
 namespace dtk {
@@ -18,50 +20,46 @@ __global__ void k_reset_counter(unsigned int* counter) { *counter = 0u; }
 __global__ __launch_bounds__(256, 4) void k_stack_persistent(const StackArgs* __restrict__ descs,
                                                              const WorkItem* __restrict__ items, int n_items,
                                                              unsigned int* __restrict__ counter) {
-  __shared__ int s_item;
   __shared__ TrackQueue tq[4];
+  // every wavefront pulls items of at most 64 orbits on its own (no
+  // workgroup barrier); item, descriptor and first orbit are wave-uniform
+  // scalar loads
   while (true) {
-    if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    // uniform across the workgroup: scalar loads of the item and its
-    // descriptor, held in scalar registers
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();  // every lane has read s_item before it is overwritten
+    unsigned int t = 0;
+    if (__lane_id() == 0) t = atomicAdd(counter, 1u);
+    const int it = __builtin_amdgcn_readfirstlane((int)t);
     if (it >= n_items) break;
     const WorkItem w = items[it];
     const StackArgs& A = descs[w.patch];
-    const int64_t end = w.begin + w.count;
+    const int64_t b = w.begin;
     if (A.vobs < __builtin_inf()) {
-      // checkpoint prediction, one wavefront per 64 orbits (as k_stack_track);
-      // b is the wavefront's first orbit
-      const int64_t wofs = (int64_t)__builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
-      for (int64_t b = w.begin + wofs; b < end; b += blockDim.x) {
-        bool in;
-        float snr, flux;
-        int nv;
-        {
-          const int64_t o = b + __lane_id();
-          in = o < end;
-          double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-          if (in) {
-            el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
-          }
-          track_stack_lane<false, false>(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]),
-                                         tq[threadIdx.x >> 6], snr, flux, nv);
-        }
+      // checkpoint prediction, one wavefront per 64 orbits (as k_stack_track)
+      bool in;
+      float snr, flux;
+      int nv;
+      {
+        const int64_t o = b + __lane_id();
+        in = (int)__lane_id() < w.count;
+        double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (in) {
-          // the lane id again, opaque to the compiler (see thread_index_after_walk)
-          int lane = (int)__lane_id();
-          asm volatile("" : "+v"(lane));
-          const int64_t o = b + lane;
-          if (A.snr) A.snr[o] = snr;
-          if (A.flux) A.flux[o] = flux;
-          if (A.nvalid) A.nvalid[o] = nv;
+          el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
         }
+        track_stack_lane<false, false>(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]),
+                                       tq[threadIdx.x >> 6], snr, flux, nv);
+      }
+      if (in) {
+        // the lane id again, opaque to the compiler (see thread_index_after_walk)
+        int lane = (int)__lane_id();
+        asm volatile("" : "+v"(lane));
+        const int64_t o = b + lane;
+        if (A.snr) A.snr[o] = snr;
+        if (A.flux) A.flux[o] = flux;
+        if (A.nvalid) A.nvalid[o] = nv;
       }
       continue;
     }
-    for (int64_t o = w.begin + threadIdx.x; o < end; o += blockDim.x) {
+    if ((int)__lane_id() < w.count) {
+      const int64_t o = b + __lane_id();
       float snr, flux;
       int nv;
       stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);
