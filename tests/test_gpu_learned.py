@@ -226,14 +226,15 @@ def cells():
     return dict(g=g, el=el, exps=exps, D=D, V=V, ctx=c, patch=patch, grid=grid, reps=reps, keep=(Dt, Vt))
 
 
-def _lattice_stamps_oracle(c, reps, da, dm):
+def _lattice_stamps_oracle(c, reps, da, dm, planes=None):
     """The stamp definition on the oracle's walks and planes: per exposure the
     lattice q = (p + u (p_a - p)) + v (p_m - p), nearest pixel, constant-flux
     S/N over the nodes' valid pixels; exposures with a walk behind the plane
     are skipped.  Also returns, per representative, whether any lattice
     coordinate fell within 1e-6 px of a rounding boundary."""
     t0 = c["g"]["t0"]
-    planes = [oracle.planes(d, v, x["fwhm"]) for d, v, x in zip(c["D"], c["V"], c["exps"])]
+    if planes is None:
+        planes = [oracle.planes(d, v, x["fwhm"]) for d, v, x in zip(c["D"], c["V"], c["exps"])]
     u = (np.arange(21) - 10) / 10.0
     U = np.broadcast_to(u[None, :], (21, 21))
     Vv = np.broadcast_to(u[:, None], (21, 21))
@@ -290,6 +291,38 @@ def test_cell_stamps_match_oracle_planes(cells):
         assert ft[r, 1] == pytest.approx(st[r][10, 10], abs=1e-6)
         row, col = divmod(int(np.argmax(st[r])), 21)   # the first node holding the maximum
         assert ft[r, 11] == np.float32((col - 10) / 10.0) and ft[r, 12] == np.float32((row - 10) / 10.0)
+
+
+def test_cell_stamps_many_exposures_match_oracle(cells):
+    """Stamps over more than 256 exposures (the kernel then keeps the gathers
+    of four usable exposures in flight per lane instead of two): the small
+    set's exposures repeated eleven times (same images, epochs and observer),
+    against the oracle's lattice on the same list, on 40 cells."""
+    import torch
+    import paper_2503_08854_amd as dt
+    c = cells
+    cg = c["g"]["cell_grid"]
+    rep = 11
+    exps = c["exps"] * rep
+    assert len(exps) > 256
+    Dt, Vt = c["keep"]
+    patch = dt.Patch(c["ctx"], exps, list(Dt) * rep, list(Vt) * rep)
+    reps_el = c["el"][::cg["cell_size"]][:40]
+    reps = dt.OrbitSet(reps_el, c["g"]["t0"])
+    out = dt.cell_stamps(patch, reps, cg["da"], cg["dm"])
+    torch.cuda.synchronize()
+    st = out["stamps"].cpu().numpy()
+    planes = [oracle.planes(d, v, x["fwhm"]) for d, v, x in zip(c["D"], c["V"], c["exps"])] * rep
+    cd = dict(c, exps=exps)
+    want, band = _lattice_stamps_oracle(cd, reps_el, cg["da"], cg["dm"], planes=planes)
+    err = np.abs(st - want) / np.maximum(1.0, np.abs(want))
+    worst = err.reshape(err.shape[0], -1).max(1)
+    assert np.all(worst[~band] < 1e-4), worst[~band].max()
+    assert (~band).sum() >= 30 and np.abs(want).max() > 1.0
+    # the same cells over the single set: every node's S/N scales by sqrt(11)
+    one = dt.cell_stamps(c["patch"], reps, cg["da"], cg["dm"])["stamps"].cpu().numpy()
+    np.testing.assert_allclose(st[~band], one[~band] * np.sqrt(rep), rtol=1e-4, atol=1e-4)
+    patch.close()
 
 
 def test_cell_stamps_peak_at_a_member_source(cells):
