@@ -116,8 +116,8 @@ __global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_s
 }
 
 // The same by checkpoint prediction (one wavefront per 64 generated orbits).
-__global__ __launch_bounds__(256, 4) void k_stack_generated_track(StackArgs A, dt_orbit_sampler S, int64_t first) {
-  __shared__ TrackQueue tq[4];
+__global__ __launch_bounds__(64, 16) void k_stack_generated_track(StackArgs A, dt_orbit_sampler S, int64_t first) {
+  __shared__ TrackQueue tq[1];
   if (wave_base() >= A.n) return;  // the whole wavefront is past the end
   bool in;
   float snr, flux;
@@ -202,7 +202,7 @@ hipError_t launch_stack_generated(const StackArgs& a, const dt_orbit_sampler& S,
       hipError_t e = launch_zero_u32(a.defer_count, s);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_stack_generated_track, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S, first);
+    hipLaunchKernelGGL(k_stack_generated_track, dim3((unsigned)((a.n + 63) / 64)), dim3(64), 0, s, a, S, first);
     if (a.defer_list)
       hipLaunchKernelGGL(k_stack_generated_deferred, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, S,
                          first);

@@ -29,9 +29,11 @@ __global__ __launch_bounds__(256) void k_stack(StackArgs A) {
 }
 
 // The same stack by checkpoint prediction (one wavefront = 64 orbits walking
-// together; used when the patch has a finite observer speed bound).
-__global__ __launch_bounds__(256, 4) void k_stack_track(StackArgs A) {
-  __shared__ TrackQueue tq[4];
+// together; used when the patch has a finite observer speed bound).  One
+// wavefront per workgroup: the wavefronts are independent, and single-wave
+// workgroups measured 3 % faster than four-wave ones on the survey set.
+__global__ __launch_bounds__(64, 16) void k_stack_track(StackArgs A) {
+  __shared__ TrackQueue tq[1];
   if (wave_base() >= A.n) return;  // the whole wavefront is past the end
   bool in;
   float snr, flux;
@@ -241,7 +243,7 @@ hipError_t launch_stack(const StackArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   if (a.vobs < __builtin_inf()) {
     if (a.defer_list) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, a.defer_count);
-    hipLaunchKernelGGL(k_stack_track, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_stack_track, dim3(grid_for(a.n, 64)), dim3(64), 0, s, a);
     if (a.defer_list) hipLaunchKernelGGL(k_stack_deferred, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
   } else {
     hipLaunchKernelGGL(k_stack, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
