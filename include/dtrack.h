@@ -215,7 +215,7 @@ dt_status dt_topk_noalloc(dt_ctx *ctx, const float *d_snr, int64_t n, int32_t k,
 
 /* Launch shape of the batched stack: orbits per work item for the
  * largest-first ordering (multiple of 256 in [256, 65536]) and persistent
- * workgroups per compute unit ([1, 16]). */
+ * groups of four wavefronts per compute unit ([1, 16]). */
 typedef struct {
   int32_t chunk;
   int32_t wg_per_cu;
@@ -230,8 +230,8 @@ enum {
  * persistent launch (the same per-orbit computation as dt_stack, Sec. 3):
  * every patch's orbits are cut into work items of cfg->chunk orbits, ordered
  * largest first (exposures x orbits), cut again into items of 64 orbits in
- * that order and pulled from a device counter by the wavefronts of a grid of
- * cfg->wg_per_cu workgroups per CU.  Then, if k > 0, the top-k of
+ * that order and pulled from a device counter by 4 cfg->wg_per_cu persistent
+ * wavefronts per CU.  Then, if k > 0, the top-k of
  * every patch (as dt_topk) is written to d_topk_idx / d_topk_val
  * [n_patches * k] and d_topk_count [n_patches] (device).  patches, sets and
  * the output arrays are host arrays of n_patches entries; d_snr / d_flux /

@@ -17,10 +17,10 @@ namespace dtk {
 
 __global__ void k_reset_counter(unsigned int* counter) { *counter = 0u; }
 
-__global__ __launch_bounds__(256, 4) void k_stack_persistent(const StackArgs* __restrict__ descs,
+__global__ __launch_bounds__(64, 4) void k_stack_persistent(const StackArgs* __restrict__ descs,
                                                              const WorkItem* __restrict__ items, int n_items,
                                                              unsigned int* __restrict__ counter) {
-  __shared__ TrackQueue tq[4];
+  __shared__ TrackQueue tq[1];
   // every wavefront pulls items of at most 64 orbits on its own (no
   // workgroup barrier); item, descriptor and first orbit are wave-uniform
   // scalar loads
@@ -74,7 +74,9 @@ hipError_t launch_batched(const StackArgs* d_descs, const WorkItem* d_items, int
                           int n_wg, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, d_counter);
-  hipLaunchKernelGGL(k_stack_persistent, dim3(n_wg), dim3(256), 0, s, d_descs, d_items, n_items, d_counter);
+  // n_wg groups of four wavefronts, launched as single-wavefront workgroups
+  // (each with its own LDS queue; the wavefronts share nothing)
+  hipLaunchKernelGGL(k_stack_persistent, dim3(4 * n_wg), dim3(64), 0, s, d_descs, d_items, n_items, d_counter);
   return hipGetLastError();
 }
 

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_stack_generated(StackArgs A, dt_orbit_s
 }
 
 // The same by checkpoint prediction (one wavefront per 64 generated orbits).
-__global__ __launch_bounds__(64, 16) void k_stack_generated_track(StackArgs A, dt_orbit_sampler S, int64_t first) {
+__global__ __launch_bounds__(64, 4) void k_stack_generated_track(StackArgs A, dt_orbit_sampler S, int64_t first) {
   __shared__ TrackQueue tq[1];
   if (wave_base() >= A.n) return;  // the whole wavefront is past the end
   bool in;

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_stack(StackArgs A) {
 // together; used when the patch has a finite observer speed bound).  One
 // wavefront per workgroup: the wavefronts are independent, and single-wave
 // workgroups measured 3 % faster than four-wave ones on the survey set.
-__global__ __launch_bounds__(64, 16) void k_stack_track(StackArgs A) {
+__global__ __launch_bounds__(64, 4) void k_stack_track(StackArgs A) {
   __shared__ TrackQueue tq[1];
   if (wave_base() >= A.n) return;  // the whole wavefront is past the end
   bool in;
