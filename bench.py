@@ -380,12 +380,12 @@ def counted_work(ctx, launch):
 def roofline_block(kernel, ms, n_orbits, n_exp, valid, flops, stored, traffic):
     """Both rooflines of the dominant launch.  HBM: algorithmic bytes = 8 B per
     valid sample (the psi, phi gather) + 12 B of outputs per orbit + 48 B of
-    elements per stored orbit + 208 B per exposure record.  FP64: the
+    elements per stored orbit + 224 B per exposure record.  FP64: the
     kernel's own flop count (its work counters).  The binding one is HBM when
     the measured traffic (committed counters, same sources) keeps HBM busier
     than the FP64 units are, else the one whose algorithmic fraction is
     nearer its peak."""
-    nbytes = 8.0 * valid + (12.0 + (48.0 if stored else 0.0)) * n_orbits + 208.0 * n_exp
+    nbytes = 8.0 * valid + (12.0 + (48.0 if stored else 0.0)) * n_orbits + 224.0 * n_exp
     hbm = dict(bound="hbm", achieved=nbytes / (ms * 1e-3) / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                algorithmic_bytes=nbytes, traffic=traffic)
     hbm["frac"] = hbm["achieved"] / HBM_PEAK_GBS

@@ -18,6 +18,9 @@ constexpr double C_AU_DAY = 299792458.0 * 86400.0 / 149597870700.0;
 constexpr double OBLIQUITY_ARCSEC = 84381.448;
 constexpr double PI = 3.14159265358979323846;
 
+// Days of epochs between checkpoints of the checkpoint walk (at least this often).
+constexpr double CK_SPAN = 16.0;
+
 // Per-exposure constants, prepared on the device from a dt_exposure.
 // Everything is expressed in the heliocentric ecliptic frame so no rotation
 // is needed per sample: the TAN basis is rotated once per exposure instead.
@@ -39,8 +42,28 @@ struct alignas(16) ExpMeta {
   float fwhm;               // PSF FWHM (px)
   int32_t R;                // stamp half-width ceil(3 sigma)
   float vs;                 // scalar pixel variance when the patch has no variance planes
+  int32_t ck_next;          // first exposure (epoch order) more than CK_SPAN days after this one (n when none)
 };
-static_assert(sizeof(ExpMeta) == 208, "ExpMeta layout");
+static_assert(sizeof(ExpMeta) == 224, "ExpMeta layout");
+
+// Exposure records, planes and elements seen through the global address
+// space.  A pointer read from device memory (a batched launch's per-patch
+// descriptor) is generic to the compiler, and generic (flat) loads count as
+// possibly per-lane: a wave-uniform record read through one would make the
+// whole exposure walk per-lane (vector registers, masked branches).  Through
+// a global pointer a uniform record is read with scalar loads.  Functions
+// that take a generic reference get an explicit cast, which the compiler
+// sees through.
+typedef const __attribute__((address_space(1))) ExpMeta GExpMeta;
+__device__ __forceinline__ GExpMeta* global_meta(const ExpMeta* p) { return (GExpMeta*)p; }
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ T global_load(const T* p, int64_t i) {
+  return *(const T*)&global_ptr(p)[i];
+}
 
 // One tile of the matched-filter pre-pass.
 struct PrepTile {

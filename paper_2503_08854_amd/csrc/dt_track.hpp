@@ -25,7 +25,7 @@
 // per-sample walk.
 //
 // The prediction pays while most samples miss.  A wavefront whose orbits land
-// often (more than TRACK_SWITCH of its lane-exposures queued, once
+// often (more than 1 / TRACK_SWITCH_DEN of its lane-exposures queued, once
 // TRACK_SWITCH_MIN exposures are tested or its queue is full, e.g. distant
 // objects the field follows for months) gives its orbits up when the launch
 // allows it:
@@ -37,14 +37,21 @@
 
 namespace dtk {
 
-constexpr double CK_SPAN = 16.0;      // days: checkpoints at least this often (epoch span)
 constexpr double CK_REACH = 0.3;     // rad: largest Kepler start step taken warm from a checkpoint
 constexpr float PRED_SLACK = 1e-9f;  // AU: rounding of the checkpoint state and of the prediction
 constexpr int TQ_CAP = 128;          // queued samples per wavefront (< 64 held + 64 pushed)
 constexpr int TQ_LIST = 8;           // queued samples per lane between flushes
 constexpr int CK_ANCHOR = 8;         // checkpoints between full sincos re-anchors of sin E, cos E
-constexpr float TRACK_SWITCH = 0.20f; // queued fraction of lane-exposures above which a wavefront defers
-constexpr int TRACK_SWITCH_MIN = 3;   // exposures tested before the fraction is trusted
+constexpr int TRACK_SWITCH_DEN = 5;  // a wavefront defers above 1/5 of its lane-exposures queued
+constexpr int TRACK_SWITCH_MIN = 3;  // exposures tested before the fraction is trusted
+
+// More than 1 / TRACK_SWITCH_DEN of the 64 n_tested lane-exposures queued:
+// for an integer count, q > 64 n / 5 exactly when q > floor(64 n / 5).  Plain
+// 32-bit arithmetic on wave-uniform counts, so scalar instructions only (the
+// walk runs with fewer than 2^25 exposures, so 64 n_tested < 2^31).
+__device__ __forceinline__ bool over_switch(int queued, int n_tested) {
+  return queued > (int)(((unsigned)n_tested << 6) / (unsigned)TRACK_SWITCH_DEN);
+}
 
 // One wavefront's state in LDS: the queue, and each lane's prepared orbit and
 // checkpoint Kepler state (read by whichever lane solves that orbit's queued
@@ -58,7 +65,7 @@ struct TrackQueue {
   unsigned char list[TQ_LIST][64]; // queue slots of each lane, in push order
   double orb[9][64];               // e, n, M0, aP, bQ of each lane's orbit
   double kep[4][64];               // E, sin E, cos E, g at the lane's checkpoint (M = E - e sin E)
-  float bnd[3][64];                // j6, l1, vmax of TrackBound, rounded up (vmax -1: never pruned)
+  float bnd[3][64];                // j6, l1, vmax of TrackBound, rounded up (vmax -1: never pruned; -inf: not live)
 };
 typedef __attribute__((address_space(3))) TrackQueue LdsTrackQueue;
 
@@ -103,7 +110,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   // would be kept generic (flat) by the compiler
   volatile LdsTrackQueue& Q = *(volatile LdsTrackQueue*)(&Qm);
   const int lane = (int)__lane_id();
-  const ExpMeta* __restrict__ meta = A.meta;
+  GExpMeta* __restrict__ meta = global_meta(A.meta);
   P.ps.init();
   P.ph.init();
   P.nv = 0;
@@ -124,11 +131,12 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   const bool bounded = bd.j6 < 1e30 && bd.l1 < 1e30 && bd.vmax < 1e30;
   Q.bnd[0][lane] = bounded ? __double2float_ru(bd.j6) : 0.f;
   Q.bnd[1][lane] = bounded ? __double2float_ru(bd.l1) : 0.f;
-  Q.bnd[2][lane] = bounded ? __double2float_ru(bd.vmax) : -1.f;  // read back at checkpoints only
+  Q.bnd[2][lane] = !live ? -__builtin_inff() : bounded ? __double2float_ru(bd.vmax) : -1.f;  // read at checkpoints
   double j6 = 0.0, l1 = 0.0;  // reloaded after every service step
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, v0 = 0.0, v1 = 0.0, v2 = 0.0, h0 = 0.0, h1 = 0.0, h2 = 0.0;
-  float s0 = 0.f;    // slack (AU, rounded up), or +inf after a checkpoint whose light time did not converge
+  float s0 = 0.f;    // slack (AU, rounded up); +inf: not pruned at this checkpoint; -inf: lane not live
   double tc = 0.0;   // checkpoint epoch
+  int ck_at = 0;     // exposure of the next checkpoint (the last one's ck_next: the first more than CK_SPAN on)
   int n_ck = 0;      // checkpoints so far
   int count = 0;     // queued samples (wave-uniform)
   int len = 0;       // this lane's queued samples
@@ -141,18 +149,21 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
 
   for (; ex <= A.n_exp && !tail; ++ex) {
     const bool last = ex == A.n_exp;
-    const ExpMeta& x = meta[last ? ex - 1 : ex];
+    GExpMeta& x = meta[last ? ex - 1 : ex];
     double D = x.t - tc;
     double p0 = fma(fma(h0, D, v0), D, r0) - x.ox;
     double p1 = fma(fma(h1, D, v1), D, r1) - x.oy;
     double p2 = fma(fma(h2, D, v2), D, r2) - x.oz;
-    const bool ck = !last && (ex == 0 || D > CK_SPAN);
+    // D > CK_SPAN, precomputed per exposure (ck_next: the same subtraction,
+    // non-decreasing along the epochs) and tested here as an integer compare
+    const bool ck = !last && ex >= ck_at;
     const bool fl = count > 0 && (last || ck || full);
     // a wavefront due to serve its queue whose queued fraction is already
-    // above TRACK_SWITCH defers now rather than solve samples the per-sample
-    // walk repeats (nothing more is queued; the loop ends at its next test)
-    tail = may_defer && fl && !last && (float)(queued + count) > TRACK_SWITCH * 64.f * (float)n_tested;
-    if ((fl || ck) && !tail) {
+    // above 1 / TRACK_SWITCH_DEN defers now rather than solve samples the
+    // per-sample walk repeats
+    tail = may_defer && fl && !last && over_switch(queued + count, n_tested);
+    if (tail) break;
+    if (fl || ck) {
       const int nb = fl ? (count + 63) >> 6 : 0;
       float tg_ck = 0.f;  // a Newton start only
       if (ck && ex > 0) {
@@ -183,7 +194,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
           kk.cE = Q.kep[2][L];
           kk.g = Q.kep[3][L];
           kk.M = fma(-oo.e, kk.sE, kk.E);  // the solved equation, to the Newton tolerance
-          const ExpMeta& xm = meta[ent >> 6];
+          GExpMeta& xm = meta[ent >> 6];
           const double dt = xm.t - A.epoch;
           const double b0 = -xm.ox, b1 = -xm.oy, b2 = -xm.oz;
           double tg = (double)(ckj ? tg_ck : Q.tg[i]);
@@ -218,19 +229,21 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
             // three roundings is below 1e-7 relative, and the factor
             // 1.1 * (1 + 1e-6) keeps s0 above 1.1 (PRED_SLACK + vmax dtau)
             const float dtau = fmaf(1.01f, fabsf((float)s.D), 1e-9f);
+            // a lane that is not live gets -inf: its cone test never passes
             const float vmax = Q.bnd[2][lane];
-            s0 = vmax >= 0.f && dtau < 1.f ? 1.1000011f * fmaf(vmax, dtau, PRED_SLACK) : __builtin_inff();
+            s0 = vmax >= 0.f && dtau < 1.f ? 1.1000011f * fmaf(vmax, dtau, PRED_SLACK)
+                                           : vmax < -1.f ? -__builtin_inff() : __builtin_inff();
           } else {
             SampleOut so;
-            project(xm, s, so);
+            project((const ExpMeta&)xm, s, so);
             float2 v = make_float2(0.f, 0.f);
-            if (so.inside) v = A.planes[xm.plane_off + (int64_t)so.iy * xm.W + so.ix];
+            if (so.inside) v = global_load(A.planes, xm.plane_off + (int64_t)so.iy * xm.W + so.ix);
             const bool ok = v.y > 0.f;
             Q.rx[i] = ok ? v.x : 0.f;
             Q.ry[i] = ok ? v.y : 0.f;
             if (REC) {
               so.tau = tg + s.D;
-              rec_sample(*dbg, A.n_exp, rowbase + L, xm, so, v);
+              rec_sample(*dbg, A.n_exp, rowbase + L, (const ExpMeta&)xm, so, v);
             }
           }
         }
@@ -280,9 +293,10 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       // this exposure's record again, by an index the compiler does not
       // match with the first one (ex >> 30 is 0), so the first values need
       // not be kept in registers across the solves
-      const ExpMeta& y = meta[(last ? ex - 1 : ex) + (ex >> 30)];
+      GExpMeta& y = meta[(last ? ex - 1 : ex) + (ex >> 30)];
       if (ck) {
         tc = y.t;
+        ck_at = y.ck_next;
         n_ck++;
         D = 0.0;
       }
@@ -291,13 +305,13 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       p2 = fma(fma(h2, D, v2), D, r2) - y.oz;
     }
     if (last) break;
-    n_tested += tail ? 0 : 1;
+    n_tested++;
     // cone test of the prediction (bitwise logic, no branches)
     const double sc = fma(x.ux, p0, fma(x.uy, p1, x.uz * p2));
     const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
     const double m = fma(j6 * D * D, D, fma(l1, D, (double)s0));
     const double R = fma(x.cone_tan, sc, m);
-    const bool may = live & !tail & (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
+    const bool may = (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
     const uint64_t mask = __builtin_amdgcn_ballot_w64(may);
     if (mask) {
       if (may) {
@@ -314,8 +328,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       // (nothing queued is served; the loop ends at its next test).  A queue
       // that fills before TRACK_SWITCH_MIN exposures decides at once, rather
       // than serving solves the per-sample walk would repeat.
-      tail = may_defer && (n_tested >= TRACK_SWITCH_MIN || full) &&
-             (float)(queued + count) > TRACK_SWITCH * 64.f * (float)n_tested;
+      tail = may_defer && (n_tested >= TRACK_SWITCH_MIN || full) && over_switch(queued + count, n_tested);
     }
   }
   deferred = tail;

@@ -42,7 +42,13 @@ __global__ __launch_bounds__(64, 4) void k_stack_persistent(const StackArgs* __r
         in = (int)__lane_id() < w.count;
         double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (in) {
-          el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+          // the descriptor's pointers are generic to the compiler: read as global
+          el[0] = global_load(A.a, o);
+          el[1] = global_load(A.e, o);
+          el[2] = global_load(A.inc, o);
+          el[3] = global_load(A.node, o);
+          el[4] = global_load(A.peri, o);
+          el[5] = global_load(A.m0, o);
         }
         track_stack_lane<false, false>(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]),
                                        tq[threadIdx.x >> 6], snr, flux, nv);

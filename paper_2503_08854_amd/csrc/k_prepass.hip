@@ -79,6 +79,15 @@ __global__ void k_exposure_prep(const dt_exposure* __restrict__ in, const int64_
   m.fwhm = x.psf_fwhm_px;
   m.R = rad[i];
   m.vs = 0.f;
+  // first later exposure whose epoch exceeds this one by more than CK_SPAN
+  // (the input is in epoch order and t_j - t is non-decreasing in j)
+  int lo = i + 1, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (in[mid].t - x.t > CK_SPAN) hi = mid;
+    else lo = mid + 1;
+  }
+  m.ck_next = lo;
   // Sky cone of the image.  The pixel (x, y) is the direction
   // c + xi e + eta n with (xi, eta) = CD (x - px0, y - py0) in radians; the
   // axis is the centre pixel's direction and the half-angle is the largest

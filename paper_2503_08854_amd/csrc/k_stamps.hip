@@ -297,23 +297,28 @@ __global__ __launch_bounds__(256) void k_stack_cells(StackArgs A, const int64_t*
 __global__ __launch_bounds__(256, 4) void k_stack_cells_track(StackArgs A, const int64_t* __restrict__ cells,
                                                               int64_t n_sel, int cell_size) {
   __shared__ TrackQueue tq[4];
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r - (int64_t)__lane_id() >= n_sel * cell_size) return;  // the whole wavefront is past the end
-  int64_t o = -1;
-  if (r < n_sel * cell_size) {
+  if (wave_base() >= n_sel * cell_size) return;  // the whole wavefront is past the end
+  // member orbit of a row (-1: none), taken again after the walk rather than
+  // kept live through it
+  auto member = [&](int64_t r) -> int64_t {
+    if (r >= n_sel * cell_size) return -1;
     const int64_t c = cells[r / cell_size];
-    if (c >= 0) o = c * cell_size + r % cell_size;
-  }
-  const bool ok = o >= 0 && o < A.n;
-  double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (ok) {
-    el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
-  }
+    const int64_t o = c >= 0 ? c * cell_size + r % cell_size : -1;
+    return o < A.n ? o : -1;
+  };
   float snr, flux;
   int nv;
-  track_stack_lane(A, el, ok && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr, flux,
-                   nv);
-  if (!ok) return;
+  {
+    const int64_t o = member(wave_base() + __lane_id());
+    double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (o >= 0) {
+      el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
+    }
+    track_stack_lane(A, el, o >= 0 && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6], snr,
+                     flux, nv);
+  }
+  const int64_t o = member(thread_index_after_walk());
+  if (o < 0) return;
   if (A.snr) A.snr[o] = snr;
   if (A.flux) A.flux[o] = flux;
   if (A.nvalid) A.nvalid[o] = nv;
