@@ -309,10 +309,13 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
     // cone test of the prediction (bitwise logic, no branches)
     const double sc = fma(x.ux, p0, fma(x.uy, p1, x.uz * p2));
     const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
-    const double m = fma(j6 * D * D, D, fma(l1, D, (double)s0));
+    const double m = fma(fma(j6, D * D, l1), D, (double)s0);
     const double R = fma(x.cone_tan, sc, m);
-    const bool may = (R >= 0.0) & (fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim);
-    const uint64_t mask = __builtin_amdgcn_ballot_w64(may);
+    const bool in_front = R >= 0.0, in_cone = fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim;
+    const bool may = in_front & in_cone;
+    // the mask from one ballot per compare (each is the compare's own lane
+    // mask; a ballot of the combined flag would rebuild it from a vector)
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(in_front) & __builtin_amdgcn_ballot_w64(in_cone);
     if (mask) {
       if (may) {
         const int slot = count + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
