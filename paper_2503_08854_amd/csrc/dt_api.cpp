@@ -72,7 +72,7 @@ dt_status check_exposure(const dt_exposure& x, int i) {
 
 void patch_free(dt_patch* p) {
   dt_ctx* c = p->ctx;
-  ctx_free(c, p->d_meta, sizeof(ExpMeta) * p->n_exp);
+  ctx_free(c, p->d_meta, sizeof(ExpMeta) * (p->n_exp + 1));
   ctx_free(c, p->d_planes, sizeof(float2) * p->plane_elems);
   ctx_free(c, p->d_tiles, sizeof(PrepTile) * p->n_tiles);
   ctx_free(c, p->d_flux, sizeof(void*) * p->n_exp);
@@ -341,7 +341,7 @@ dt_status dt_patch_create(dt_ctx* c, const dt_exposure* exps, int32_t n_exp, con
   auto A = [&](void** ptr, size_t bytes, const char* what) {
     if (st == DT_OK) st = ctx_alloc(c, ptr, bytes, what);
   };
-  A((void**)&p->d_meta, sizeof(ExpMeta) * n_exp, "exposure metadata");
+  A((void**)&p->d_meta, sizeof(ExpMeta) * (n_exp + 1), "exposure metadata");  // + the repeated last record
   A((void**)&p->d_planes, sizeof(float2) * p->plane_elems, "matched-filter planes");
   A((void**)&p->d_tiles, sizeof(PrepTile) * p->n_tiles, "pre-pass tiles");
   A((void**)&p->d_flux, sizeof(void*) * n_exp, "flux pointers");

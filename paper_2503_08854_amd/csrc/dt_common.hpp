@@ -42,8 +42,10 @@ struct alignas(16) ExpMeta {
   float fwhm;               // PSF FWHM (px)
   int32_t R;                // stamp half-width ceil(3 sigma)
   float vs;                 // scalar pixel variance when the patch has no variance planes
-  int32_t ck_next;          // first exposure (epoch order) more than CK_SPAN days after this one (n when none)
+  int32_t ck_next;          // first exposure (epoch order) more than CK_SPAN days after this one (n + 1 when none)
 };
+// A patch holds n + 1 records: the last exposure's record is repeated once
+// (the checkpoint walk's final queue-serving step reads it, uses nothing of it).
 static_assert(sizeof(ExpMeta) == 224, "ExpMeta layout");
 
 // Exposure records, planes and elements seen through the global address

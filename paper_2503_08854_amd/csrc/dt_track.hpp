@@ -141,29 +141,34 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
   int count = 0;     // queued samples (wave-uniform)
   int len = 0;       // this lane's queued samples
   int queued = 0;    // samples queued so far (wave-uniform)
-  bool full = false; // the queue must be served before more samples are pushed
+  int svc_at = 0;    // step of the next service: the next checkpoint, the final step, or the one after the queue filled
   int ex = 0;
   int n_tested = 0;  // exposures tested by prediction (wave-uniform)
   bool tail = false; // give the orbits up for the per-sample walk
   const bool may_defer = DEFER && A.defer_list != nullptr;
 
-  for (; ex <= A.n_exp && !tail; ++ex) {
-    const bool last = ex == A.n_exp;
-    GExpMeta& x = meta[last ? ex - 1 : ex];
+  for (;; ++ex) {
+    // the step after the last exposure only serves the queue; the record
+    // after the last one repeats it, so it is read like any other
+    GExpMeta& x = meta[ex];
     double D = x.t - tc;
     double p0 = fma(fma(h0, D, v0), D, r0) - x.ox;
     double p1 = fma(fma(h1, D, v1), D, r1) - x.oy;
     double p2 = fma(fma(h2, D, v2), D, r2) - x.oz;
-    // D > CK_SPAN, precomputed per exposure (ck_next: the same subtraction,
-    // non-decreasing along the epochs) and tested here as an integer compare
-    const bool ck = !last && ex >= ck_at;
-    const bool fl = count > 0 && (last || ck || full);
-    // a wavefront due to serve its queue whose queued fraction is already
-    // above 1 / TRACK_SWITCH_DEN defers now rather than solve samples the
-    // per-sample walk repeats
-    tail = may_defer && fl && !last && over_switch(queued + count, n_tested);
-    if (tail) break;
-    if (fl || ck) {
+    // one integer compare decides whether this step serves (svc_at <= n_exp,
+    // so the final step always does)
+    if (ex >= svc_at) {
+      const bool last = ex == A.n_exp;
+      // D > CK_SPAN, precomputed per exposure (ck_next: the same subtraction,
+      // non-decreasing along the epochs); "none" is n_exp + 1, so the final
+      // step never takes a checkpoint
+      const bool ck = ex >= ck_at;
+      const bool fl = count > 0;
+      // a wavefront due to serve its queue whose queued fraction is already
+      // above 1 / TRACK_SWITCH_DEN defers now rather than solve samples the
+      // per-sample walk repeats
+      tail = may_defer && fl && !last && over_switch(queued + count, n_tested);
+      if (tail) break;
       const int nb = fl ? (count + 63) >> 6 : 0;
       float tg_ck = 0.f;  // a Newton start only
       if (ck && ex > 0) {
@@ -293,7 +298,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       // this exposure's record again, by an index the compiler does not
       // match with the first one (ex >> 30 is 0), so the first values need
       // not be kept in registers across the solves
-      GExpMeta& y = meta[(last ? ex - 1 : ex) + (ex >> 30)];
+      GExpMeta& y = meta[ex + (ex >> 30)];
       if (ck) {
         tc = y.t;
         ck_at = y.ck_next;
@@ -303,8 +308,9 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       p0 = fma(fma(h0, D, v0), D, r0) - y.ox;
       p1 = fma(fma(h1, D, v1), D, r1) - y.oy;
       p2 = fma(fma(h2, D, v2), D, r2) - y.oz;
+      svc_at = ck_at < A.n_exp ? ck_at : A.n_exp;
+      if (last) break;
     }
-    if (last) break;
     n_tested++;
     // cone test of the prediction (bitwise logic, no branches)
     const double sc = fma(x.ux, p0, fma(x.uy, p1, x.uz * p2));
@@ -326,12 +332,15 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
         len++;
       }
       count += __builtin_popcountll(mask);
-      full = count >= 64 || __builtin_amdgcn_ballot_w64(len >= TQ_LIST) != 0;
+      // a full queue (or a lane's list) is served at the next step
+      const bool full = count >= 64 || __builtin_amdgcn_ballot_w64(len >= TQ_LIST) != 0;
+      if (full) svc_at = ex + 1;
       // most samples may land: leave these orbits to the per-sample walk
-      // (nothing queued is served; the loop ends at its next test).  A queue
-      // that fills before TRACK_SWITCH_MIN exposures decides at once, rather
-      // than serving solves the per-sample walk would repeat.
+      // (nothing queued is served).  A queue that fills before
+      // TRACK_SWITCH_MIN exposures decides at once, rather than serving
+      // solves the per-sample walk would repeat.
       tail = may_defer && (n_tested >= TRACK_SWITCH_MIN || full) && over_switch(queued + count, n_tested);
+      if (tail) break;
     }
   }
   deferred = tail;

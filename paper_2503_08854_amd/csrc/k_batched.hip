@@ -65,10 +65,12 @@ __global__ __launch_bounds__(64, 4) void k_stack_persistent(const StackArgs* __r
       continue;
     }
     if ((int)__lane_id() < w.count) {
-      const int64_t o = b + __lane_id();
       float snr, flux;
       int nv;
-      stack_orbit<false>(A, o, nullptr, 0, snr, flux, nv);
+      stack_orbit<false>(A, b + __lane_id(), nullptr, 0, snr, flux, nv);
+      int lane = (int)__lane_id();  // opaque again, as above
+      asm volatile("" : "+v"(lane));
+      const int64_t o = b + lane;
       if (A.snr) A.snr[o] = snr;
       if (A.flux) A.flux[o] = flux;
       if (A.nvalid) A.nvalid[o] = nv;

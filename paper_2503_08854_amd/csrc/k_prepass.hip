@@ -80,14 +80,15 @@ __global__ void k_exposure_prep(const dt_exposure* __restrict__ in, const int64_
   m.R = rad[i];
   m.vs = 0.f;
   // first later exposure whose epoch exceeds this one by more than CK_SPAN
-  // (the input is in epoch order and t_j - t is non-decreasing in j)
+  // (the input is in epoch order and t_j - t is non-decreasing in j); n + 1
+  // when there is none
   int lo = i + 1, hi = n;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (in[mid].t - x.t > CK_SPAN) hi = mid;
     else lo = mid + 1;
   }
-  m.ck_next = lo;
+  m.ck_next = lo < n ? lo : n + 1;
   // Sky cone of the image.  The pixel (x, y) is the direction
   // c + xi e + eta n with (xi, eta) = CD (x - px0, y - py0) in radians; the
   // axis is the centre pixel's direction and the half-angle is the largest
@@ -123,6 +124,7 @@ __global__ void k_exposure_prep(const dt_exposure* __restrict__ in, const int64_
   m.cone_tan = cone ? tmax * 1.0001 + 1e-12 : 0.0;
   m.cone_lim = cone ? 0.0 : __builtin_inf();
   out[i] = m;
+  if (i == n - 1) out[n] = m;  // the repeated last record
 }
 
 hipError_t launch_exposure_prep(const dt_exposure* d_in, const int64_t* d_plane_off, const int32_t* d_src,
