@@ -25,17 +25,19 @@ constexpr double CK_SPAN = 16.0;
 // Everything is expressed in the heliocentric ecliptic frame so no rotation
 // is needed per sample: the TAN basis is rotated once per exposure instead.
 struct alignas(16) ExpMeta {
+  // The fields every step of the checkpoint walk reads come first (72 bytes,
+  // two scalar loads issued together).
   double t;                 // epoch (days)
   double ox, oy, oz;        // observer (AU, ecliptic)
+  // Sky cone holding every direction that projects into the pixel rectangle
+  // widened by one pixel: unit axis u, tangent of the half-angle, and the
+  // limit of the cone test (0; +inf with u = 0 when no cone is used).
+  double ux, uy, uz, cone_tan, cone_lim;
   double cx, cy, cz;        // tangent-point direction (ecliptic)
   double a0x, a0y, a0z;     // row 0 of (180/pi) CD^-1 [east; north] (px per unit, ecliptic)
   double a1x, a1y, a1z;     // row 1
   double px0, py0;          // CRPIX - 1
   double gap, inv_gap;      // epoch step from the previous exposure (epoch order) and its reciprocal
-  // Sky cone holding every direction that projects into the pixel rectangle
-  // widened by one pixel: unit axis u, tangent of the half-angle, and the
-  // limit of the cone test (0; +inf with u = 0 when no cone is used).
-  double ux, uy, uz, cone_tan, cone_lim;
   int64_t plane_off;        // offset of this exposure's plane (in float2 units)
   int32_t W, H;             // image size
   int32_t src;              // caller's index of this exposure
@@ -48,15 +50,17 @@ struct alignas(16) ExpMeta {
 // (the checkpoint walk's final queue-serving step reads it, uses nothing of it).
 static_assert(sizeof(ExpMeta) == 224, "ExpMeta layout");
 
-// Exposure records, planes and elements seen through the global address
-// space.  A pointer read from device memory (a batched launch's per-patch
+// Exposure records, planes and elements seen through a named address space.
+// A pointer read from device memory (a batched launch's per-patch
 // descriptor) is generic to the compiler, and generic (flat) loads count as
 // possibly per-lane: a wave-uniform record read through one would make the
-// whole exposure walk per-lane (vector registers, masked branches).  Through
-// a global pointer a uniform record is read with scalar loads.  Functions
-// that take a generic reference get an explicit cast, which the compiler
-// sees through.
-typedef const __attribute__((address_space(1))) ExpMeta GExpMeta;
+// whole exposure walk per-lane (vector registers, masked branches).  The
+// records are read through the constant address space (device memory no
+// kernel writes while it runs), so a uniform record is read with scalar
+// loads even where the kernel also stores to global memory; planes and
+// elements through the global one.  Functions that take a generic
+// reference get an explicit cast, which the compiler sees through.
+typedef const __attribute__((address_space(4))) ExpMeta GExpMeta;
 __device__ __forceinline__ GExpMeta* global_meta(const ExpMeta* p) { return (GExpMeta*)p; }
 template <typename T>
 __device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {

@@ -151,6 +151,9 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
     // the step after the last exposure only serves the queue; the record
     // after the last one repeats it, so it is read like any other
     GExpMeta& x = meta[ex];
+    // the cone of this exposure read now, with the epoch and observer, so
+    // both loads are in flight together
+    double ux = x.ux, uy = x.uy, uz = x.uz, ctan = x.cone_tan, clim = x.cone_lim;
     double D = x.t - tc;
     double p0 = fma(fma(h0, D, v0), D, r0) - x.ox;
     double p1 = fma(fma(h1, D, v1), D, r1) - x.oy;
@@ -308,16 +311,21 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       p0 = fma(fma(h0, D, v0), D, r0) - y.ox;
       p1 = fma(fma(h1, D, v1), D, r1) - y.oy;
       p2 = fma(fma(h2, D, v2), D, r2) - y.oz;
+      ux = y.ux;  // the cone again too: nothing of the first read stays live across the solves
+      uy = y.uy;
+      uz = y.uz;
+      ctan = y.cone_tan;
+      clim = y.cone_lim;
       svc_at = ck_at < A.n_exp ? ck_at : A.n_exp;
       if (last) break;
     }
     n_tested++;
     // cone test of the prediction (bitwise logic, no branches)
-    const double sc = fma(x.ux, p0, fma(x.uy, p1, x.uz * p2));
+    const double sc = fma(ux, p0, fma(uy, p1, uz * p2));
     const double d2 = fma(p0, p0, fma(p1, p1, p2 * p2));
     const double m = fma(fma(j6, D * D, l1), D, (double)s0);
-    const double R = fma(x.cone_tan, sc, m);
-    const bool in_front = R >= 0.0, in_cone = fma(-R, R, fma(-sc, sc, d2)) <= x.cone_lim;
+    const double R = fma(ctan, sc, m);
+    const bool in_front = R >= 0.0, in_cone = fma(-R, R, fma(-sc, sc, d2)) <= clim;
     const bool may = in_front & in_cone;
     // the mask from one ballot per compare (each is the compare's own lane
     // mask; a ballot of the combined flag would rebuild it from a vector)
