@@ -45,7 +45,7 @@ FLOPS_PER_SOLVE = 125
 # 24, rounding 2, light time 5).
 FLOPS_PER_TAIL_SAMPLE = 82
 FLOPS_PER_TAIL_FULL = 60
-CK_SPAN_DAYS = 16.0  # the kernel's checkpoint span (epoch days)
+CK_SPAN_DAYS = 12.0  # the kernel's checkpoint span (epoch days, CK_SPAN in the library)
 # HBM bytes of one full-size stack launch per workload from the committed
 # FETCH_SIZE / WRITE_SIZE passes; reported only while the kernel's sources
 # are the ones those counters were taken on.

@@ -30,7 +30,8 @@
  *   propagate, project, gather, stack (orbits in HBM): dt_stack
  *   the same with orbits drawn on the device:           dt_stack_generated
  *   many patches in one persistent launch:               dt_stack_batched
- *   threshold + top-k selection:                         dt_topk (dt_topk_noalloc)
+ *   threshold + top-k selection:                         dt_topk (dt_topk_noalloc,
+ *                                                        dt_topk_unordered)
  *   learned cell proposer: dt_cell_stamps, dt_scorer_*, dt_cell_members_near,
  *                          dt_stack_ids, dt_stack_cells
  *   checking only: dt_debug_samples, dt_debug_stack_samples, dt_record_gathers,
@@ -193,6 +194,15 @@ dt_status dt_orbits_validate(dt_ctx *ctx, const dt_orbits *orbits, int64_t *n_ba
  * written (<= k).  1 <= k <= 4096, n < 2^32. */
 dt_status dt_topk(dt_ctx *ctx, const float *d_snr, int64_t n, int32_t k, float threshold,
                   int64_t *d_idx, float *d_val, int32_t *d_count);
+
+/* The same selection as dt_topk (same arguments, rules and errors; the same
+ * set of orbits and count), for callers that only need the set, such as the
+ * learned proposer's choice of cells: for n <= 16384 the first *d_count
+ * entries are in an order fixed by the input but not sorted (the final sort
+ * is skipped); larger inputs come out sorted as by dt_topk.  Entries past
+ * the count are idx -1, val NaN. */
+dt_status dt_topk_unordered(dt_ctx *ctx, const float *d_snr, int64_t n, int32_t k, float threshold,
+                            int64_t *d_idx, float *d_val, int32_t *d_count);
 
 /* Allocation-free top-k, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -80,6 +80,7 @@ def lib():
         "dt_orbits_validate": ([_P, C.POINTER(DtOrbits), C.POINTER(C.c_int64)], C.c_int),
         "dt_topk": ([_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P, _P], C.c_int),
         "dt_topk_noalloc": ([_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P, _P], C.c_int),
+        "dt_topk_unordered": ([_P, _P, C.c_int64, C.c_int32, C.c_float, _P, _P, _P], C.c_int),
         "dt_debug_samples": ([_P, C.POINTER(DtOrbits), _P, C.c_int64, _P, _P, _P, _P, _P, _P, _P, _P], C.c_int),
         "dt_stack_batched": ([_P, C.POINTER(_P), C.POINTER(DtOrbits), C.c_int32, C.POINTER(_P), C.POINTER(_P),
                               C.POINTER(_P), C.c_int32, C.c_float, _P, _P, _P, C.POINTER(DtBatchConfig),
@@ -333,15 +334,16 @@ def validate_orbits(ctx: Context, orbits: OrbitSet) -> int:
     return n_bad.value
 
 
-def topk(ctx: Context, snr, k: int, threshold: float = float("-inf")):
-    """(idx int64[k], val float32[k], count int32[1]) device tensors."""
+def topk(ctx: Context, snr, k: int, threshold: float = float("-inf"), ordered: bool = True):
+    """(idx int64[k], val float32[k], count int32[1]) device tensors;
+    ordered=False calls dt_topk_unordered (the same set, not sorted)."""
     import torch
     dev = snr.device
     idx = torch.empty(k, dtype=torch.int64, device=dev)
     val = torch.empty(k, dtype=torch.float32, device=dev)
     cnt = torch.empty(1, dtype=torch.int32, device=dev)
-    _check(lib().dt_topk(ctx.handle, _ptr(snr), int(snr.numel()), int(k), float(threshold), _ptr(idx), _ptr(val),
-                         _ptr(cnt)))
+    fn = lib().dt_topk if ordered else lib().dt_topk_unordered
+    _check(fn(ctx.handle, _ptr(snr), int(snr.numel()), int(k), float(threshold), _ptr(idx), _ptr(val), _ptr(cnt)))
     return idx, val, cnt
 
 

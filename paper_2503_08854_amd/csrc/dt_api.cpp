@@ -536,8 +536,8 @@ dt_status dt_orbits_validate(dt_ctx* c, const dt_orbits* o, int64_t* n_bad) {
   return DT_OK;
 }
 
-dt_status dt_topk(dt_ctx* c, const float* d_snr, int64_t n, int32_t k, float threshold, int64_t* d_idx,
-                  float* d_val, int32_t* d_count) {
+static dt_status topk_call(dt_ctx* c, const float* d_snr, int64_t n, int32_t k, float threshold, int64_t* d_idx,
+                           float* d_val, int32_t* d_count, bool ordered) {
   if (!c || !c->alive) return fail(DT_E_ARG, "invalid context");
   if (n < 0 || (n > 0 && !d_snr)) return fail(DT_E_ARG, "bad S/N array");
   if (n >= ((int64_t)1 << 32)) return fail(DT_E_ARG, "n must be < 2^32");
@@ -555,9 +555,19 @@ dt_status dt_topk(dt_ctx* c, const float* d_snr, int64_t n, int32_t k, float thr
     if (st != DT_OK) return st;
     c->topk_bytes = need;
   }
-  hipError_t e = launch_topk(d_snr, n, k, threshold, d_idx, d_val, d_count, c->topk_scratch, c->stream);
+  hipError_t e = launch_topk(d_snr, n, k, threshold, d_idx, d_val, d_count, c->topk_scratch, c->stream, ordered);
   if (e != hipSuccess) return hip_fail(e, "top-k launch");
   return DT_OK;
+}
+
+dt_status dt_topk(dt_ctx* c, const float* d_snr, int64_t n, int32_t k, float threshold, int64_t* d_idx,
+                  float* d_val, int32_t* d_count) {
+  return topk_call(c, d_snr, n, k, threshold, d_idx, d_val, d_count, true);
+}
+
+dt_status dt_topk_unordered(dt_ctx* c, const float* d_snr, int64_t n, int32_t k, float threshold, int64_t* d_idx,
+                            float* d_val, int32_t* d_count) {
+  return topk_call(c, d_snr, n, k, threshold, d_idx, d_val, d_count, false);
 }
 
 dt_status dt_debug_samples(dt_patch* p, const dt_orbits* o, const int64_t* d_ids, int64_t m, double* d_px,

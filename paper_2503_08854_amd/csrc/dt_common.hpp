@@ -19,7 +19,7 @@ constexpr double OBLIQUITY_ARCSEC = 84381.448;
 constexpr double PI = 3.14159265358979323846;
 
 // Days of epochs between checkpoints of the checkpoint walk (at least this often).
-constexpr double CK_SPAN = 16.0;
+constexpr double CK_SPAN = 12.0;
 
 // Per-exposure constants, prepared on the device from a dt_exposure.
 // Everything is expressed in the heliocentric ecliptic frame so no rotation
@@ -287,7 +287,9 @@ hipError_t launch_stack_generated_walk(const StackArgs& a, const dt_orbit_sample
 hipError_t topk_noalloc_setup(int device);
 // Top-k scratch requirement (bytes) for n inputs and k outputs.
 size_t topk_scratch_bytes(int64_t n, int32_t k);
+// ordered false: inputs of at most 16384 keys skip the final sort (the
+// selection is the same; larger inputs come out sorted either way).
 hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,
-                       int32_t* d_count, void* d_scratch, hipStream_t s);
+                       int32_t* d_count, void* d_scratch, hipStream_t s, bool ordered = true);
 
 }  // namespace dtk

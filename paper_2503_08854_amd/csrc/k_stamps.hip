@@ -455,6 +455,8 @@ __global__ __launch_bounds__(64 * IDS_SPLIT) void k_stack_ids_split(StackArgs A,
                                                                     const int64_t* __restrict__ count) {
   __shared__ float part[IDS_SPLIT][4][64];  // [wavefront][ps.s, ps.c, ph.s, ph.c][lane]
   __shared__ int part_nv[IDS_SPLIT][64];
+  // the long-list kernels run after this one: it zeroes their deferral counter
+  if (A.defer_count && blockIdx.x == 0 && threadIdx.x == 0) *A.defer_count = 0u;
   const int64_t m = *count;
   const int j = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
@@ -539,10 +541,7 @@ hipError_t launch_stack_ids(const StackArgs& a, const int64_t* d_ids, const int6
                      d_count);
   if (m_max > STACK_IDS_SHORT) {  // the count may be long: the kernels for long lists too
     if (a.vobs < __builtin_inf()) {
-      if (a.defer_list) {
-        hipError_t e = launch_zero_u32(a.defer_count, s);
-        if (e != hipSuccess) return e;
-      }
+      // (the deferral counter was zeroed by k_stack_ids_split)
       hipLaunchKernelGGL(k_stack_ids_track, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
       if (a.defer_list) hipLaunchKernelGGL(k_stack_ids_deferred, dim3(grid), dim3(256), 0, s, a, d_ids, d_count);
     } else {

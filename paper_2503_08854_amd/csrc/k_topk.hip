@@ -228,8 +228,10 @@ constexpr int SMALL_PER = TOPK_SMALL_MAX / SMALL_THREADS;
 
 // The best k (<= TOPK_T / 2) of the n <= TOPK_SMALL_MAX keys load(i) (0 =
 // empty), emitted as indices, values and their count; one workgroup of
-// SMALL_THREADS threads.
-template <typename Load>
+// SMALL_THREADS threads.  SORTED false skips the sort: the selected keys are
+// written in thread order (thread t's keys t, t + 1024, ... after those of
+// threads below t), which depends on the input alone.
+template <bool SORTED = true, typename Load>
 __device__ __forceinline__ void select_small(int n, int k, Load load, int64_t* __restrict__ idx,
                                              float* __restrict__ val, int32_t* __restrict__ count) {
   __shared__ uint64_t s[TOPK_T / 2];
@@ -329,6 +331,37 @@ __device__ __forceinline__ void select_small(int n, int k, Load load, int64_t* _
     }
     kth = prefix;
   }
+  if (!SORTED) {
+    // exclusive prefix of the per-thread counts of selected keys: within
+    // each wavefront by shuffles, across wavefronts through LDS
+    int mine = 0;
+#pragma unroll
+    for (int q = 0; q < SMALL_PER; ++q) mine += (key[q] != 0 && key[q] >= kth) ? 1 : 0;
+    int inc = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    if (lane == 63) hist[0][wv] = inc;
+    __syncthreads();
+    int pos = inc - mine;
+    for (int w = 0; w < wv; ++w) pos += hist[0][w];
+#pragma unroll
+    for (int q = 0; q < SMALL_PER; ++q) {
+      if (key[q] != 0 && key[q] >= kth) {
+        idx[pos] = key_idx(key[q]);
+        val[pos] = key_val(key[q]);
+        pos++;
+      }
+    }
+    for (int j = m + t; j < k; j += SMALL_THREADS) {
+      idx[j] = -1;
+      val[j] = __builtin_nanf("");
+    }
+    if (t == 0) *count = m;
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < SMALL_PER; ++q)
     if (key[q] != 0 && key[q] >= kth) s[atomicAdd(&sh_sel, 1)] = key[q];
@@ -355,10 +388,11 @@ __device__ __forceinline__ void select_small(int n, int k, Load load, int64_t* _
   if (t == 0) *count = m;
 }
 
+template <bool SORTED>
 __global__ __launch_bounds__(SMALL_THREADS) void k_topk_small(const float* __restrict__ snr, int n, float thr, int k,
                                                               int64_t* __restrict__ idx, float* __restrict__ val,
                                                               int32_t* __restrict__ count) {
-  select_small(n, k, [&](int i) -> uint64_t {
+  select_small<SORTED>(n, k, [&](int i) -> uint64_t {
     const float f = snr[i];
     return f >= thr ? make_key(f, (uint64_t)i) : 0ull;  // false for NaN
   }, idx, val, count);
@@ -440,11 +474,15 @@ static void launch_round(int T, unsigned tiles, const float* snr, const uint64_t
 }
 
 hipError_t launch_topk(const float* d_snr, int64_t n, int32_t k, float thr, int64_t* d_idx, float* d_val,
-                       int32_t* d_count, void* d_scratch, hipStream_t s) {
+                       int32_t* d_count, void* d_scratch, hipStream_t s, bool ordered) {
   if (k < 1 || k > TOPK_T / 2) return hipErrorInvalidValue;
   if (n <= TOPK_SMALL_MAX) {
-    hipLaunchKernelGGL(k_topk_small, dim3(1), dim3(SMALL_THREADS), 0, s, d_snr, (int)(n > 0 ? n : 0), thr, k, d_idx,
-                       d_val, d_count);
+    if (ordered)
+      hipLaunchKernelGGL(k_topk_small<true>, dim3(1), dim3(SMALL_THREADS), 0, s, d_snr, (int)(n > 0 ? n : 0), thr, k,
+                         d_idx, d_val, d_count);
+    else
+      hipLaunchKernelGGL(k_topk_small<false>, dim3(1), dim3(SMALL_THREADS), 0, s, d_snr, (int)(n > 0 ? n : 0), thr,
+                         k, d_idx, d_val, d_count);
     return hipGetLastError();
   }
   const int T1 = first_tile(n, k);

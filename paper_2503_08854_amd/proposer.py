@@ -39,8 +39,9 @@ def score_cells(scorer, stamps_bf16, feats_bf16):
 
 
 def select_cells(ctx, scores, budget: int):
-    """Indices of the `budget` highest scores (ties to the lower index)."""
-    idx, val, cnt = B.topk(ctx, scores, int(budget))
+    """Indices of the `budget` highest scores (ties to the lower index), as a
+    set: the stacks that follow do not depend on their order."""
+    idx, val, cnt = B.topk(ctx, scores, int(budget), ordered=False)
     return idx
 
 

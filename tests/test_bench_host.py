@@ -1,6 +1,6 @@
 """Host-side logic of the benchmark (no GPU): the checkpoint count that the
 roofline's algorithmic flop count uses follows the stack kernel's rule (the
-first exposure in epoch order, then every exposure more than 16 days after
+first exposure in epoch order, then every exposure more than 12 days after
 the last checkpoint), and the one-GPU guard."""
 import subprocess
 import sys
@@ -9,9 +9,9 @@ import bench
 
 
 def test_checkpoint_count_follows_the_kernel_rule():
-    # epoch order 0, 1, 5, 16, 17, 33.1, 40: checkpoints at 0, 17 (> 16 after 0) and 33.1 (> 16 after 17);
-    # 16 is exactly 16 days after 0 and is not one
-    exps = [dict(t=t) for t in (5.0, 0.0, 1.0, 16.0, 17.0, 33.1, 40.0)]
+    # epoch order 0, 1, 5, 12, 13, 25.1, 30: checkpoints at 0, 13 (> 12 after 0) and 25.1 (> 12 after 13);
+    # 12 is exactly 12 days after 0 and is not one
+    exps = [dict(t=t) for t in (5.0, 0.0, 1.0, 12.0, 13.0, 25.1, 30.0)]
     assert bench.checkpoints(exps) == 3
     assert bench.checkpoints([dict(t=3.0)]) == 1
     assert bench.checkpoints([dict(t=float(d)) for d in range(0, 200, 10)]) == 10

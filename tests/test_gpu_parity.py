@@ -105,7 +105,7 @@ def test_stack_walk_samples_match_oracle(name):
 def test_work_counters(name):
     """The stack's work counters: a wavefront either walks every exposure by
     prediction or gives up (deferred) and its live orbits are then walked per
-    sample over every exposure; checkpoints follow the 16-day rule when no
+    sample over every exposure; checkpoints follow the 12-day rule when no
     wavefront defers; every valid sample was solved (queued or on the per-sample
     walk's full path); counting changes no result."""
     import torch
@@ -262,6 +262,16 @@ def test_topk_edge_cases():
         np.testing.assert_array_equal(idx.cpu().numpy()[:c], want)
         np.testing.assert_array_equal(val.cpu().numpy()[:c], v[want])
         assert np.all(idx.cpu().numpy()[c:] == -1)
+        # the unordered call: the same count and set, each index with its value
+        iu, vu, cu = dt.topk(ctx, t, k, thr, ordered=False)
+        torch.cuda.synchronize()
+        assert int(cu.cpu()[0]) == c
+        iu, vu = iu.cpu().numpy(), vu.cpu().numpy()
+        np.testing.assert_array_equal(np.sort(iu[:c]), np.sort(want))
+        np.testing.assert_array_equal(vu[:c], v[iu[:c]])
+        assert np.all(iu[c:] == -1) and np.all(np.isnan(vu[c:]))
+        if n > 16384:
+            np.testing.assert_array_equal(iu[:c], want)  # larger inputs come out sorted
 
 
 def test_argument_errors():
