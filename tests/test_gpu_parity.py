@@ -752,3 +752,44 @@ def test_stack_distant_objects_fp16():
     assert ok.all(), f"{(~ok).sum()} orbits outside tolerance"
     want = oracle.topk(g["snr"].astype(np.float64), 50)
     np.testing.assert_array_equal(g["topk_idx"][:g["topk_cnt"]], want)
+
+
+def test_checkpoint_epochs_at_the_span_boundary(tiny):
+    """The checkpoint schedule taken per exposure in the exposure preparation
+    follows the walk's rule exactly at the boundary: epochs on a 1/64-day
+    grid (exact differences), one exposure exactly 12 days after the first
+    checkpoint and one exactly 12 days after the second (neither is a
+    checkpoint: the span must be exceeded), and the stack against the oracle
+    on these exposures."""
+    import paper_2503_08854_amd as dt
+    import bench
+    w = tiny
+    order = np.argsort([x["t"] for x in w.exps])
+    t_rel = np.array([w.exps[i]["t"] for i in order]) - w.exps[order[0]]["t"]
+    new = np.round(t_rel * 64.0) / 64.0
+    new[9] = 12.0                    # was 12.96: exactly the span after the first checkpoint (0)
+    new[16] = new[10] + 12.0         # was 24.27: exactly the span after the checkpoint at new[10]
+    assert np.all(np.diff(new) > 0) and new[10] > 12.0 and new[17] > new[16]
+    base = float(np.floor(w.exps[order[0]]["t"]))
+    exps = [dict(x) for x in w.exps]
+    for rank, i in enumerate(order):
+        exps[i]["t"] = base + float(new[rank])
+    assert bench.checkpoints(exps) == 3      # at new[0], new[10] and new[17]
+    w2 = synth.Workload(name="span_boundary", exps=exps, t0=w.t0, elements=w.elements, D=w.D, V=w.V)
+    g = gpu_run(w2)
+    ctx, patch, orb, _, _ = g["_keep"]
+    ctx.count_work(True)
+    snr, flux, nv = dt.stack(patch, orb)
+    wk = ctx.work()
+    ctx.count_work(False)
+    np.testing.assert_array_equal(nv.cpu().numpy(), g["nv"])
+    # every wavefront that walks to the end takes exactly the three checkpoints
+    # (live lanes only are counted; a deferring wavefront stops early)
+    sw = wk["switched_waves"]
+    assert 3 * (orb.n - 64 * sw) <= wk["checkpoint_solves"] <= 3 * orb.n
+    if sw == 0:
+        assert wk["checkpoint_solves"] == 3 * orb.n
+    snr_o, _, nv_o = oracle.stack(w2.elements, w2.t0, exps, w2.D, w2.V)
+    np.testing.assert_array_equal(g["nv"], nv_o)
+    ok = snr_close(g["snr"], snr_o)
+    assert ok.all(), f"{(~ok).sum()} orbits outside tolerance"
