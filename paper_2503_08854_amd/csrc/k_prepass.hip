@@ -145,15 +145,19 @@ hipError_t launch_exposure_prep(const dt_exposure* d_in, const int64_t* d_plane_
 // per column that is filtered along y to give one output row.  R is a
 // template parameter so the window lives in registers.
 // ----------------------------------------------------------------------------
+// The image pointers come from a device array, so they are generic to the
+// compiler; reading through global pointers keeps these loads off the LDS
+// counter (a generic load is counted with the LDS operations, so the waits
+// for a row's LDS reads would also wait for rows still in flight).
 template <typename T>
 __device__ __forceinline__ float load_px(const void* p, int64_t k);
 template <>
 __device__ __forceinline__ float load_px<float>(const void* p, int64_t k) {
-  return __builtin_nontemporal_load(static_cast<const float*>(p) + k);
+  return __builtin_nontemporal_load(global_ptr(static_cast<const float*>(p)) + k);
 }
 template <>
 __device__ __forceinline__ float load_px<_Float16>(const void* p, int64_t k) {
-  return (float)__builtin_nontemporal_load(static_cast<const _Float16*>(p) + k);
+  return (float)__builtin_nontemporal_load(global_ptr(static_cast<const _Float16*>(p)) + k);
 }
 
 __device__ __forceinline__ float2 weight_pair(float d, float v) {
