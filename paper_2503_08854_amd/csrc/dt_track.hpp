@@ -101,8 +101,11 @@ __device__ __forceinline__ void track_bound(double a, double e, const Orbit& o, 
 //
 // REC (debug kernels only): every sample the walk solves exactly is written
 // to row rowbase + lane of dbg (the owner's row for queued samples).  DEFER
-// false compiles the deferral out (launches that never defer).
-template <bool REC = false, bool DEFER = true>
+// false compiles the deferral out (launches that never defer).  TCV keeps the
+// checkpoint epoch in a vector register, so that D = t - tc is one
+// instruction per exposure rather than a copy and a subtraction (~1 % on the
+// stacks that fit it without spilling; the cell and id-list kernels do not).
+template <bool REC = false, bool DEFER = true, bool TCV = false>
 __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, const TrackBound& bd, bool live,
                                            TrackQueue& Qm, StackPart& P, bool& deferred,
                                            const DebugArgs* dbg = nullptr, int64_t rowbase = 0) {
@@ -304,6 +307,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
       GExpMeta& y = meta[ex + (ex >> 30)];
       if (ck) {
         tc = y.t;
+        if (TCV) asm volatile("" : "+v"(tc));
         ck_at = y.ck_next;
         n_ck++;
         D = 0.0;
@@ -368,7 +372,7 @@ __device__ __forceinline__ void track_walk(const StackArgs& A, const Orbit& o, c
 // per-sample stack (NaN, NaN, -1 for an orbit that is not live), or nothing
 // when the wavefront deferred its orbits (returns true).  All 64 lanes of the
 // wavefront call it together; Q is the wavefront's LDS queue.
-template <bool REC = false, bool DEFER = true>
+template <bool REC = false, bool DEFER = true, bool TCV = false>
 __device__ __forceinline__ bool track_stack_lane(const StackArgs& A, const double el[6], bool live, TrackQueue& Q,
                                                  float& snr, float& flux, int& nv, const DebugArgs* dbg = nullptr,
                                                  int64_t rowbase = 0) {
@@ -383,7 +387,7 @@ __device__ __forceinline__ bool track_stack_lane(const StackArgs& A, const doubl
   track_bound(a, e, ob, A.vobs, bd);
   StackPart P;
   bool deferred = false;
-  track_walk<REC, DEFER>(A, ob, bd, live, Q, P, deferred, dbg, rowbase);
+  track_walk<REC, DEFER, TCV>(A, ob, bd, live, Q, P, deferred, dbg, rowbase);
   snr = flux = __builtin_nanf("");
   nv = -1;
   if (deferred) return true;

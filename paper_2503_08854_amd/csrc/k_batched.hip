@@ -50,7 +50,7 @@ __global__ __launch_bounds__(64, 4) void k_stack_persistent(const StackArgs* __r
           el[4] = global_load(A.peri, o);
           el[5] = global_load(A.m0, o);
         }
-        track_stack_lane<false, false>(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]),
+        track_stack_lane<false, false, true>(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]),
                                        tq[threadIdx.x >> 6], snr, flux, nv);
       }
       if (in) {

@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64, 4) void k_stack_generated_track(StackArgs A, dt
     double el[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const bool live = in && gen_orbit(S, (uint64_t)(first + i), el) &&
                       orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]);
-    if (track_stack_lane(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv)) {
+    if (track_stack_lane<false, true, true>(A, el, live, tq[threadIdx.x >> 6], snr, flux, nv)) {
       defer_wave(A, wave_base());
       return;
     }

@@ -45,8 +45,8 @@ __global__ __launch_bounds__(64, 4) void k_stack_track(StackArgs A) {
     if (in) {
       el[0] = A.a[o]; el[1] = A.e[o]; el[2] = A.inc[o]; el[3] = A.node[o]; el[4] = A.peri[o]; el[5] = A.m0[o];
     }
-    if (track_stack_lane(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]), tq[threadIdx.x >> 6],
-                         snr, flux, nv)) {
+    if (track_stack_lane<false, true, true>(A, el, in && orbit_ok(el[0], el[1], el[2], el[3], el[4], el[5]),
+                                           tq[threadIdx.x >> 6], snr, flux, nv)) {
       defer_wave(A, wave_base());
       return;
     }
